@@ -1,0 +1,113 @@
+"""Bloch stiffness, mass and preconditioner operators in Fourier space (oracle).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Vectors are complex128 arrays of shape (..., 3, N0, N1, N2) holding the DFT
+coefficients U^ of the periodic displacement; any leading axes are a batch.
+
+Operators (Sec. 3.2):
+  K(k) U^ = (xi_j + k_j) F{ C_ijkl(x) F^-1[(xi_l + k_l) U^_k] }      eq. hatA
+  M U^    = F{ rho(x) F^-1[U^] }                                      eq. hatM
+  M^-1 Y^ = F{ rho(x)^-1 F^-1[Y^] }                                   eq. def_invM
+  P(xi)   = C0_ijkl (xi_j + k_j)(xi_l + k_l),  P^ Y^ = P^-1 Y^        eqs. matrixP, precond
+with C0 the volume-averaged stiffness.  The operator K is written here with
+the minor symmetry of C (Sec. 2.2) so that only the symmetric part of the
+shifted gradient enters: in Voigt form with engineering shear the strain is
+e = [q1 U1, q2 U2, q3 U3, q3 U2 + q2 U3, q3 U1 + q1 U3, q2 U1 + q1 U2] and
+the divergence is out_i = sum_j q_j s_ij.  The factors i of the gradient and of
+the divergence cancel, which makes K Hermitian positive semidefinite.
+
+Pins (tests/test_oracle_*.py): homogeneous Christoffel spectra, a single
+plane-wave probe against numpy's FFT of C(x), Hermitian PSD, exactly three
+rigid zero modes at k = 0, unitary equivalence of K(k + G) and K(k), the exact
+inverse mass, and P^ = K^-1 for a homogeneous medium.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2106_12487_amd.inputs import RVE, c21_to_voigt, voigt_to_tensor
+
+from .fourier import fft3, ifft3, shifted_wavevector
+
+
+class Operators:
+    """Fourier-space operators of one RVE at one Bloch wave vector k (SI units)."""
+
+    def __init__(self, rve: RVE, k):
+        self.rve = rve
+        self.n = tuple(rve.n)
+        self.L = tuple(rve.L)
+        self.k = np.asarray(k, dtype=np.float64)
+        C6 = np.stack([c21_to_voigt(c) for c in rve.C21])          # (G, 6, 6)
+        g = rve.grain_map.astype(np.int64)
+        self.C_field = C6[g]                                        # (N0, N1, N2, 6, 6)
+        self.rho_field = rve.rho[g]                                 # (N0, N1, N2)
+        self.C0 = self.C_field.reshape(-1, 6, 6).mean(axis=0)       # volume average
+        self.rho_bar = float(self.rho_field.mean())
+        q = shifted_wavevector(self.n, self.L, self.k)
+        self.q1 = q[0][:, None, None]
+        self.q2 = q[1][None, :, None]
+        self.q3 = q[2][None, None, :]
+        # per-voxel shifted wavevector (N0, N1, N2, 3)
+        self.qvec = np.stack(np.broadcast_arrays(self.q1, self.q2, self.q3), axis=-1)
+        self.null_mask = np.all(self.qvec == 0.0, axis=-1)          # xi + k = 0
+
+    # -- K -----------------------------------------------------------------
+    def strain(self, U: np.ndarray) -> np.ndarray:
+        q1, q2, q3 = self.q1, self.q2, self.q3
+        U1, U2, U3 = U[..., 0, :, :, :], U[..., 1, :, :, :], U[..., 2, :, :, :]
+        return np.stack([q1 * U1, q2 * U2, q3 * U3,
+                         q3 * U2 + q2 * U3, q3 * U1 + q1 * U3, q2 * U1 + q1 * U2], axis=-4)
+
+    def divergence(self, S: np.ndarray) -> np.ndarray:
+        q1, q2, q3 = self.q1, self.q2, self.q3
+        s11, s22, s33, s23, s13, s12 = (S[..., i, :, :, :] for i in range(6))
+        return np.stack([q1 * s11 + q2 * s12 + q3 * s13,
+                         q1 * s12 + q2 * s22 + q3 * s23,
+                         q1 * s13 + q2 * s23 + q3 * s33], axis=-4)
+
+    def apply_K(self, U: np.ndarray) -> np.ndarray:
+        """K(k) U^ (eq. hatA)."""
+        e = ifft3(self.strain(U))                                   # real-space strain
+        s = np.einsum("xyzab,...bxyz->...axyz", self.C_field, e, optimize=True)
+        return self.divergence(fft3(s))
+
+    # -- M, M^-1 ---------------------------------------------------------------
+    def apply_M(self, U: np.ndarray) -> np.ndarray:
+        """M U^ (eq. hatM)."""
+        return fft3(self.rho_field * ifft3(U))
+
+    def apply_Minv(self, U: np.ndarray) -> np.ndarray:
+        """M^-1 U^ (eq. def_invM)."""
+        return fft3(ifft3(U) / self.rho_field)
+
+    # -- preconditioner ----------------------------------------------------------
+    def acoustic_tensor(self, C6: np.ndarray) -> np.ndarray:
+        """P_ik = C_ijkl q_j q_l per Fourier voxel for a uniform stiffness C6 (eq. matrixP)."""
+        T = voigt_to_tensor(C6)
+        return np.einsum("ijkl,xyzj,xyzl->xyzik", T, self.qvec, self.qvec, optimize=True)
+
+    def precond(self, R: np.ndarray) -> np.ndarray:
+        """P^ R^ = P(C0, xi + k)^-1 R^ per Fourier voxel, zero where xi + k = 0 (eq. precond)."""
+        if not hasattr(self, "_Pinv"):
+            P = self.acoustic_tensor(self.C0)
+            P[self.null_mask] = np.eye(3)
+            Pinv = np.linalg.inv(P)
+            Pinv[self.null_mask] = 0.0
+            self._Pinv = Pinv
+        return np.einsum("xyzik,...kxyz->...ixyz", self._Pinv, R, optimize=True)
+
+    # -- dense assembly (Sec. 3.3: the dense-matrix argument; used on tiny grids) --
+    def dense(self, which: str = "K") -> np.ndarray:
+        n0, n1, n2 = self.n
+        D = 3 * n0 * n1 * n2
+        E = np.eye(D, dtype=np.complex128).reshape(D, 3, n0, n1, n2)
+        f = {"K": self.apply_K, "M": self.apply_M}[which]
+        cols = np.concatenate([f(E[s:s + 512]) for s in range(0, D, 512)], axis=0)
+        return cols.reshape(D, D).T                                 # column j = op(e_j)
+
+
+def inner(a: np.ndarray, b: np.ndarray) -> complex:
+    """Euclidean inner product a^H b over all DFT coefficients."""
+    return complex(np.vdot(a.ravel(), b.ravel()))
