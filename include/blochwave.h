@@ -1,0 +1,175 @@
+/*
+ * blochwave.h -- C ABI of the MI355X (gfx950) implementation of the FFT-based
+ * Bloch-wave method of Segurado & Lebensohn ("An FFT-based approach for Bloch
+ * wave analysis: application to polycrystals").
+ *
+ * Problem (Sec. 3.2, eqs. hatA, hatM, eigen_fourier_3D): for a voxelized
+ * periodic cell with stiffness C(x) and density rho(x), find the lowest
+ * eigenpairs of  K(k) U^ = omega^2 M U^  at each Bloch wave vector k, with
+ *   K(k) U^ = (xi_j + k_j) F{ C_ijkl(x) F^-1[(xi_l + k_l) U^_k] },
+ *   M U^    = F{ rho(x) F^-1[U^] }.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units      SI throughout (Pa, kg/m^3, m, rad/m, rad/s).
+ * Grid       n[0] x n[1] x n[2] voxels, C order (n[2] fastest), cell edges L[3].
+ * Vectors    Fourier coefficients of the periodic displacement, layout
+ *            [nvec][3][n0][n1][n2] of interleaved complex numbers: double2 when
+ *            the cell was created with BW_FP64, float2 with BW_MIXED.  The
+ *            forward DFT is unnormalized, U^(m) = sum_x U(x) exp(-2 pi i j.m/n);
+ *            storage index j holds the frequency label m = j (mod n) taken from
+ *            the window of Sec. 3.1 eq. "frequencies" (Nyquist label -n/2),
+ *            shifted by whole reciprocal vectors so that the reduced wave number
+ *            k_a L_a / 2 pi - shift lies in (-1/2, 1/2].  For k in the first
+ *            Brillouin zone this is exactly the paper's window.
+ * Stiffness  per grain, 21 entries of the 6x6 Voigt matrix (engineering shear
+ *            strain [e11, e22, e33, 2e23, 2e13, 2e12]), upper triangle,
+ *            row-major, in the sample frame.
+ * Memory     pointers named *_host are host memory; all vector arguments are
+ *            device memory owned by the caller.  The library owns only what
+ *            bw_create_rve allocates (freed by bw_destroy_rve) plus cached
+ *            workspaces attached to the cell.  It never frees caller memory.
+ * Streams    `stream` is a hipStream_t (NULL = the default stream).  Operator
+ *            calls are asynchronous on it; calls returning host results
+ *            synchronize it before returning.
+ * Errors     0 = success; < 0 = error, outputs undefined (BW_EINVAL bad
+ *            argument, BW_ENOMEM allocation failed, BW_EHIP a HIP runtime
+ *            error, BW_EUNSUPPORTED grid size without a compiled FFT);
+ *            > 0 = warning with valid outputs (BW_ENOTCONV an iteration hit its
+ *            limit, results carry their error bounds).  bw_last_error() returns a
+ *            thread-local message for the last non-zero status.
+ * Threads    a cell handle is not thread-safe; different handles may be used
+ *            concurrently on different streams.
+ */
+#ifndef BLOCHWAVE_H
+#define BLOCHWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BW_OK 0
+#define BW_ENOTCONV 1
+#define BW_EINVAL (-1)
+#define BW_ENOMEM (-2)
+#define BW_EHIP (-3)
+#define BW_EUNSUPPORTED (-4)
+
+/* working precision of a cell */
+#define BW_FP64 0   /* FFTs, contraction and vectors in double              */
+#define BW_MIXED 1  /* FFTs, contraction and PCG vectors in float; FP64
+                       reductions, Rayleigh-Ritz and eigen-residuals        */
+
+/* eigen-solver */
+#define BW_SUBSPACE 0 /* Sec. 3.3, Algorithm "subspace" (Bathe), block PCG   */
+#define BW_LANCZOS 1  /* Sec. 3.3, shift-invert restarted Lanczos           */
+
+typedef struct bw_rve bw_rve;
+
+/* Options of bw_lowest_modes.  Zero-initialized fields take the defaults shown. */
+typedef struct bw_eig_opts {
+  int32_t method;      /* BW_SUBSPACE (default) or BW_LANCZOS                    */
+  int32_t block;       /* subspace block q; 0 -> min(2 nmodes, nmodes + 8)       */
+  int32_t ncv;         /* Lanczos basis size; 0 -> max(2 nmodes + 1, 20)         */
+  int32_t maxit_outer; /* outer iterations / restarts per k; 0 -> 200            */
+  int32_t maxit_lin;   /* PCG iterations per solve; 0 -> 20000                   */
+  int32_t warm_start;  /* subspace: start k from the previous k's Ritz block     */
+  double tol_eig;      /* eigen tolerance TOL_eig; 0 -> 1e-10                    */
+  double tol_lin;      /* PCG relative tolerance TOL_lin; 0 -> 1e-10 (FP64),
+                          1e-6 (MIXED inner solves)                              */
+} bw_eig_opts;
+
+/* Statistics of the last solver call (all optional outputs). */
+typedef struct bw_stats {
+  int64_t pcg_iterations;   /* sum over right-hand sides of PCG iterations      */
+  int64_t block_iterations; /* batched PCG sweeps (each sweep = one K apply of
+                               the whole block)                                 */
+  int64_t outer_iterations; /* subspace iterations / Lanczos restarts            */
+  int64_t k_applies;        /* single-vector K applies, all precisions          */
+  int64_t m_applies;        /* single-vector M applies                          */
+  double seconds;           /* wall time of the call                            */
+} bw_stats;
+
+/* Create a cell (Sec. 3.2; Algorithm "Full algorithm" step (a)).
+ *   out            receives the handle
+ *   n[3], L[3]     grid and cell edges (n[i] >= 1, L[i] > 0)
+ *   grain_map_host n0*n1*n2 uint16 grain index per voxel (C order)
+ *   n_grains       number of grains G (1 .. 65535)
+ *   C21_host       G x 21 Voigt stiffness per grain (see Conventions); each
+ *                  6x6 matrix must be symmetric positive definite
+ *   rho_host       G densities (> 0)
+ *   precision      BW_FP64 or BW_MIXED
+ * The volume-averaged stiffness C0 used by the preconditioner (Sec. 3.3 eq.
+ * precond) and the mean density are computed here.  Returns BW_EINVAL on bad
+ * input, BW_EUNSUPPORTED if a grid size has no compiled FFT length. */
+int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3],
+                  const uint16_t* grain_map_host, int32_t n_grains,
+                  const double* C21_host, const double* rho_host, int32_t precision,
+                  void* stream);
+
+/* Release the cell and every workspace the library allocated for it. */
+void bw_destroy_rve(bw_rve* rve);
+
+/* Query grid / precision / volume averages of a cell.  Any output may be NULL. */
+int bw_rve_info(const bw_rve* rve, int32_t n[3], int32_t* precision, double C0_21[21],
+                double* rho_bar);
+
+/* y = K(k) u for nvec vectors (Sec. 3.2 eq. hatA).  k_host: 3 doubles (rad/m).
+ * u and y: device [nvec][3][n0][n1][n2] complex in the cell's precision; they
+ * must not alias. */
+int bw_apply_K(bw_rve* rve, const double k_host[3], const void* u, void* y, int32_t nvec,
+               void* stream);
+
+/* y = M u (Sec. 3.2 eq. hatM).  Same layout rules as bw_apply_K. */
+int bw_apply_M(bw_rve* rve, const void* u, void* y, int32_t nvec, void* stream);
+
+/* y = P^ u, the homogeneous-reference preconditioner P(C0, xi + k)^-1 applied
+ * per Fourier voxel (Sec. 3.3 eqs. matrixP, precond); zero where xi + k = 0. */
+int bw_apply_P(bw_rve* rve, const double k_host[3], const void* u, void* y, int32_t nvec,
+               void* stream);
+
+/* Solve K(k) x = b for nrhs right-hand sides by preconditioned CG
+ * (Sec. 3.3, Algorithm "InvA"), stopping when the true residual satisfies
+ * ||K x - b|| <= rtol ||b|| (Euclidean norm of the DFT coefficients).
+ *   b, x       device [nrhs][3][n0][n1][n2]; x holds the initial guess on entry
+ *              and the solution on exit; b is not modified
+ *   maxit      iteration limit per right-hand side (<= 0: 20000)
+ *   iters_host optional int32[nrhs]: iterations used
+ *   relres_host optional double[nrhs]: final true relative residual, computed
+ *              in the working precision with FP64 accumulation
+ * When xi + k = 0 for some voxel (k a reciprocal lattice vector) K is singular;
+ * the component of b on that voxel must be zero (BW_EINVAL otherwise) and the
+ * solution is returned with that component zero.  Returns BW_ENOTCONV if some
+ * right-hand side hit maxit.  Synchronizes `stream`. */
+int bw_pcg_solve(bw_rve* rve, const double k_host[3], const void* b, void* x, int32_t nrhs,
+                 double rtol, int32_t maxit, int32_t* iters_host, double* relres_host,
+                 void* stream);
+
+/* Lowest nmodes eigenpairs of K(k) U = omega^2 M U at nk wave vectors
+ * (Algorithm "Full algorithm"; eigen-solver per opts->method).
+ *   k_list_host  nk x 3 doubles (rad/m), processed in order (warm starts follow it)
+ *   omega_host   nk x nmodes doubles, ascending per k (rad/s)
+ *   err_host     optional nk x nmodes: a-posteriori bound on |omega - omega*| /
+ *                omega* from the FP64 eigen-residual (Kato-Temple when the gap
+ *                to the next Ritz value allows it, else the residual bound)
+ *   modes        optional device nk x nmodes x [3][n0][n1][n2] complex in the
+ *                cell's precision, M-normalized (U^H M U = 1)
+ *   stats_host   optional solver statistics
+ * At k = 0 (mod reciprocal lattice) the three rigid translations are returned
+ * as omega = 0 with constant M-normalized modes and the rest is solved on their
+ * M-orthogonal complement.  Synchronizes `stream`. */
+int bw_lowest_modes(bw_rve* rve, const double* k_list_host, int32_t nk, int32_t nmodes,
+                    const bw_eig_opts* opts, double* omega_host, double* err_host,
+                    void* modes, bw_stats* stats_host, void* stream);
+
+/* Thread-local message describing the last non-zero status. */
+const char* bw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLOCHWAVE_H */

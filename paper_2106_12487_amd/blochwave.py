@@ -1,0 +1,209 @@
+"""Thin ctypes binding of libblochwave.so (the C ABI in include/blochwave.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Device vectors are torch tensors (complex128 for BW_FP64 cells,
+complex64 for BW_MIXED cells) of shape (nvec, 3, n0, n1, n2), contiguous, on
+the current HIP device; the current torch stream is used unless one is given.
+The library must be built (``python -m paper_2106_12487_amd.build_lib``);
+loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libblochwave.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "blochwave.h")
+
+BW_OK, BW_ENOTCONV = 0, 1
+BW_EINVAL, BW_ENOMEM, BW_EHIP, BW_EUNSUPPORTED = -1, -2, -3, -4
+BW_FP64, BW_MIXED = 0, 1
+BW_SUBSPACE, BW_LANCZOS = 0, 1
+
+
+class BlochwaveError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"blochwave error {code}: {msg}")
+        self.code = code
+
+
+class bw_eig_opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("block", ctypes.c_int32), ("ncv", ctypes.c_int32),
+                ("maxit_outer", ctypes.c_int32), ("maxit_lin", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("tol_eig", ctypes.c_double),
+                ("tol_lin", ctypes.c_double)]
+
+
+class bw_stats(ctypes.Structure):
+    _fields_ = [("pcg_iterations", ctypes.c_int64), ("block_iterations", ctypes.c_int64),
+                ("outer_iterations", ctypes.c_int64), ("k_applies", ctypes.c_int64),
+                ("m_applies", ctypes.c_int64), ("seconds", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_D = ctypes.c_double
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int32)
+
+_SIGS = {
+    "bw_create_rve": (_I, [ctypes.POINTER(_P), _IP, _DP, ctypes.POINTER(ctypes.c_uint16), _I, _DP, _DP, _I, _P]),
+    "bw_destroy_rve": (None, [_P]),
+    "bw_rve_info": (_I, [_P, _IP, _IP, _DP, _DP]),
+    "bw_apply_K": (_I, [_P, _DP, _P, _P, _I, _P]),
+    "bw_apply_M": (_I, [_P, _P, _P, _I, _P]),
+    "bw_apply_P": (_I, [_P, _DP, _P, _P, _I, _P]),
+    "bw_pcg_solve": (_I, [_P, _DP, _P, _P, _I, _D, _I, _IP, _DP, _P]),
+    "bw_lowest_modes": (_I, [_P, _DP, _I, _I, ctypes.POINTER(bw_eig_opts), _DP, _DP, _P,
+                             ctypes.POINTER(bw_stats), _P]),
+    "bw_last_error": (ctypes.c_char_p, []),
+}
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/blochwave.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\*]+\s+)+\**(bw_\w+)\s*\(", txt, flags=re.M)))
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2106_12487_amd.build_lib`")
+        # torch ships its own HIP runtime under the same soname; load it first so
+        # that the library and torch share one runtime (device memory, streams).
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def bw_last_error() -> str:
+    return lib().bw_last_error().decode()
+
+
+def _check(code: int) -> int:
+    if code < 0:
+        raise BlochwaveError(code, bw_last_error())
+    return code
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    if not t.is_contiguous():
+        raise ValueError("device tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _darr(a) -> ctypes.Array:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_DP)
+
+
+class Rve:
+    """Owning wrapper of a bw_rve handle."""
+
+    def __init__(self, n, L, grain_map, C21, rho, precision: int = BW_FP64, stream=None):
+        n_arr = (ctypes.c_int32 * 3)(*[int(v) for v in n])
+        L_arr, L_p = _darr(L)
+        g = np.ascontiguousarray(grain_map, dtype=np.uint16).reshape(-1)
+        C_arr, C_p = _darr(np.asarray(C21).reshape(-1, 21))
+        r_arr, r_p = _darr(np.asarray(rho).reshape(-1))
+        h = ctypes.c_void_p()
+        _check(lib().bw_create_rve(ctypes.byref(h), n_arr, L_p, g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                   int(C_arr.shape[0]), C_p, r_p, int(precision),
+                                   _stream(stream) if stream is not None else None))
+        self.handle = h
+        self.n = tuple(int(v) for v in n)
+        self.precision = int(precision)
+
+    @classmethod
+    def from_inputs(cls, rve, precision: int = BW_FP64):
+        return cls(rve.n, rve.L, rve.grain_map, rve.C21, rve.rho, precision)
+
+    @property
+    def complex_dtype(self):
+        import torch
+        return torch.complex128 if self.precision == BW_FP64 else torch.complex64
+
+    def info(self) -> dict:
+        n = (ctypes.c_int32 * 3)()
+        prec = ctypes.c_int32()
+        c0 = (ctypes.c_double * 21)()
+        rb = ctypes.c_double()
+        _check(lib().bw_rve_info(self.handle, n, ctypes.byref(prec), c0, ctypes.byref(rb)))
+        return dict(n=tuple(n), precision=prec.value, C0=np.array(c0[:]), rho_bar=rb.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bw_destroy_rve(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bw_apply_K(rve: Rve, k, u, y, stream=None) -> None:
+    k_arr, k_p = _darr(k)
+    _check(lib().bw_apply_K(rve.handle, k_p, _dptr(u), _dptr(y), int(u.shape[0]), _stream(stream)))
+
+
+def bw_apply_M(rve: Rve, u, y, stream=None) -> None:
+    _check(lib().bw_apply_M(rve.handle, _dptr(u), _dptr(y), int(u.shape[0]), _stream(stream)))
+
+
+def bw_apply_P(rve: Rve, k, u, y, stream=None) -> None:
+    k_arr, k_p = _darr(k)
+    _check(lib().bw_apply_P(rve.handle, k_p, _dptr(u), _dptr(y), int(u.shape[0]), _stream(stream)))
+
+
+def bw_pcg_solve(rve: Rve, k, b, x, rtol: float, maxit: int = 0, stream=None):
+    """Solve K(k) x = b in place of x; returns (status, iterations, true relative residuals)."""
+    nrhs = int(b.shape[0])
+    k_arr, k_p = _darr(k)
+    it = np.zeros(nrhs, dtype=np.int32)
+    rr = np.zeros(nrhs)
+    code = _check(lib().bw_pcg_solve(rve.handle, k_p, _dptr(b), _dptr(x), nrhs, float(rtol), int(maxit),
+                                     it.ctypes.data_as(_IP), rr.ctypes.data_as(_DP), _stream(stream)))
+    return code, it, rr
+
+
+def bw_lowest_modes(rve: Rve, k_list, nmodes: int, method: int = BW_SUBSPACE, block: int = 0, ncv: int = 0,
+                    tol_eig: float = 0.0, tol_lin: float = 0.0, maxit_outer: int = 0, maxit_lin: int = 0,
+                    warm_start: bool = True, modes=None, want_err: bool = True, stream=None):
+    """omega (nk x nmodes, rad/s), error bounds, status and statistics."""
+    k_arr, k_p = _darr(np.asarray(k_list).reshape(-1, 3))
+    nk = int(k_arr.shape[0])
+    om = np.zeros((nk, nmodes))
+    er = np.zeros((nk, nmodes))
+    opts = bw_eig_opts(method, block, ncv, maxit_outer, maxit_lin, int(bool(warm_start)), tol_eig, tol_lin)
+    st = bw_stats()
+    code = _check(lib().bw_lowest_modes(rve.handle, k_p, nk, int(nmodes), ctypes.byref(opts),
+                                        om.ctypes.data_as(_DP), er.ctypes.data_as(_DP) if want_err else None,
+                                        _dptr(modes) if modes is not None else None, ctypes.byref(st),
+                                        _stream(stream)))
+    return om, (er if want_err else None), code, st.as_dict()

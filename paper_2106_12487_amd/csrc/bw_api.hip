@@ -1,0 +1,486 @@
+// C-ABI entry points: cell creation, operator applies and the batched PCG
+// solver (Sec. 3.3, Algorithm "InvA").
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "bw_ops_impl.h"
+
+namespace bw {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------------------
+// discrete frequencies (Sec. 3.1 eq. "frequencies", Sec. 3.2)
+// ---------------------------------------------------------------------------
+// Label stored at DFT index j: the paper's window shifted by whole reciprocal
+// vectors so that the reduced wave number lies in (-1/2, 1/2].
+static int window_lo(int N, double kappa) {
+  const int paper_lo = -(N / 2);
+  const int g = (int)std::ceil(kappa - 0.5 - 1e-9);
+  return paper_lo - g;
+}
+
+QTable make_qtable(const bw_rve* r, const double* k_host, int nk) {
+  QTable t;
+  const int n[3] = {r->g.n0, r->g.n1, r->g.n2};
+  const int per = n[0] + n[1] + n[2];
+  t.nvec = nk;
+  t.host.resize((size_t)nk * per);
+  t.null_index.assign(nk, -1);
+  for (int v = 0; v < nk; ++v) {
+    int zero_at[3] = {-1, -1, -1};
+    double* dst = t.host.data() + (size_t)v * per;
+    for (int a = 0; a < 3; ++a) {
+      const double k = k_host[3 * v + a];
+      const double kappa = k * r->L[a] / (2.0 * M_PI);
+      const int lo = window_lo(n[a], kappa);
+      for (int j = 0; j < n[a]; ++j) {
+        int mm = (j - lo) % n[a];
+        if (mm < 0) mm += n[a];
+        const int m = lo + mm;
+        const double q = 2.0 * M_PI * m / r->L[a] + k;  // SI, as xi + k
+        *dst++ = q * r->ell;
+        if (q == 0.0) zero_at[a] = j;
+      }
+    }
+    if (zero_at[0] >= 0 && zero_at[1] >= 0 && zero_at[2] >= 0)
+      t.null_index[v] = (zero_at[0] * n[1] + zero_at[1]) * n[2] + zero_at[2];
+  }
+  return t;
+}
+
+// Upload a q table to `buf` through a pinned staging area.
+const double* upload_qtable(bw_rve* r, const QTable& t, DevBuf& buf, hipStream_t s) {
+  const size_t bytes = t.host.size() * sizeof(double);
+  double* d = (double*)buf.get(bytes);
+  BW_HIP(hipMemcpyAsync(d, t.host.data(), bytes, hipMemcpyHostToDevice, s));
+  BW_HIP(hipStreamSynchronize(s));
+  return d;
+}
+
+// Cached q table for a single k repeated nvec times (operator applies).
+static const double* qtab_for(bw_rve* r, const double* k, int nvec, hipStream_t s) {
+  if (r->qcache_nvec == nvec && std::memcmp(r->qcache_k, k, sizeof(r->qcache_k)) == 0 && r->ws_q.p)
+    return (const double*)r->ws_q.p;
+  std::vector<double> ks((size_t)nvec * 3);
+  for (int v = 0; v < nvec; ++v)
+    for (int a = 0; a < 3; ++a) ks[3 * v + a] = k[a];
+  QTable t = make_qtable(r, ks.data(), nvec);
+  const double* d = upload_qtable(r, t, r->ws_q, s);
+  std::memcpy(r->qcache_k, k, sizeof(r->qcache_k));
+  r->qcache_nvec = nvec;
+  return d;
+}
+
+double K_scale(const bw_rve* r) { return r->Cref / (r->ell * r->ell); }
+double M_scale(const bw_rve* r) { return r->rho_bar; }
+
+// ---------------------------------------------------------------------------
+// batched PCG on the scaled operator K' (Sec. 3.3, Algorithm "InvA")
+// ---------------------------------------------------------------------------
+template <typename T>
+PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<T>* b, cplx<T>* x, int nvec,
+                  double tol, int maxit, bool x0_zero, hipStream_t s) {
+  const Geom& g = r->g;
+  const size_t n3 = (size_t)g.nvox * 3;
+  PcgResult res;
+  res.iters.assign(nvec, 0);
+  res.relres.assign(nvec, 0.0);
+  Workspace<T>& w = ws<T>(r);
+  cplx<T>* rv = w.vec(0, (size_t)nvec * n3);
+  cplx<T>* p = w.vec(1, (size_t)nvec * n3);
+  cplx<T>* Ap = w.vec(2, (size_t)nvec * n3);
+  cplx<T>* W = w.work((size_t)nvec * 6 * g.nvox);
+  PcgDev pd = pcg_dev(r, nvec);
+
+  launch_residual<T>(r, d_qtab, b, x0_zero ? nullptr : x, rv, Ap, W, nvec, pd.rr, pd.rz /* ||b||^2 */, pd.partial,
+                     pd.counter, pd.max_blocks, s);
+  std::vector<double> rr(nvec), bb(nvec), thr(nvec);
+  BW_HIP(hipMemcpyAsync(rr.data(), pd.rr, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
+  BW_HIP(hipMemcpyAsync(bb.data(), pd.rz, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
+  BW_HIP(hipStreamSynchronize(s));
+  std::vector<int> act(nvec), it0(nvec, 0);
+  for (int v = 0; v < nvec; ++v) {
+    thr[v] = tol * tol * bb[v];
+    act[v] = rr[v] > thr[v] ? 1 : 0;
+  }
+  BW_HIP(hipMemcpyAsync(pd.bb, thr.data(), nvec * sizeof(double), hipMemcpyHostToDevice, s));
+  BW_HIP(hipMemcpyAsync(pd.active, act.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
+  BW_HIP(hipMemcpyAsync(pd.mask, act.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
+  BW_HIP(hipMemcpyAsync(pd.iters, it0.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
+  launch_pcg_restart<T>(r, d_qtab, rv, nvec, pd, pd.mask, s);
+  BW_HIP(hipStreamSynchronize(s));
+
+  const int chunk = g.nvox >= (1 << 18) ? 4 : 8;
+  std::vector<int> its(nvec);
+  int restarts = 0;
+  for (;;) {
+    bool any = false;
+    for (int v = 0; v < nvec; ++v) any |= act[v] != 0;
+    if (any) {
+      for (int c = 0; c < chunk; ++c) {
+        launch_pcg_apply<T>(r, d_qtab, rv, p, Ap, W, nvec, pd, s);
+        launch_pcg_update<T>(r, d_qtab, x, rv, p, Ap, nvec, pd, s);
+        res.block_iters += 1;
+      }
+      BW_HIP(hipMemcpyAsync(act.data(), pd.active, nvec * sizeof(int), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipMemcpyAsync(its.data(), pd.iters, nvec * sizeof(int), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipStreamSynchronize(s));
+      bool cap = false;
+      for (int v = 0; v < nvec; ++v)
+        if (act[v] && its[v] >= maxit) {
+          act[v] = 0;
+          cap = true;
+        }
+      if (cap) BW_HIP(hipMemcpyAsync(pd.active, act.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
+      any = false;
+      for (int v = 0; v < nvec; ++v) any |= act[v] != 0;
+      if (any) continue;
+    }
+    // every vector stopped: check the true residual
+    launch_residual<T>(r, d_qtab, b, x, rv, Ap, W, nvec, pd.rr, nullptr, pd.partial, pd.counter, pd.max_blocks, s);
+    BW_HIP(hipMemcpyAsync(rr.data(), pd.rr, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
+    BW_HIP(hipMemcpyAsync(its.data(), pd.iters, nvec * sizeof(int), hipMemcpyDeviceToHost, s));
+    BW_HIP(hipStreamSynchronize(s));
+    bool again = false;
+    std::vector<int> mask(nvec, 0);
+    for (int v = 0; v < nvec; ++v) {
+      if (rr[v] > thr[v] && its[v] < maxit && restarts < 8) {
+        mask[v] = 1;
+        again = true;
+      }
+    }
+    if (!again) break;
+    ++restarts;
+    act = mask;
+    BW_HIP(hipMemcpyAsync(pd.active, act.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
+    BW_HIP(hipMemcpyAsync(pd.mask, mask.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
+    launch_pcg_restart<T>(r, d_qtab, rv, nvec, pd, pd.mask, s);
+  }
+  res.converged = true;
+  for (int v = 0; v < nvec; ++v) {
+    res.iters[v] = its[v];
+    res.relres[v] = bb[v] > 0 ? std::sqrt(rr[v] / bb[v]) : 0.0;
+    if (rr[v] > thr[v]) res.converged = false;
+    res.total_iters += its[v];
+  }
+  return res;
+}
+
+template PcgResult pcg_run<double>(bw_rve*, const double*, const QTable&, const cplx<double>*, cplx<double>*, int,
+                                   double, int, bool, hipStream_t);
+template PcgResult pcg_run<float>(bw_rve*, const double*, const QTable&, const cplx<float>*, cplx<float>*, int,
+                                  double, int, bool, hipStream_t);
+
+PcgDev pcg_dev(bw_rve* r, int nvec) {
+  const Geom& g = r->g;
+  // blocks per vector of every reducing kernel: row tiles (<= n0 n1) and the
+  // pointwise kernels
+  int maxb = std::max(pw_blocks(g.nvox * 3), (int)std::max<long>(1, (long)g.n0 * g.n1));
+  const size_t dbl = (size_t)nvec * 8;
+  const size_t part = (size_t)nvec * maxb * 2;
+  const size_t ints = (size_t)nvec * 4;
+  char* base = (char*)r->ws_pcg.get((dbl + part) * sizeof(double) + ints * sizeof(int) + 256);
+  PcgDev pd{};
+  double* d = (double*)base;
+  pd.rz = d;
+  pd.pAp = d + nvec;
+  pd.alpha = d + 2 * nvec;
+  pd.beta = d + 3 * nvec;
+  pd.rr = d + 4 * nvec;
+  pd.bb = d + 5 * nvec;
+  pd.partial = d + dbl;
+  int* ip = (int*)(d + dbl + part);
+  pd.active = ip;
+  pd.iters = ip + nvec;
+  pd.mask = ip + 2 * nvec;
+  pd.counter = (unsigned*)(ip + 3 * nvec);
+  pd.max_blocks = maxb;
+  if (r->pcg_counters_nvec < nvec) {
+    BW_HIP(hipMemset(pd.counter, 0, nvec * sizeof(unsigned)));
+    r->pcg_counters_nvec = nvec;
+  }
+  return pd;
+}
+
+// ---------------------------------------------------------------------------
+// workspaces
+// ---------------------------------------------------------------------------
+
+}  // namespace bw
+
+using namespace bw;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+#define BW_GUARD_BEGIN try {
+#define BW_GUARD_END                               \
+  }                                                \
+  catch (const bw::Error& e) {                     \
+    bw::set_error(e.msg);                          \
+    return e.code;                                 \
+  }                                                \
+  catch (const std::exception& e) {                \
+    bw::set_error(std::string("internal: ") + e.what()); \
+    return BW_EINVAL;                              \
+  }
+
+extern "C" const char* bw_last_error(void) { return g_last_error.c_str(); }
+
+static bool spd6(const double* c21) {
+  // Cholesky of the symmetric 6x6
+  double A[6][6];
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) A[a][b] = c21[vidx(a, b)];
+  for (int j = 0; j < 6; ++j) {
+    double d = A[j][j];
+    for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
+    if (!(d > 0)) return false;
+    d = std::sqrt(d);
+    A[j][j] = d;
+    for (int i = j + 1; i < 6; ++i) {
+      double v = A[i][j];
+      for (int k = 0; k < j; ++k) v -= A[i][k] * A[j][k];
+      A[i][j] = v / d;
+    }
+  }
+  return true;
+}
+
+extern "C" int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3], const uint16_t* grain_map_host,
+                             int32_t n_grains, const double* C21_host, const double* rho_host, int32_t precision,
+                             void* stream) {
+  BW_GUARD_BEGIN
+  BW_REQUIRE(out && n && L && grain_map_host && C21_host && rho_host, BW_EINVAL, "null argument");
+  *out = nullptr;
+  BW_REQUIRE(precision == BW_FP64 || precision == BW_MIXED, BW_EINVAL, "precision must be BW_FP64 or BW_MIXED");
+  BW_REQUIRE(n_grains >= 1 && n_grains <= 65535, BW_EINVAL, "n_grains out of range");
+  for (int a = 0; a < 3; ++a) {
+    BW_REQUIRE(n[a] >= 1, BW_EINVAL, "grid size must be >= 1");
+    BW_REQUIRE(L[a] > 0 && std::isfinite(L[a]), BW_EINVAL, "cell edge must be > 0");
+    BW_REQUIRE(size_supported(n[a]), BW_EUNSUPPORTED, "no compiled FFT of length " + std::to_string(n[a]));
+  }
+  const long nvox = (long)n[0] * n[1] * n[2];
+  BW_REQUIRE(nvox <= (1L << 30), BW_EINVAL, "grid too large");
+  for (int gi = 0; gi < n_grains; ++gi) {
+    BW_REQUIRE(rho_host[gi] > 0 && std::isfinite(rho_host[gi]), BW_EINVAL, "density must be > 0");
+    for (int i = 0; i < 21; ++i) BW_REQUIRE(std::isfinite(C21_host[gi * 21 + i]), BW_EINVAL, "non-finite stiffness");
+    BW_REQUIRE(spd6(C21_host + gi * 21), BW_EINVAL,
+               "stiffness of grain " + std::to_string(gi) + " is not positive definite");
+  }
+  std::vector<long> count(n_grains, 0);
+  for (long i = 0; i < nvox; ++i) {
+    BW_REQUIRE(grain_map_host[i] < n_grains, BW_EINVAL, "grain index out of range");
+    count[grain_map_host[i]]++;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  auto* r = new bw_rve();
+  try {
+    r->g = Geom{n[0], n[1], n[2], nvox};
+    for (int a = 0; a < 3; ++a) r->L[a] = L[a];
+    r->G = n_grains;
+    r->precision = precision;
+    BW_HIP(hipGetDevice(&r->device));
+    // volume averages (Sec. 3.3: C0 = volume-averaged stiffness)
+    double rs = 0;
+    for (int i = 0; i < 21; ++i) r->C0_si[i] = 0;
+    for (int gi = 0; gi < n_grains; ++gi) {
+      const double w = (double)count[gi] / (double)nvox;
+      for (int i = 0; i < 21; ++i) r->C0_si[i] += w * C21_host[gi * 21 + i];
+      rs += w * rho_host[gi];
+    }
+    r->rho_bar = rs;
+    r->Cref = r->C0_si[0];
+    r->ell = L[0] / (2.0 * M_PI);
+    for (int i = 0; i < 21; ++i) r->C0s[i] = r->C0_si[i] / r->Cref;
+    r->C21s_host.resize((size_t)n_grains * 21);
+    r->rhos_host.resize(n_grains);
+    for (int gi = 0; gi < n_grains; ++gi) {
+      for (int i = 0; i < 21; ++i) r->C21s_host[gi * 21 + i] = C21_host[gi * 21 + i] / r->Cref;
+      r->rhos_host[gi] = rho_host[gi] / r->rho_bar;
+    }
+    std::vector<float> c32(r->C21s_host.begin(), r->C21s_host.end());
+    std::vector<float> r32(r->rhos_host.begin(), r->rhos_host.end());
+    BW_HIP(hipMalloc(&r->d_gmap, nvox * sizeof(uint16_t)));
+    BW_HIP(hipMalloc(&r->d_C64, r->C21s_host.size() * sizeof(double)));
+    BW_HIP(hipMalloc(&r->d_C32, c32.size() * sizeof(float)));
+    BW_HIP(hipMalloc(&r->d_rho64, n_grains * sizeof(double)));
+    BW_HIP(hipMalloc(&r->d_rho32, n_grains * sizeof(float)));
+    BW_HIP(hipMemcpy(r->d_gmap, grain_map_host, nvox * sizeof(uint16_t), hipMemcpyHostToDevice));
+    BW_HIP(hipMemcpy(r->d_C64, r->C21s_host.data(), r->C21s_host.size() * sizeof(double), hipMemcpyHostToDevice));
+    BW_HIP(hipMemcpy(r->d_C32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
+    BW_HIP(hipMemcpy(r->d_rho64, r->rhos_host.data(), n_grains * sizeof(double), hipMemcpyHostToDevice));
+    BW_HIP(hipMemcpy(r->d_rho32, r32.data(), n_grains * sizeof(float), hipMemcpyHostToDevice));
+    // twiddle tables exp(-2 pi i t / N), computed in long double
+    for (int a = 0; a < 3; ++a) {
+      const int N = n[a];
+      std::vector<double> t64(2 * N);
+      std::vector<float> t32(2 * N);
+      for (int t = 0; t < N; ++t) {
+        const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)N;
+        t64[2 * t] = (double)cosl(ang);
+        t64[2 * t + 1] = (double)sinl(ang);
+        t32[2 * t] = (float)cosl(ang);
+        t32[2 * t + 1] = (float)sinl(ang);
+      }
+      BW_HIP(hipMalloc(&r->d_tw64[a], 2 * N * sizeof(double)));
+      BW_HIP(hipMalloc(&r->d_tw32[a], 2 * N * sizeof(float)));
+      BW_HIP(hipMemcpy(r->d_tw64[a], t64.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice));
+      BW_HIP(hipMemcpy(r->d_tw32[a], t32.data(), 2 * N * sizeof(float), hipMemcpyHostToDevice));
+    }
+    (void)s;
+  } catch (...) {
+    bw_destroy_rve(r);
+    throw;
+  }
+  *out = r;
+  return BW_OK;
+  BW_GUARD_END
+}
+
+extern "C" void bw_destroy_rve(bw_rve* r) {
+  if (!r) return;
+  (void)hipFree(r->d_gmap);
+  (void)hipFree(r->d_C64);
+  (void)hipFree(r->d_C32);
+  (void)hipFree(r->d_rho64);
+  (void)hipFree(r->d_rho32);
+  for (int a = 0; a < 3; ++a) {
+    (void)hipFree(r->d_tw64[a]);
+    (void)hipFree(r->d_tw32[a]);
+  }
+  r->ws_q.release();
+  r->ws_pcg.release();
+  r->ws_misc.release();
+  r->ws64.release();
+  r->ws32.release();
+  delete r;
+}
+
+extern "C" int bw_rve_info(const bw_rve* r, int32_t n[3], int32_t* precision, double C0_21[21], double* rho_bar) {
+  BW_GUARD_BEGIN
+  BW_REQUIRE(r, BW_EINVAL, "null cell");
+  if (n) {
+    n[0] = r->g.n0;
+    n[1] = r->g.n1;
+    n[2] = r->g.n2;
+  }
+  if (precision) *precision = r->precision;
+  if (C0_21)
+    for (int i = 0; i < 21; ++i) C0_21[i] = r->C0_si[i];
+  if (rho_bar) *rho_bar = r->rho_bar;
+  return BW_OK;
+  BW_GUARD_END
+}
+
+extern "C" int bw_apply_K(bw_rve* r, const double k[3], const void* u, void* y, int32_t nvec, void* stream) {
+  BW_GUARD_BEGIN
+  BW_REQUIRE(r && k && u && y, BW_EINVAL, "null argument");
+  BW_REQUIRE(nvec >= 0, BW_EINVAL, "nvec < 0");
+  BW_REQUIRE(u != y, BW_EINVAL, "u and y must not alias");
+  if (nvec == 0) return BW_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const double* q = qtab_for(r, k, nvec, s);
+  if (r->precision == BW_FP64) {
+    auto* W = ws<double>(r).work((size_t)nvec * 6 * r->g.nvox);
+    launch_apply_K<double>(r, q, (const cplx<double>*)u, (cplx<double>*)y, nvec, K_scale(r), W, s);
+  } else {
+    auto* W = ws<float>(r).work((size_t)nvec * 6 * r->g.nvox);
+    launch_apply_K<float>(r, q, (const cplx<float>*)u, (cplx<float>*)y, nvec, K_scale(r), W, s);
+  }
+  BW_HIP(hipGetLastError());
+  return BW_OK;
+  BW_GUARD_END
+}
+
+extern "C" int bw_apply_M(bw_rve* r, const void* u, void* y, int32_t nvec, void* stream) {
+  BW_GUARD_BEGIN
+  BW_REQUIRE(r && u && y, BW_EINVAL, "null argument");
+  BW_REQUIRE(nvec >= 0, BW_EINVAL, "nvec < 0");
+  BW_REQUIRE(u != y, BW_EINVAL, "u and y must not alias");
+  if (nvec == 0) return BW_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (r->precision == BW_FP64) {
+    auto* W = ws<double>(r).work((size_t)nvec * 6 * r->g.nvox);
+    launch_apply_M<double>(r, (const cplx<double>*)u, (cplx<double>*)y, nvec, M_scale(r), W, s);
+  } else {
+    auto* W = ws<float>(r).work((size_t)nvec * 6 * r->g.nvox);
+    launch_apply_M<float>(r, (const cplx<float>*)u, (cplx<float>*)y, nvec, M_scale(r), W, s);
+  }
+  BW_HIP(hipGetLastError());
+  return BW_OK;
+  BW_GUARD_END
+}
+
+extern "C" int bw_apply_P(bw_rve* r, const double k[3], const void* u, void* y, int32_t nvec, void* stream) {
+  BW_GUARD_BEGIN
+  BW_REQUIRE(r && k && u && y, BW_EINVAL, "null argument");
+  BW_REQUIRE(nvec >= 0, BW_EINVAL, "nvec < 0");
+  if (nvec == 0) return BW_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const double* q = qtab_for(r, k, nvec, s);
+  const double sc = 1.0 / K_scale(r);
+  if (r->precision == BW_FP64)
+    launch_apply_P<double>(r, q, (const cplx<double>*)u, (cplx<double>*)y, nvec, sc, s);
+  else
+    launch_apply_P<float>(r, q, (const cplx<float>*)u, (cplx<float>*)y, nvec, sc, s);
+  BW_HIP(hipGetLastError());
+  return BW_OK;
+  BW_GUARD_END
+}
+
+template <typename T>
+static int pcg_entry(bw_rve* r, const double* k, const void* b, void* x, int nrhs, double rtol, int maxit,
+                     int32_t* iters, double* relres, hipStream_t s) {
+  const Geom& g = r->g;
+  const double* q = qtab_for(r, k, nrhs, s);
+  QTable qt = make_qtable(r, k, 1);
+  const int nullv = qt.null_index[0];
+  const cplx<T>* bb = (const cplx<T>*)b;
+  cplx<T>* xx = (cplx<T>*)x;
+  if (nullv >= 0) {
+    // K is singular: b must vanish on the xi + k = 0 voxel
+    std::vector<cplx<T>> vals((size_t)nrhs * 3);
+    for (int v = 0; v < nrhs; ++v)
+      for (int c = 0; c < 3; ++c)
+        BW_HIP(hipMemcpyAsync(&vals[v * 3 + c], bb + ((size_t)v * 3 + c) * g.nvox + nullv, sizeof(cplx<T>),
+                              hipMemcpyDeviceToHost, s));
+    BW_HIP(hipStreamSynchronize(s));
+    for (auto& z : vals)
+      BW_REQUIRE(z.x == 0 && z.y == 0, BW_EINVAL, "b must vanish where xi + k = 0 (singular K)");
+  }
+  // x' = x * Kscale (solve the scaled system K' x' = b, K = Kscale K')
+  const double ks = K_scale(r);
+  scale_vectors<T>(xx, (size_t)nrhs * 3 * g.nvox, ks, s);
+  PcgResult res = pcg_run<T>(r, q, qt, bb, xx, nrhs, rtol, maxit, false, s);
+  scale_vectors<T>(xx, (size_t)nrhs * 3 * g.nvox, 1.0 / ks, s);
+  if (nullv >= 0) zero_voxel<T>(xx, nrhs, g.nvox, nullv, s);
+  BW_HIP(hipStreamSynchronize(s));
+  for (int v = 0; v < nrhs; ++v) {
+    if (iters) iters[v] = res.iters[v];
+    if (relres) relres[v] = res.relres[v];
+  }
+  if (!res.converged) {
+    set_error("PCG: some right-hand side did not reach the tolerance within maxit");
+    return BW_ENOTCONV;
+  }
+  return BW_OK;
+}
+
+extern "C" int bw_pcg_solve(bw_rve* r, const double k[3], const void* b, void* x, int32_t nrhs, double rtol,
+                            int32_t maxit, int32_t* iters, double* relres, void* stream) {
+  BW_GUARD_BEGIN
+  BW_REQUIRE(r && k && b && x, BW_EINVAL, "null argument");
+  BW_REQUIRE(nrhs >= 0, BW_EINVAL, "nrhs < 0");
+  BW_REQUIRE(rtol > 0 && rtol < 1, BW_EINVAL, "rtol must be in (0, 1)");
+  BW_REQUIRE(b != x, BW_EINVAL, "b and x must not alias");
+  if (nrhs == 0) return BW_OK;
+  if (maxit <= 0) maxit = 20000;
+  hipStream_t s = (hipStream_t)stream;
+  if (r->precision == BW_FP64) return pcg_entry<double>(r, k, b, x, nrhs, rtol, maxit, iters, relres, s);
+  return pcg_entry<float>(r, k, b, x, nrhs, rtol, maxit, iters, relres, s);
+  BW_GUARD_END
+}

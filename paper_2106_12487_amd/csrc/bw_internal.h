@@ -1,0 +1,200 @@
+// Internal declarations shared by the translation units of libblochwave.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/blochwave.h"
+#include "bw_fft.h"
+
+namespace bw {
+
+constexpr int NT = 256;  // threads per workgroup of the FFT / pointwise kernels
+
+// Maximum tile points per workgroup (one component of a tile is staged in LDS;
+// all components of a point live in registers).
+template <typename T> struct TileCfg;
+template <> struct TileCfg<float> { static constexpr int TP = 2048; };
+template <> struct TileCfg<double> { static constexpr int TP = 1024; };
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+struct Error {
+  int code;
+  std::string msg;
+};
+#define BW_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::bw::Error{BW_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)};      \
+  } while (0)
+#define BW_REQUIRE(cond, code, msg)                   \
+  do {                                                \
+    if (!(cond)) throw ::bw::Error{(code), (msg)};    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffer with grow-on-demand semantics
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void* get(size_t need) {
+    if (need > bytes) {
+      if (p) BW_HIP(hipFree(p));
+      p = nullptr;
+      bytes = 0;
+      hipError_t e = hipMalloc(&p, need);
+      if (e != hipSuccess) throw Error{BW_ENOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed"};
+      bytes = need;
+    }
+    return p;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+// Bloch data of a batch: per vector the scaled shifted wavevector tables
+// q_a(j) = m_a(j) L0 / L_a + k_a L0 / (2 pi), concatenated [n0 | n1 | n2].
+struct QTable {
+  std::vector<double> host;   // nvec * (n0 + n1 + n2)
+  int nvec = 0;
+  std::vector<int> null_index;  // per vector: flat voxel index where q = 0, or -1
+};
+
+// Geometry and per-launch tile choices of one cell.
+struct Geom {
+  int n0, n1, n2;
+  long nvox;
+};
+
+// Cached vector workspaces of one precision.
+template <typename T> struct Workspace {
+  DevBuf v[12];
+  DevBuf w;
+  cplx<T>* vec(int i, size_t n) { return (cplx<T>*)v[i].get(n * sizeof(cplx<T>)); }
+  cplx<T>* work(size_t n) { return (cplx<T>*)w.get(n * sizeof(cplx<T>)); }
+  void release() {
+    for (auto& b : v) b.release();
+    w.release();
+  }
+};
+
+struct PcgResult {
+  std::vector<int> iters;
+  std::vector<double> relres;
+  bool converged = false;
+  long total_iters = 0;
+  long block_iters = 0;
+};
+
+}  // namespace bw
+
+// The opaque cell handle.
+struct bw_rve {
+  bw::Geom g;
+  double L[3];
+  int G;
+  int precision;
+  int device;
+  // nondimensionalization: C' = C / Cref, q' = q * ell, rho' = rho / rho_bar
+  double Cref, ell, rho_bar;
+  double C0_si[21];     // volume-averaged stiffness (Pa)
+  double C0s[21];       // scaled
+  std::vector<double> C21s_host;  // G x 21 scaled
+  std::vector<double> rhos_host;  // G scaled
+  std::vector<uint16_t> gmap_host;
+  // device copies
+  uint16_t* d_gmap = nullptr;
+  double* d_C64 = nullptr;
+  float* d_C32 = nullptr;
+  double* d_rho64 = nullptr;
+  float* d_rho32 = nullptr;
+  double* d_tw64[3] = {nullptr, nullptr, nullptr};
+  float* d_tw32[3] = {nullptr, nullptr, nullptr};
+  double* d_C0s = nullptr;      // 21 scaled (double)
+  float* d_C0s32 = nullptr;     // 21 scaled (float)
+  // workspaces
+  bw::DevBuf ws_q, ws_pcg, ws_misc;
+  bw::Workspace<double> ws64;
+  bw::Workspace<float> ws32;
+  double qcache_k[3] = {0, 0, 0};
+  int qcache_nvec = -1;
+  int pcg_counters_nvec = 0;
+};
+
+namespace bw {
+
+// q tables for a list of k (SI, rad/m); fills null_index.
+QTable make_qtable(const bw_rve* r, const double* k_host, int nk);
+
+// Launchers (defined per precision in bw_ops_impl.h).  All pointers are device
+// pointers; qtab is a device table for nvec vectors.
+template <typename T>
+void launch_apply_K(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<T>* y, int nvec,
+                    double scale, cplx<T>* W, hipStream_t s);
+template <typename T>
+void launch_apply_M(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, double scale,
+                    cplx<T>* W, hipStream_t s);
+template <typename T>
+void launch_apply_P(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<T>* y, int nvec,
+                    double scale, hipStream_t s);
+
+// PCG building blocks (bw_ops_impl.h)
+struct PcgDev {
+  // per-vector scalars and control, device
+  double* rz;       // <r, z>
+  double* pAp;      // <p, K p>
+  double* alpha;
+  double* beta;
+  double* rr;       // ||r||^2
+  double* bb;       // ||b||^2 * tol^2 (threshold)
+  int* active;      // 1 while iterating
+  int* iters;       // iterations per vector
+  int* mask;        // restart selection
+  double* partial;  // [nvec][max_blocks] partial sums (2 per block)
+  unsigned* counter;  // [nvec] last-block counters
+  int max_blocks;
+};
+
+template <typename T>
+void launch_pcg_update(const bw_rve* r, const double* d_qtab, cplx<T>* x, cplx<T>* rv,
+                       const cplx<T>* p, const cplx<T>* Ap, int nvec, const PcgDev& pd,
+                       hipStream_t s);
+// r = b - K x stored in rv (K x computed into tmp), with ||r||^2, ||b||^2 (FP64)
+template <typename T>
+void launch_residual(const bw_rve* r, const double* d_qtab, const cplx<T>* b, const cplx<T>* x,
+                     cplx<T>* rv, cplx<T>* tmp, cplx<T>* W, int nvec, double* d_rr, double* d_bb,
+                     double* d_partial, unsigned* d_counter, int max_blocks, hipStream_t s);
+// z = P^ r, <r, z> -> rz, beta = 0 for restart
+template <typename T>
+void launch_pcg_restart(const bw_rve* r, const double* d_qtab, const cplx<T>* rv, int nvec,
+                        const PcgDev& pd, const int* d_mask, hipStream_t s);
+
+template <typename T>
+void launch_pcg_apply(const bw_rve* r, const double* d_qtab, const cplx<T>* rv, cplx<T>* p, cplx<T>* Ap,
+                      cplx<T>* W, int nvec, const PcgDev& pd, hipStream_t s);
+template <typename T> void scale_vectors(cplx<T>* x, size_t n, double sc, hipStream_t s);
+template <typename T> void zero_voxel(cplx<T>* x, int nvec, long nvox, long vox, hipStream_t s);
+
+// solver layer (bw_api.hip)
+template <typename T> Workspace<T>& ws(bw_rve* r);
+template <> inline Workspace<double>& ws<double>(bw_rve* r) { return r->ws64; }
+template <> inline Workspace<float>& ws<float>(bw_rve* r) { return r->ws32; }
+PcgDev pcg_dev(bw_rve* r, int nvec);
+const double* upload_qtable(bw_rve* r, const QTable& t, DevBuf& buf, hipStream_t s);
+double K_scale(const bw_rve* r);
+double M_scale(const bw_rve* r);
+template <typename T>
+PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<T>* b, cplx<T>* x, int nvec,
+                  double tol, int maxit, bool x0_zero, hipStream_t s);
+
+}  // namespace bw

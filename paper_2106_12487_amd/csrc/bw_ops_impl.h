@@ -1,0 +1,915 @@
+// Operator kernels of the Bloch method, templated on the working precision T.
+//
+// Data layout: a batch of vectors is [nvec][3][n0][n1][n2] complex (n2 fastest);
+// the strain / stress work array is [nvec][6][n0][n1][n2].  The 3D transforms
+// are split into one kernel per axis; the pointwise steps are fused into them:
+//
+//   K(k) u (Sec. 3.2 eq. hatA, six independent strain components by the minor
+//   symmetry of C):
+//     k_strain_row   e^ = B(q) u^ (Voigt strain), inverse FFT along axis 2
+//     k_axis1        inverse FFT along axis 1
+//     k_axis0_op     inverse FFT along axis 0, s = C(x) e, forward FFT axis 0
+//     k_axis1        forward FFT along axis 1
+//     k_row_div      forward FFT along axis 2, out = B(q)^T s^ (divergence)
+//   M u (eq. hatM): the same chain with three components and s = rho(x) u.
+//
+// One component of a tile is staged in LDS at a time; every component of the
+// points a thread owns stays in its registers, so a pass reads and writes each
+// word of its input and output once.  The 1/(n0 n1 n2) of the inverse
+// transform and the caller's scale are folded into the pointwise step.
+#pragma once
+#include <type_traits>
+
+#include "bw_internal.h"
+
+namespace bw {
+
+template <typename T> struct C21v { T c[21]; };
+
+// Voigt upper-triangle index of (a, b)
+__host__ __device__ constexpr int vidx(int a, int b) {
+  return a <= b ? a * 6 - (a * (a - 1)) / 2 + (b - a) : b * 6 - (b * (b - 1)) / 2 + (a - b);
+}
+
+// sigma = C e for one voxel (C symmetric 6x6 given by its 21 upper entries)
+template <typename T, typename V>
+__device__ __forceinline__ void contract6(const T* __restrict__ c, const V* e, V* s, T scale) {
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    T sx = 0, sy = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const T cab = c[vidx(a, b)];
+      sx += cab * e[b].x;
+      sy += cab * e[b].y;
+    }
+    s[a] = V{sx * scale, sy * scale};
+  }
+}
+
+// z = P(C0, q)^-1 r with P_ik = C0_ijkl q_j q_l (Sec. 3.3 eqs. matrixP, precond);
+// z = 0 where q = 0.
+template <typename T, typename V>
+__device__ __forceinline__ void precond3(const C21v<T>& C0, T q0, T q1, T q2, const V* r, V* z) {
+  if (q0 == T(0) && q1 == T(0) && q2 == T(0)) {
+    z[0] = z[1] = z[2] = V{0, 0};
+    return;
+  }
+  // B(q): rows = Voigt strain components, columns = displacement components
+  const T B[6][3] = {{q0, 0, 0}, {0, q1, 0}, {0, 0, q2}, {0, q2, q1}, {q2, 0, q0}, {q1, q0, 0}};
+  T CB[6][3];
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T acc = 0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) acc += C0.c[vidx(a, b)] * B[b][k];
+      CB[a][k] = acc;
+    }
+  T P[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) acc += B[a][i] * CB[a][k];
+      P[i][k] = acc;
+    }
+  const T a = P[0][0], b = P[0][1], c = P[0][2], d = P[1][1], e = P[1][2], f = P[2][2];
+  const T A00 = d * f - e * e, A01 = c * e - b * f, A02 = b * e - c * d;
+  const T A11 = a * f - c * c, A12 = b * c - a * e, A22 = a * d - b * b;
+  const T inv = T(1) / (a * A00 + b * A01 + c * A02);
+  const T Ai[3][3] = {{A00, A01, A02}, {A01, A11, A12}, {A02, A12, A22}};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T zx = 0, zy = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      zx += Ai[i][k] * r[k].x;
+      zy += Ai[i][k] * r[k].y;
+    }
+    z[i] = V{zx * inv, zy * inv};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions: wave64 shuffles, LDS across waves, deterministic last-block sum
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block sum (valid in thread 0).  `sh` needs NT/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) s += sh[i];
+  return s;
+}
+
+__device__ __forceinline__ double coherent_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publishes NV partial sums of this block for vector v and returns true in
+// the block that arrives last; that block then holds, in `tot`, the sums over
+// all blocks taken in block order (independent of arrival order).
+template <int NV>
+__device__ __forceinline__ bool reduce_partials(double (&vals)[NV], double (&tot)[NV], double* partial,
+                                                unsigned* counter, int v, int blk, int nblk, int maxb,
+                                                double* sh) {
+  __shared__ int is_last;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = block_sum(vals[i], sh);
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&partial[((size_t)v * maxb + blk) * NV + i], s, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = __hip_atomic_fetch_add(&counter[v], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (prev == (unsigned)(nblk - 1));
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double acc = 0;
+    for (int b = threadIdx.x; b < nblk; b += NT) acc += coherent_load(&partial[((size_t)v * maxb + b) * NV + i]);
+    tot[i] = block_sum(acc, sh);
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(&counter[v], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// tile bookkeeping for row kernels (axis 2, contiguous)
+// ---------------------------------------------------------------------------
+struct RowTile {
+  int NR, lsh, tpv;  // rows per tile, log2(NR), tiles per vector
+};
+struct ColTile {
+  int LT, lsh, tpv;  // lines per tile, log2(LT), tiles per vector
+};
+
+// ---------------------------------------------------------------------------
+// K, first pass: strain (optionally preceded by the PCG direction update
+// p = P^ r + beta p) and inverse FFT along axis 2.
+// MODE 0: u = U.  MODE 1: U = r, P = p (updated in place), u = p_new.
+// ---------------------------------------------------------------------------
+template <typename T, int N2, int MODE>
+__global__ __launch_bounds__(NT) void k_strain_row(const cplx<T>* __restrict__ U, cplx<T>* __restrict__ Pp,
+                                                   cplx<T>* __restrict__ W, const double* __restrict__ qtab,
+                                                   int n0, int n1, long nvox, RowTile rt,
+                                                   const cplx<T>* __restrict__ tw, const int* __restrict__ active,
+                                                   const double* __restrict__ beta, C21v<T> C0) {
+  using V = cplx<T>;
+  constexpr int TP = TileCfg<T>::TP;
+  constexpr int PPT = TP / NT;
+  __shared__ V lds[TP + N2];
+  const int v = blockIdx.x / rt.tpv;
+  const int tile = blockIdx.x - v * rt.tpv;
+  if (active && !active[v]) return;
+  const int tid = threadIdx.x;
+  const int npts = rt.NR * N2;
+  const int P = rt.NR + 1;
+  const double* q = qtab + (size_t)v * (n0 + n1 + N2);
+  T bt = 0;
+  if (MODE == 1) bt = (T)beta[v];
+  V u[3][PPT];
+  T qa[PPT], qb[PPT], qc[PPT];
+  int off[PPT];
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int idx = tid + s * NT;
+    off[s] = -1;
+    if (idx < npts) {
+      const int rl = idx / N2, n = idx - rl * N2;
+      const int row = tile * rt.NR + rl;
+      const int i0 = row / n1, i1 = row - i0 * n1;
+      off[s] = row * N2 + n;
+      qa[s] = (T)q[i0];
+      qb[s] = (T)q[n0 + i1];
+      qc[s] = (T)q[n0 + n1 + n];
+      V w[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[c] = U[((size_t)v * 3 + c) * nvox + off[s]];
+      if (MODE == 1) {
+        V z[3];
+        precond3<T, V>(C0, qa[s], qb[s], qc[s], w, z);
+        if (bt != T(0)) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) z[c] = caxpy(z[c], bt, Pp[((size_t)v * 3 + c) * nvox + off[s]]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          Pp[((size_t)v * 3 + c) * nvox + off[s]] = z[c];
+          w[c] = z[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u[c][s] = w[c];
+    }
+  }
+#pragma unroll 1
+  for (int c = 0; c < 6; ++c) {
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      if (off[s] >= 0) {
+        const int idx = tid + s * NT;
+        const int rl = idx / N2, n = idx - rl * N2;
+        V e;
+        switch (c) {
+          case 0: e = cscale(u[0][s], qa[s]); break;
+          case 1: e = cscale(u[1][s], qb[s]); break;
+          case 2: e = cscale(u[2][s], qc[s]); break;
+          case 3: e = cadd(cscale(u[1][s], qc[s]), cscale(u[2][s], qb[s])); break;
+          case 4: e = cadd(cscale(u[0][s], qc[s]), cscale(u[2][s], qa[s])); break;
+          default: e = cadd(cscale(u[0][s], qb[s]), cscale(u[1][s], qa[s])); break;
+        }
+        lds[n * P + rl] = e;
+      }
+    }
+    __syncthreads();
+    lds_fft<T, N2, true, NT, TP>(lds, P, rt.NR, rt.lsh, tw, tid);
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      if (off[s] >= 0) {
+        const int idx = tid + s * NT;
+        const int rl = idx / N2, n = idx - rl * N2;
+        W[((size_t)v * 6 + c) * nvox + off[s]] = lds[n * P + rl];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Last pass of K: forward FFT along axis 2 and divergence out_i = q_j s^_ij.
+// MODE 1 also forms <p, K p> (FP64) and, in the last block of the vector,
+// alpha = <r, z> / <p, K p>.
+// ---------------------------------------------------------------------------
+template <typename T, int N2, int MODE>
+__global__ __launch_bounds__(NT) void k_row_div(const cplx<T>* __restrict__ W, cplx<T>* __restrict__ Y,
+                                                const double* __restrict__ qtab, int n0, int n1, long nvox,
+                                                RowTile rt, const cplx<T>* __restrict__ tw,
+                                                const int* __restrict__ active, const cplx<T>* __restrict__ Pp,
+                                                PcgDev pd, T oscale) {
+  using V = cplx<T>;
+  constexpr int TP = TileCfg<T>::TP;
+  constexpr int PPT = TP / NT;
+  __shared__ V lds[TP + N2];
+  __shared__ double sh[NT / 64];
+  const int v = blockIdx.x / rt.tpv;
+  const int tile = blockIdx.x - v * rt.tpv;
+  if (active && !active[v]) return;
+  const int tid = threadIdx.x;
+  const int npts = rt.NR * N2;
+  const int P = rt.NR + 1;
+  const double* q = qtab + (size_t)v * (n0 + n1 + N2);
+  V acc[3][PPT];
+  T qa[PPT], qb[PPT], qc[PPT];
+  int off[PPT];
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int idx = tid + s * NT;
+    off[s] = -1;
+    acc[0][s] = acc[1][s] = acc[2][s] = V{0, 0};
+    if (idx < npts) {
+      const int rl = idx / N2, n = idx - rl * N2;
+      const int row = tile * rt.NR + rl;
+      const int i0 = row / n1, i1 = row - i0 * n1;
+      off[s] = row * N2 + n;
+      qa[s] = (T)q[i0];
+      qb[s] = (T)q[n0 + i1];
+      qc[s] = (T)q[n0 + n1 + n];
+    }
+  }
+#pragma unroll 1
+  for (int c = 0; c < 6; ++c) {
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      if (off[s] >= 0) {
+        const int idx = tid + s * NT;
+        const int rl = idx / N2, n = idx - rl * N2;
+        lds[n * P + rl] = W[((size_t)v * 6 + c) * nvox + off[s]];
+      }
+    }
+    __syncthreads();
+    lds_fft<T, N2, false, NT, TP>(lds, P, rt.NR, rt.lsh, tw, tid);
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      if (off[s] >= 0) {
+        const int idx = tid + s * NT;
+        const int rl = idx / N2, n = idx - rl * N2;
+        const V sg = lds[n * P + rl];
+        switch (c) {
+          case 0: acc[0][s] = caxpy(acc[0][s], qa[s], sg); break;                      // s11
+          case 1: acc[1][s] = caxpy(acc[1][s], qb[s], sg); break;                      // s22
+          case 2: acc[2][s] = caxpy(acc[2][s], qc[s], sg); break;                      // s33
+          case 3: acc[1][s] = caxpy(acc[1][s], qc[s], sg); acc[2][s] = caxpy(acc[2][s], qb[s], sg); break;  // s23
+          case 4: acc[0][s] = caxpy(acc[0][s], qc[s], sg); acc[2][s] = caxpy(acc[2][s], qa[s], sg); break;  // s13
+          default: acc[0][s] = caxpy(acc[0][s], qb[s], sg); acc[1][s] = caxpy(acc[1][s], qa[s], sg); break; // s12
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double part = 0;
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    if (off[s] >= 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const V o = cscale(acc[c][s], oscale);
+        Y[((size_t)v * 3 + c) * nvox + off[s]] = o;
+        if (MODE == 1) {
+          const V pv = Pp[((size_t)v * 3 + c) * nvox + off[s]];
+          part += (double)pv.x * (double)o.x + (double)pv.y * (double)o.y;
+        }
+      }
+    }
+  }
+  if (MODE == 1) {
+    double vals[1] = {part}, tot[1];
+    if (reduce_partials<1>(vals, tot, pd.partial, pd.counter, v, tile, rt.tpv, pd.max_blocks, sh)) {
+      if (threadIdx.x == 0) {
+        pd.pAp[v] = tot[0];
+        pd.alpha[v] = tot[0] > 0 ? pd.rz[v] / tot[0] : 0.0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plain row FFT (axis 2) of NC-component fields: rows are flattened over
+// (vector, component, i0, i1); a tile never crosses a component.
+// ---------------------------------------------------------------------------
+template <typename T, int N2, bool INV>
+__global__ __launch_bounds__(NT) void k_row_plain(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst,
+                                                  RowTile rt, int rows_per_vec, const cplx<T>* __restrict__ tw,
+                                                  const int* __restrict__ active) {
+  using V = cplx<T>;
+  constexpr int TP = TileCfg<T>::TP;
+  constexpr int PPT = TP / NT;
+  __shared__ V lds[TP + N2];
+  const int v = blockIdx.x / rt.tpv;
+  if (active && !active[v]) return;
+  const size_t base = ((size_t)v * rows_per_vec + (size_t)(blockIdx.x - v * rt.tpv) * rt.NR) * N2;
+  const int tid = threadIdx.x;
+  const int npts = rt.NR * N2;
+  const int P = rt.NR + 1;
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int idx = tid + s * NT;
+    if (idx < npts) {
+      const int rl = idx / N2, n = idx - rl * N2;
+      lds[n * P + rl] = src[base + idx];
+    }
+  }
+  __syncthreads();
+  lds_fft<T, N2, INV, NT, TP>(lds, P, rt.NR, rt.lsh, tw, tid);
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int idx = tid + s * NT;
+    if (idx < npts) {
+      const int rl = idx / N2, n = idx - rl * N2;
+      dst[base + idx] = lds[n * P + rl];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FFT along axis 1 (stride n2), in place, for NC-component fields.  Lines are
+// (plane, column) with plane = (component, i0); a tile holds LT consecutive
+// lines (within one plane, or whole consecutive planes).
+// ---------------------------------------------------------------------------
+template <typename T, int N1, bool INV>
+__global__ __launch_bounds__(NT) void k_axis1(cplx<T>* __restrict__ X, int n2, long vec_stride, ColTile ct,
+                                              const cplx<T>* __restrict__ tw, const int* __restrict__ active) {
+  using V = cplx<T>;
+  constexpr int TP = TileCfg<T>::TP;
+  constexpr int PPT = TP / NT;
+  __shared__ V lds[TP];
+  const int v = blockIdx.x / ct.tpv;
+  if (active && !active[v]) return;
+  const int tile = blockIdx.x - v * ct.tpv;
+  const int tid = threadIdx.x;
+  const int line = tid & (ct.LT - 1);
+  const int gl = tile * ct.LT + line;
+  const int plane = gl / n2, col = gl - plane * n2;
+  cplx<T>* base = X + (size_t)v * vec_stride + (size_t)plane * N1 * n2 + col;
+  const int npts = ct.LT * N1;
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int idx = tid + s * NT;
+    if (idx < npts) {
+      const int n = idx >> ct.lsh;
+      lds[n * ct.LT + line] = base[(size_t)n * n2];
+    }
+  }
+  __syncthreads();
+  lds_fft<T, N1, INV, NT, TP>(lds, ct.LT, ct.LT, ct.lsh, tw, tid);
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int idx = tid + s * NT;
+    if (idx < npts) {
+      const int n = idx >> ct.lsh;
+      base[(size_t)n * n2] = lds[n * ct.LT + line];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Axis 0: inverse FFT, pointwise real-space step, forward FFT, in place.
+// OP 0: stiffness contraction on 6 Voigt components (Ctab: G x 21).
+// OP 1: density scaling on 3 components (Ctab: G densities).
+// ---------------------------------------------------------------------------
+template <typename T, int N0, int OP>
+__global__ __launch_bounds__(NT) void k_axis0_op(cplx<T>* __restrict__ X, long n12, long nvox, ColTile ct,
+                                                 const uint16_t* __restrict__ gmap, const T* __restrict__ Ctab,
+                                                 T scale, const cplx<T>* __restrict__ tw,
+                                                 const int* __restrict__ active) {
+  using V = cplx<T>;
+  constexpr int NC = OP == 0 ? 6 : 3;
+  constexpr int TP = TileCfg<T>::TP;
+  constexpr int PPT = TP / NT;
+  __shared__ V lds[TP];
+  const int v = blockIdx.x / ct.tpv;
+  if (active && !active[v]) return;
+  const int tile = blockIdx.x - v * ct.tpv;
+  const int tid = threadIdx.x;
+  const int line = tid & (ct.LT - 1);
+  const long pos = (long)tile * ct.LT + line;
+  const int npts = ct.LT * N0;
+  V x[NC][PPT];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    cplx<T>* base = X + ((size_t)v * NC + c) * nvox + pos;
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int idx = tid + s * NT;
+      if (idx < npts) {
+        const int n = idx >> ct.lsh;
+        lds[n * ct.LT + line] = base[(size_t)n * n12];
+      }
+    }
+    __syncthreads();
+    lds_fft<T, N0, true, NT, TP>(lds, ct.LT, ct.LT, ct.lsh, tw, tid);
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int idx = tid + s * NT;
+      if (idx < npts) x[c][s] = lds[(idx >> ct.lsh) * ct.LT + line];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int idx = tid + s * NT;
+    if (idx < npts) {
+      const int n = idx >> ct.lsh;
+      const int g = gmap[(size_t)n * n12 + pos];
+      if (OP == 0) {
+        T cg[21];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) cg[i] = Ctab[g * 21 + i];
+        V e[6], sg[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) e[c] = x[c][s];
+        contract6<T, V>(cg, e, sg, scale);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) x[c][s] = sg[c];
+      } else {
+        const T rs = Ctab[g] * scale;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c][s] = cscale(x[c][s], rs);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    cplx<T>* base = X + ((size_t)v * NC + c) * nvox + pos;
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int idx = tid + s * NT;
+      if (idx < npts) lds[(idx >> ct.lsh) * ct.LT + line] = x[c][s];
+    }
+    __syncthreads();
+    lds_fft<T, N0, false, NT, TP>(lds, ct.LT, ct.LT, ct.lsh, tw, tid);
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int idx = tid + s * NT;
+      if (idx < npts) {
+        const int n = idx >> ct.lsh;
+        base[(size_t)n * n12] = lds[n * ct.LT + line];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pointwise kernels over [nvec][3][nvox]; each block owns a chunk of voxels of
+// one vector (grid = nvec * bpv).
+// ---------------------------------------------------------------------------
+struct VoxIdx {
+  int n0, n1, n2;
+  __device__ __forceinline__ void split(long vox, int& i0, int& i1, int& i2) const {
+    const long r = vox / n2;
+    i2 = (int)(vox - r * n2);
+    i0 = (int)(r / n1);
+    i1 = (int)(r - (long)i0 * n1);
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_apply_P(const cplx<T>* __restrict__ U, cplx<T>* __restrict__ Y,
+                                                const double* __restrict__ qtab, VoxIdx vi, long nvox, int bpv,
+                                                C21v<T> C0, T scale) {
+  using V = cplx<T>;
+  const int v = blockIdx.x / bpv;
+  const int b = blockIdx.x - v * bpv;
+  const double* q = qtab + (size_t)v * (vi.n0 + vi.n1 + vi.n2);
+  for (long vox = (long)b * NT + threadIdx.x; vox < nvox; vox += (long)bpv * NT) {
+    int i0, i1, i2;
+    vi.split(vox, i0, i1, i2);
+    V r[3], z[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = U[((size_t)v * 3 + c) * nvox + vox];
+    precond3<T, V>(C0, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], r, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Y[((size_t)v * 3 + c) * nvox + vox] = cscale(z[c], scale);
+  }
+}
+
+// x += alpha p; r -= alpha Kp; z = P^ r; <r, z>, ||r||^2; last block: beta,
+// convergence flag (recurrence residual below the threshold).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pcg_update(cplx<T>* __restrict__ x, cplx<T>* __restrict__ r,
+                                                   const cplx<T>* __restrict__ p, const cplx<T>* __restrict__ Ap,
+                                                   const double* __restrict__ qtab, VoxIdx vi, long nvox, int bpv,
+                                                   C21v<T> C0, PcgDev pd) {
+  using V = cplx<T>;
+  __shared__ double sh[NT / 64];
+  const int v = blockIdx.x / bpv;
+  const int b = blockIdx.x - v * bpv;
+  if (!pd.active[v]) return;
+  const T al = (T)pd.alpha[v];
+  const double* q = qtab + (size_t)v * (vi.n0 + vi.n1 + vi.n2);
+  double rz = 0, rr = 0;
+  for (long vox = (long)b * NT + threadIdx.x; vox < nvox; vox += (long)bpv * NT) {
+    int i0, i1, i2;
+    vi.split(vox, i0, i1, i2);
+    V rv[3], z[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t o = ((size_t)v * 3 + c) * nvox + vox;
+      const V pv = p[o];
+      x[o] = caxpy(x[o], al, pv);
+      rv[c] = caxpy(r[o], -al, Ap[o]);
+      r[o] = rv[c];
+    }
+    precond3<T, V>(C0, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], rv, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      rz += (double)rv[c].x * z[c].x + (double)rv[c].y * z[c].y;
+      rr += (double)rv[c].x * rv[c].x + (double)rv[c].y * rv[c].y;
+    }
+  }
+  double vals[2] = {rz, rr}, tot[2];
+  if (reduce_partials<2>(vals, tot, pd.partial, pd.counter, v, b, bpv, pd.max_blocks, sh)) {
+    if (threadIdx.x == 0) {
+      const double old = pd.rz[v];
+      pd.beta[v] = old != 0.0 ? tot[0] / old : 0.0;
+      pd.rz[v] = tot[0];
+      pd.rr[v] = tot[1];
+      pd.iters[v] += 1;
+      if (tot[1] <= pd.bb[v]) pd.active[v] = 0;
+    }
+  }
+}
+
+// r = b - Kx (Kx given), ||r||^2 and ||b||^2 per vector (FP64).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_residual(const cplx<T>* __restrict__ bv, const cplx<T>* __restrict__ Kx,
+                                                 cplx<T>* __restrict__ r, long nvox3, int bpv, double* rrv,
+                                                 double* bbv, double* partial, unsigned* counter, int maxb) {
+  using V = cplx<T>;
+  __shared__ double sh[NT / 64];
+  const int v = blockIdx.x / bpv;
+  const int b = blockIdx.x - v * bpv;
+  double rr = 0, bb = 0;
+  for (long i = (long)b * NT + threadIdx.x; i < nvox3; i += (long)bpv * NT) {
+    const size_t o = (size_t)v * nvox3 + i;
+    const V bb_ = bv[o];
+    const V rv = Kx ? csub(bb_, Kx[o]) : bb_;
+    r[o] = rv;
+    rr += (double)rv.x * rv.x + (double)rv.y * rv.y;
+    bb += (double)bb_.x * bb_.x + (double)bb_.y * bb_.y;
+  }
+  double vals[2] = {rr, bb}, tot[2];
+  if (reduce_partials<2>(vals, tot, partial, counter, v, b, bpv, maxb, sh)) {
+    if (threadIdx.x == 0) {
+      rrv[v] = tot[0];
+      if (bbv) bbv[v] = tot[1];
+    }
+  }
+}
+
+// restart of the selected vectors: rz = <r, P^ r>, beta = 0
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pcg_restart(const cplx<T>* __restrict__ r, const double* __restrict__ qtab,
+                                                    VoxIdx vi, long nvox, int bpv, C21v<T> C0, PcgDev pd,
+                                                    const int* __restrict__ mask) {
+  using V = cplx<T>;
+  __shared__ double sh[NT / 64];
+  const int v = blockIdx.x / bpv;
+  const int b = blockIdx.x - v * bpv;
+  if (!mask[v]) return;
+  const double* q = qtab + (size_t)v * (vi.n0 + vi.n1 + vi.n2);
+  double rz = 0;
+  for (long vox = (long)b * NT + threadIdx.x; vox < nvox; vox += (long)bpv * NT) {
+    int i0, i1, i2;
+    vi.split(vox, i0, i1, i2);
+    V rv[3], z[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rv[c] = r[((size_t)v * 3 + c) * nvox + vox];
+    precond3<T, V>(C0, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], rv, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rz += (double)rv[c].x * z[c].x + (double)rv[c].y * z[c].y;
+  }
+  double vals[1] = {rz}, tot[1];
+  if (reduce_partials<1>(vals, tot, pd.partial, pd.counter, v, b, bpv, pd.max_blocks, sh)) {
+    if (threadIdx.x == 0) {
+      pd.rz[v] = tot[0];
+      pd.beta[v] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side tile selection and size dispatch
+// ---------------------------------------------------------------------------
+inline int ilog2(int x) {
+  int l = 0;
+  while ((1 << (l + 1)) <= x) ++l;
+  return l;
+}
+
+template <typename T> RowTile row_tile(int N2, long rows_per_vec) {
+  constexpr int TP = TileCfg<T>::TP;
+  int NR = 1;
+  while (NR * 2 * N2 <= TP && rows_per_vec % (NR * 2) == 0) NR *= 2;
+  return RowTile{NR, ilog2(NR), (int)(rows_per_vec / NR)};
+}
+
+template <typename T> ColTile axis1_tile(int N1, int n2, long lines_per_vec) {
+  constexpr int TP = TileCfg<T>::TP;
+  int LT = 1;
+  while (LT * 2 * N1 <= TP && LT * 2 <= NT && lines_per_vec % (LT * 2) == 0 &&
+         (n2 % (LT * 2) == 0 || (LT * 2) % n2 == 0))
+    LT *= 2;
+  return ColTile{LT, ilog2(LT), (int)(lines_per_vec / LT)};
+}
+
+template <typename T> ColTile axis0_tile(int N0, long n12) {
+  constexpr int TP = TileCfg<T>::TP;
+  int LT = 1;
+  while (LT * 2 * N0 <= TP && LT * 2 <= NT && n12 % (LT * 2) == 0) LT *= 2;
+  return ColTile{LT, ilog2(LT), (int)(n12 / LT)};
+}
+
+#define BW_SIZES(X) X(1) X(2) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(40) X(48) X(64) X(96) X(128) X(256)
+
+template <class F> void with_n(int n, F&& f) {
+  switch (n) {
+#define BW_CASE(N) \
+  case N:          \
+    f(std::integral_constant<int, N>{}); \
+    break;
+    BW_SIZES(BW_CASE)
+#undef BW_CASE
+    default:
+      throw Error{BW_EUNSUPPORTED, "no compiled FFT of length " + std::to_string(n)};
+  }
+}
+
+inline bool size_supported(int n) {
+  switch (n) {
+#define BW_CASE(N) case N:
+    BW_SIZES(BW_CASE)
+#undef BW_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+template <typename T> const cplx<T>* twiddles(const bw_rve* r, int axis);
+template <> inline const cplx<double>* twiddles<double>(const bw_rve* r, int axis) {
+  return reinterpret_cast<const cplx<double>*>(r->d_tw64[axis]);
+}
+template <> inline const cplx<float>* twiddles<float>(const bw_rve* r, int axis) {
+  return reinterpret_cast<const cplx<float>*>(r->d_tw32[axis]);
+}
+template <typename T> const T* ctab(const bw_rve* r);
+template <> inline const double* ctab<double>(const bw_rve* r) { return r->d_C64; }
+template <> inline const float* ctab<float>(const bw_rve* r) { return r->d_C32; }
+template <typename T> const T* rhotab(const bw_rve* r);
+template <> inline const double* rhotab<double>(const bw_rve* r) { return r->d_rho64; }
+template <> inline const float* rhotab<float>(const bw_rve* r) { return r->d_rho32; }
+
+template <typename T> C21v<T> c0v(const bw_rve* r) {
+  C21v<T> c;
+  for (int i = 0; i < 21; ++i) c.c[i] = (T)r->C0s[i];
+  return c;
+}
+
+inline int pw_blocks(long nvox) {
+  long b = (nvox + NT * 4 - 1) / (NT * 4);
+  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+// ---------------------------------------------------------------------------
+// operator launchers
+// ---------------------------------------------------------------------------
+// Middle passes shared by K and M: inverse axis 1, axis-0 op, forward axis 1.
+template <typename T, int OP>
+void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* active, hipStream_t s) {
+  const Geom& g = r->g;
+  constexpr int NC = OP == 0 ? 6 : 3;
+  const long n12 = (long)g.n1 * g.n2;
+  if (g.n1 > 1) {
+    with_n(g.n1, [&](auto N1) {
+      ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2);
+      hipLaunchKernelGGL((k_axis1<T, decltype(N1)::value, true>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2,
+                         (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
+    });
+  }
+  with_n(g.n0, [&](auto N0) {
+    ColTile ct = axis0_tile<T>(N0, n12);
+    const T* tab = OP == 0 ? ctab<T>(r) : rhotab<T>(r);
+    hipLaunchKernelGGL((k_axis0_op<T, decltype(N0)::value, OP>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, n12,
+                       g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+  });
+  if (g.n1 > 1) {
+    with_n(g.n1, [&](auto N1) {
+      ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2);
+      hipLaunchKernelGGL((k_axis1<T, decltype(N1)::value, false>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2,
+                         (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
+    });
+  }
+}
+
+template <typename T>
+void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<T>* y, int nvec, double scale,
+                  cplx<T>* W, hipStream_t s, int mode, cplx<T>* pp, const PcgDev* pd) {
+  const Geom& g = r->g;
+  const int* active = mode == 1 ? pd->active : nullptr;
+  PcgDev dummy{};
+  with_n(g.n2, [&](auto N2) {
+    constexpr int n2c = decltype(N2)::value;
+    RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1);
+    if (mode == 0)
+      hipLaunchKernelGGL((k_strain_row<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, (cplx<T>*)nullptr, W,
+                         d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active, (const double*)nullptr,
+                         c0v<T>(r));
+    else
+      hipLaunchKernelGGL((k_strain_row<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, pp, W, d_qtab, g.n0,
+                         g.n1, g.nvox, rt, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
+  });
+  launch_middle<T, 0>(r, W, nvec, (T)(1.0 / (double)g.nvox), active, s);
+  with_n(g.n2, [&](auto N2) {
+    constexpr int n2c = decltype(N2)::value;
+    RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1);
+    if (mode == 0)
+      hipLaunchKernelGGL((k_row_div<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab, g.n0, g.n1,
+                         g.nvox, rt, twiddles<T>(r, 2), active, (const cplx<T>*)nullptr, dummy, (T)scale);
+    else
+      hipLaunchKernelGGL((k_row_div<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab, g.n0, g.n1,
+                         g.nvox, rt, twiddles<T>(r, 2), active, (const cplx<T>*)pp, *pd, (T)scale);
+  });
+}
+
+template <typename T>
+void launch_apply_K(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<T>* y, int nvec, double scale,
+                    cplx<T>* W, hipStream_t s) {
+  apply_K_impl<T>(r, d_qtab, u, y, nvec, scale, W, s, 0, nullptr, nullptr);
+}
+
+template <typename T>
+void launch_apply_M(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, double scale, cplx<T>* W,
+                    hipStream_t s) {
+  const Geom& g = r->g;
+  const long rows = 3L * g.n0 * g.n1;
+  with_n(g.n2, [&](auto N2) {
+    constexpr int n2c = decltype(N2)::value;
+    RowTile rt = row_tile<T>(n2c, rows);
+    hipLaunchKernelGGL((k_row_plain<T, n2c, true>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, W, rt, (int)rows,
+                       twiddles<T>(r, 2), (const int*)nullptr);
+  });
+  launch_middle<T, 1>(r, W, nvec, (T)(scale / (double)g.nvox), nullptr, s);
+  with_n(g.n2, [&](auto N2) {
+    constexpr int n2c = decltype(N2)::value;
+    RowTile rt = row_tile<T>(n2c, rows);
+    hipLaunchKernelGGL((k_row_plain<T, n2c, false>), dim3(nvec * rt.tpv), dim3(NT), 0, s, (const cplx<T>*)W, y, rt,
+                       (int)rows, twiddles<T>(r, 2), (const int*)nullptr);
+  });
+}
+
+template <typename T>
+void launch_apply_P(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<T>* y, int nvec, double scale,
+                    hipStream_t s) {
+  const Geom& g = r->g;
+  const int bpv = pw_blocks(g.nvox);
+  hipLaunchKernelGGL((k_apply_P<T>), dim3(nvec * bpv), dim3(NT), 0, s, u, y, d_qtab, VoxIdx{g.n0, g.n1, g.n2},
+                     g.nvox, bpv, c0v<T>(r), (T)scale);
+}
+
+template <typename T>
+void launch_pcg_apply(const bw_rve* r, const double* d_qtab, const cplx<T>* rv, cplx<T>* p, cplx<T>* Ap, cplx<T>* W,
+                      int nvec, const PcgDev& pd, hipStream_t s) {
+  apply_K_impl<T>(r, d_qtab, rv, Ap, nvec, 1.0, W, s, 1, p, &pd);
+}
+
+template <typename T>
+void launch_pcg_update(const bw_rve* r, const double* d_qtab, cplx<T>* x, cplx<T>* rv, const cplx<T>* p,
+                       const cplx<T>* Ap, int nvec, const PcgDev& pd, hipStream_t s) {
+  const Geom& g = r->g;
+  const int bpv = pw_blocks(g.nvox);
+  hipLaunchKernelGGL((k_pcg_update<T>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
+                     VoxIdx{g.n0, g.n1, g.n2}, g.nvox, bpv, c0v<T>(r), pd);
+}
+
+template <typename T>
+void launch_residual(const bw_rve* r, const double* d_qtab, const cplx<T>* b, const cplx<T>* x, cplx<T>* rv,
+                     cplx<T>* tmp, cplx<T>* W, int nvec, double* d_rr, double* d_bb, double* d_partial,
+                     unsigned* d_counter, int max_blocks, hipStream_t s) {
+  const Geom& g = r->g;
+  if (x) launch_apply_K<T>(r, d_qtab, x, tmp, nvec, 1.0, W, s);
+  const int bpv = pw_blocks(g.nvox * 3);
+  hipLaunchKernelGGL((k_residual<T>), dim3(nvec * bpv), dim3(NT), 0, s, b, x ? (const cplx<T>*)tmp : nullptr, rv,
+                     g.nvox * 3, bpv, d_rr, d_bb, d_partial, d_counter, max_blocks);
+}
+
+template <typename T>
+void launch_pcg_restart(const bw_rve* r, const double* d_qtab, const cplx<T>* rv, int nvec, const PcgDev& pd,
+                        const int* d_mask, hipStream_t s) {
+  const Geom& g = r->g;
+  const int bpv = pw_blocks(g.nvox);
+  hipLaunchKernelGGL((k_pcg_restart<T>), dim3(nvec * bpv), dim3(NT), 0, s, rv, d_qtab, VoxIdx{g.n0, g.n1, g.n2},
+                     g.nvox, bpv, c0v<T>(r), pd, d_mask);
+}
+
+template <typename T>
+__global__ void k_scale(cplx<T>* x, size_t n, T sc) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[i] = cscale(x[i], sc);
+}
+template <typename T>
+__global__ void k_zero_voxel(cplx<T>* x, int nvec, long nvox, long vox) {
+  const int i = threadIdx.x;
+  if (i < nvec * 3) x[(size_t)i * nvox + vox] = cplx<T>{0, 0};
+}
+template <typename T> void scale_vectors(cplx<T>* x, size_t n, double sc, hipStream_t s) {
+  if (n == 0) return;
+  long b = (long)((n + NT - 1) / NT);
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL((k_scale<T>), dim3((unsigned)b), dim3(NT), 0, s, x, n, (T)sc);
+}
+template <typename T> void zero_voxel(cplx<T>* x, int nvec, long nvox, long vox, hipStream_t s) {
+  for (int v0 = 0; v0 < nvec; v0 += 64) {
+    const int nv = nvec - v0 < 64 ? nvec - v0 : 64;
+    hipLaunchKernelGGL((k_zero_voxel<T>), dim3(1), dim3(192), 0, s, x + (size_t)v0 * 3 * nvox, nv, nvox, vox);
+  }
+}
+
+#define BW_INSTANTIATE_OPS(T)                                                                                      \
+  template void launch_apply_K<T>(const bw_rve*, const double*, const cplx<T>*, cplx<T>*, int, double, cplx<T>*,    \
+                                  hipStream_t);                                                                    \
+  template void launch_apply_M<T>(const bw_rve*, const cplx<T>*, cplx<T>*, int, double, cplx<T>*, hipStream_t);     \
+  template void launch_apply_P<T>(const bw_rve*, const double*, const cplx<T>*, cplx<T>*, int, double, hipStream_t); \
+  template void launch_pcg_apply<T>(const bw_rve*, const double*, const cplx<T>*, cplx<T>*, cplx<T>*, cplx<T>*,     \
+                                    int, const PcgDev&, hipStream_t);                                              \
+  template void launch_pcg_update<T>(const bw_rve*, const double*, cplx<T>*, cplx<T>*, const cplx<T>*,              \
+                                     const cplx<T>*, int, const PcgDev&, hipStream_t);                             \
+  template void launch_residual<T>(const bw_rve*, const double*, const cplx<T>*, const cplx<T>*, cplx<T>*,          \
+                                   cplx<T>*, cplx<T>*, int, double*, double*, double*, unsigned*, int, hipStream_t); \
+  template void launch_pcg_restart<T>(const bw_rve*, const double*, const cplx<T>*, int, const PcgDev&, const int*, \
+                                      hipStream_t);                                                                 \
+  template void scale_vectors<T>(cplx<T>*, size_t, double, hipStream_t);                                           \
+  template void zero_voxel<T>(cplx<T>*, int, long, long, hipStream_t);
+
+}  // namespace bw
