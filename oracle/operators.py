@@ -41,7 +41,10 @@ class Operators:
         self.k = np.asarray(k, dtype=np.float64)
         C6 = np.stack([c21_to_voigt(c) for c in rve.C21])          # (G, 6, 6)
         g = rve.grain_map.astype(np.int64)
+        self.C6 = C6
         self.C_field = C6[g]                                        # (N0, N1, N2, 6, 6)
+        flat = g.ravel()
+        self.grain_voxels = [(gi, np.nonzero(flat == gi)[0]) for gi in range(C6.shape[0])]
         self.rho_field = rve.rho[g]                                 # (N0, N1, N2)
         self.C0 = self.C_field.reshape(-1, 6, 6).mean(axis=0)       # volume average
         self.rho_bar = float(self.rho_field.mean())
@@ -70,8 +73,12 @@ class Operators:
     def apply_K(self, U: np.ndarray) -> np.ndarray:
         """K(k) U^ (eq. hatA)."""
         e = ifft3(self.strain(U))                                   # real-space strain
-        s = np.einsum("xyzab,...bxyz->...axyz", self.C_field, e, optimize=True)
-        return self.divergence(fft3(s))
+        E = e.reshape(e.shape[:-3] + (-1,))                         # (..., 6, nvox)
+        S = np.empty_like(E)
+        for gi, idx in self.grain_voxels:                           # s(x) = C(x) e(x)
+            if idx.size:
+                S[..., idx] = self.C6[gi] @ E[..., idx]
+        return self.divergence(fft3(S.reshape(e.shape)))
 
     # -- M, M^-1 ---------------------------------------------------------------
     def apply_M(self, U: np.ndarray) -> np.ndarray:
@@ -96,7 +103,8 @@ class Operators:
             Pinv = np.linalg.inv(P)
             Pinv[self.null_mask] = 0.0
             self._Pinv = Pinv
-        return np.einsum("xyzik,...kxyz->...ixyz", self._Pinv, R, optimize=True)
+        Rt = np.moveaxis(R, -4, -1)[..., None]                      # (..., N0, N1, N2, 3, 1)
+        return np.moveaxis((self._Pinv @ Rt)[..., 0], -1, -4)
 
     # -- dense assembly (Sec. 3.3: the dense-matrix argument; used on tiny grids) --
     def dense(self, which: str = "K") -> np.ndarray:

@@ -2,6 +2,7 @@
 // solver (Sec. 3.3, Algorithm "InvA").
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 
 #include "bw_ops_impl.h"
@@ -114,7 +115,7 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
   BW_HIP(hipStreamSynchronize(s));
 
   const int chunk = g.nvox >= (1 << 18) ? 4 : 8;
-  std::vector<int> its(nvec);
+  std::vector<int> its(nvec), mask(nvec, 0);
   int restarts = 0;
   for (;;) {
     bool any = false;
@@ -145,7 +146,7 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
     BW_HIP(hipMemcpyAsync(its.data(), pd.iters, nvec * sizeof(int), hipMemcpyDeviceToHost, s));
     BW_HIP(hipStreamSynchronize(s));
     bool again = false;
-    std::vector<int> mask(nvec, 0);
+    std::fill(mask.begin(), mask.end(), 0);
     for (int v = 0; v < nvec; ++v) {
       if (rr[v] > thr[v] && its[v] < maxit && restarts < 8) {
         mask[v] = 1;
@@ -304,6 +305,18 @@ extern "C" int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3]
     }
     std::vector<float> c32(r->C21s_host.begin(), r->C21s_host.end());
     std::vector<float> r32(r->rhos_host.begin(), r->rhos_host.end());
+    std::vector<double> ri64(n_grains);
+    std::vector<float> ri32(n_grains);
+    for (int gi = 0; gi < n_grains; ++gi) {
+      ri64[gi] = 1.0 / r->rhos_host[gi];
+      ri32[gi] = (float)ri64[gi];
+    }
+    BW_HIP(hipMalloc(&r->d_rhoinv64, n_grains * sizeof(double)));
+    BW_HIP(hipMalloc(&r->d_rhoinv32, n_grains * sizeof(float)));
+    BW_HIP(hipMemcpy(r->d_rhoinv64, ri64.data(), n_grains * sizeof(double), hipMemcpyHostToDevice));
+    BW_HIP(hipMemcpy(r->d_rhoinv32, ri32.data(), n_grains * sizeof(float), hipMemcpyHostToDevice));
+    BW_HIP(hipMalloc(&r->d_ctr, 1024 * sizeof(unsigned)));
+    BW_HIP(hipMemset(r->d_ctr, 0, 1024 * sizeof(unsigned)));
     BW_HIP(hipMalloc(&r->d_gmap, nvox * sizeof(uint16_t)));
     BW_HIP(hipMalloc(&r->d_C64, r->C21s_host.size() * sizeof(double)));
     BW_HIP(hipMalloc(&r->d_C32, c32.size() * sizeof(float)));
@@ -348,11 +361,17 @@ extern "C" void bw_destroy_rve(bw_rve* r) {
   (void)hipFree(r->d_C32);
   (void)hipFree(r->d_rho64);
   (void)hipFree(r->d_rho32);
+  (void)hipFree(r->d_rhoinv64);
+  (void)hipFree(r->d_rhoinv32);
+  (void)hipFree(r->d_ctr);
   for (int a = 0; a < 3; ++a) {
     (void)hipFree(r->d_tw64[a]);
     (void)hipFree(r->d_tw32[a]);
   }
   r->ws_q.release();
+  r->ws_q2.release();
+  r->ws_red.release();
+  r->ws_red2.release();
   r->ws_pcg.release();
   r->ws_misc.release();
   r->ws64.release();

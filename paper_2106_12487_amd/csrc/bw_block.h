@@ -1,0 +1,49 @@
+// Block kernels of the eigen-solvers: Gram products on FP64 MFMA, Ritz
+// updates, batched inner products, the small generalized Hermitian
+// eigenproblem (single workgroup, FP64), Gamma-point deflation and vector
+// utilities.  Blocks of vectors are stored vector-major: vector p starts at
+// X + p * vstride (complex elements), each of length n.
+#pragma once
+#include "bw_internal.h"
+
+namespace bw {
+
+constexpr int GRAM_QMAX = 32;  // Gram / Ritz block limit
+constexpr int GEIG_QMAX = 48;  // small eigenproblem limit
+
+// G[i][j] = sum_e conj(X_i[e]) Y_j[e], i < qx, j < qy  (FP64, deterministic)
+template <typename T>
+void launch_gram(const cplx<T>* X, int qx, const cplx<T>* Y, int qy, long n, long vstride, double2* G,
+                 DevBuf& scratch, unsigned* counter, hipStream_t s);
+// Y_j = sum_p X_p Q[p][j], j < qout (Q is q x q row-major, FP64)
+template <typename T>
+void launch_ritz(const cplx<T>* X, int q, const double2* Q, int ldq, cplx<T>* Y, int qout, long n, long vstride,
+                 hipStream_t s);
+// out[p] = <X_p, Y_p> (complex, FP64) for p < nv
+template <typename T>
+void launch_dots(const cplx<T>* X, const cplx<T>* Y, int nv, long n, long vstride, double2* out, DevBuf& scratch,
+                 unsigned* counters, hipStream_t s);
+// R_p = A_p - lam_p B_p (lam device, FP64)
+template <typename T>
+void launch_lincomb(const cplx<T>* A, const cplx<T>* B, const double* lam, cplx<T>* R, int nv, long n, long vstride,
+                    hipStream_t s);
+// Y_p = s_p X_p (s device)
+template <typename T>
+void launch_scale_cols(const cplx<T>* X, const double* sc, cplx<T>* Y, int nv, long n, long vstride, hipStream_t s);
+// dst (TD) = src (TS)
+template <typename TS, typename TD>
+void launch_convert(const cplx<TS>* src, cplx<TD>* dst, size_t n, hipStream_t s);
+// M-orthogonal projection off the rigid translations for (X, MX) pairs; MN are
+// the three vectors M e_{j*,c}; coefficients a_c = MX_p(c, j*) (M n_c is 1 at j*).
+template <typename T>
+void launch_deflate(cplx<T>* X, cplx<T>* MX, const cplx<T>* MN, int nv, long nvox, long jstar, double2* coef,
+                    hipStream_t s);
+// plane-wave start vectors: vector p = pol[p] at voxel vox[p] (others zero)
+template <typename T>
+void launch_planewaves(cplx<T>* U, int nv, long nvox, const long* vox, const double* pol, hipStream_t s);
+// small generalized Hermitian eigenproblem Kq z = lam Mq z (q <= GEIG_QMAX):
+// lam ascending, Q with Q^H Mq Q = I.  info[0] != 0 if Mq is not positive definite.
+void launch_small_geig(const double2* Kq, const double2* Mq, int q, double* lam, double2* Q, int* info,
+                       hipStream_t s);
+
+}  // namespace bw

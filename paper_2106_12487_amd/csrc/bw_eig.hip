@@ -1,8 +1,494 @@
-// Eigen-solver layer (placeholder until the subspace / Lanczos drivers land).
+// Eigen-solver drivers (host side): subspace iteration (Sec. 3.3, Algorithm
+// "subspace") on the batched PCG, the per-k dispersion loop (Algorithm "Full
+// algorithm") with the Gamma-point deflation, and the FP64 Rayleigh-Ritz
+// refinement with a-posteriori error bounds of the mixed-precision path.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "bw_block.h"
 #include "bw_internal.h"
 
-extern "C" int bw_lowest_modes(bw_rve*, const double*, int32_t, int32_t, const bw_eig_opts*, double*, double*,
-                               void*, bw_stats*, void*) {
-  bw::set_error("bw_lowest_modes: not built yet");
-  return BW_EUNSUPPORTED;
+namespace bw {
+
+struct EigOpts {
+  int method, block, ncv, maxit_outer, maxit_lin, warm;
+  double tol_eig, tol_lin;
+};
+
+struct Counters {
+  long pcg_iters = 0, block_iters = 0, outer = 0, kap = 0, map = 0;
+};
+
+// Small device arrays shared by the drivers (one allocation per cell).
+struct Small {
+  double2 *Kq, *Mq, *Q, *dots, *coef;
+  double *lam, *sc;
+  int* info;
+  long* vox;
+  double* pol;
+};
+
+static Small small_bufs(bw_rve* r) {
+  constexpr int QE = GEIG_QMAX;
+  const size_t b2 = sizeof(double2);
+  const size_t need = 3 * QE * QE * b2 + 2 * 256 * b2 + 2 * 256 * sizeof(double) + 64 + 256 * sizeof(long) +
+                      3 * 256 * sizeof(double) + 1024;
+  char* p = (char*)r->ws_misc.get(need);
+  Small s;
+  s.Kq = (double2*)p;
+  s.Mq = s.Kq + QE * QE;
+  s.Q = s.Mq + QE * QE;
+  s.dots = s.Q + QE * QE;
+  s.coef = s.dots + 256;
+  s.lam = (double*)(s.coef + 256);
+  s.sc = s.lam + 256;
+  s.info = (int*)(s.sc + 256);
+  s.vox = (long*)((char*)s.info + 64);
+  s.pol = (double*)(s.vox + 256);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// cold start: lowest plane waves of the homogeneous reference medium
+// (C0, mean density): eigenpairs of P(C0, xi + k) / rho_bar per Fourier voxel.
+// ---------------------------------------------------------------------------
+static void eig3(double A[3][3], double w[3], double V[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) V[i][j] = i == j;
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    if (off < 1e-300) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (std::fabs(A[p][q]) < 1e-300) continue;
+        const double tau = (A[q][q] - A[p][p]) / (2 * A[p][q]);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1 + tau * tau));
+        const double c = 1 / std::sqrt(1 + t * t), s = t * c;
+        for (int k = 0; k < 3; ++k) {
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - s * akq;
+          A[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - s * aqk;
+          A[q][k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < 3; ++i) w[i] = A[i][i];
+}
+
+static void reference_start(const bw_rve* r, const QTable& qt, int count, std::vector<long>& vox,
+                            std::vector<double>& pol) {
+  const Geom& g = r->g;
+  const double* q0 = qt.host.data();
+  const double* q1 = q0 + g.n0;
+  const double* q2 = q1 + g.n1;
+  const long nv = g.nvox;
+  std::vector<std::pair<double, long>> cand;
+  cand.reserve(nv);
+  for (long v = 0; v < nv; ++v) {
+    const int i2 = (int)(v % g.n2), i1 = (int)((v / g.n2) % g.n1), i0 = (int)(v / ((long)g.n1 * g.n2));
+    const double qq = q0[i0] * q0[i0] + q1[i1] * q1[i1] + q2[i2] * q2[i2];
+    if (qq == 0.0) continue;
+    cand.emplace_back(qq, v);
+  }
+  const size_t keep = std::min(cand.size(), (size_t)std::max(64, 8 * count));
+  std::partial_sort(cand.begin(), cand.begin() + keep, cand.end());
+  struct E {
+    double lam, qq;
+    long v;
+    int p;
+    double vec[3];
+  };
+  std::vector<E> es;
+  double C[6][6];
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) {
+      const int i = a <= b ? a * 6 - (a * (a - 1)) / 2 + (b - a) : b * 6 - (b * (b - 1)) / 2 + (a - b);
+      C[a][b] = r->C0s[i];
+    }
+  for (size_t c = 0; c < keep; ++c) {
+    const long v = cand[c].second;
+    const int i2 = (int)(v % g.n2), i1 = (int)((v / g.n2) % g.n1), i0 = (int)(v / ((long)g.n1 * g.n2));
+    const double qa = q0[i0], qb = q1[i1], qc = q2[i2];
+    const double B[6][3] = {{qa, 0, 0}, {0, qb, 0}, {0, 0, qc}, {0, qc, qb}, {qc, 0, qa}, {qb, qa, 0}};
+    double P[3][3] = {{0}};
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 6; ++a)
+          for (int b = 0; b < 6; ++b) P[i][k] += B[a][i] * C[a][b] * B[b][k];
+    double w[3], V[3][3];
+    eig3(P, w, V);
+    for (int p = 0; p < 3; ++p) es.push_back(E{w[p], cand[c].first, v, p, {V[0][p], V[1][p], V[2][p]}});
+  }
+  std::sort(es.begin(), es.end(), [](const E& a, const E& b) {
+    if (a.lam != b.lam) return a.lam < b.lam;
+    if (a.qq != b.qq) return a.qq < b.qq;
+    if (a.v != b.v) return a.v < b.v;
+    return a.p < b.p;
+  });
+  vox.resize(count);
+  pol.resize(3 * count);
+  for (int i = 0; i < count; ++i) {
+    vox[i] = es[i].v;
+    for (int c = 0; c < 3; ++c) pol[3 * i + c] = es[i].vec[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-k subspace iteration
+// ---------------------------------------------------------------------------
+struct KOut {
+  std::vector<double> lam;   // n_want scaled eigenvalues (ascending)
+  std::vector<double> bound; // relative bound on omega
+  int n_want = 0;
+  long jstar = -1;
+  bool converged = true;
+  int outer = 0;
+};
+
+template <typename T> static void apply_K_blk(bw_rve* r, const double* dq, const cplx<T>* u, cplx<T>* y, int nv,
+                                               Counters& c, hipStream_t s) {
+  if (nv <= 0) return;
+  launch_apply_K<T>(r, dq, u, y, nv, 1.0, ws<T>(r).work((size_t)nv * 6 * r->g.nvox), s);
+  c.kap += nv;
+}
+template <typename T> static void apply_M_blk(bw_rve* r, const cplx<T>* u, cplx<T>* y, int nv, bool inverse,
+                                               Counters& c, hipStream_t s) {
+  if (nv <= 0) return;
+  launch_apply_Minv_or_M<T>(r, u, y, nv, inverse, ws<T>(r).work((size_t)nv * 6 * r->g.nvox), s);
+  c.map += nv;
+}
+
+// Rigid-translation data at a Gamma-like k: MN = M e_{j*, c}, c = 0..2.
+template <typename T>
+static void rigid_MN(bw_rve* r, long jstar, cplx<T>* N, cplx<T>* MN, Small& sm, Counters& c, hipStream_t s) {
+  std::vector<long> vox = {jstar, jstar, jstar};
+  std::vector<double> pol = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  BW_HIP(hipMemcpyAsync(sm.vox, vox.data(), 3 * sizeof(long), hipMemcpyHostToDevice, s));
+  BW_HIP(hipMemcpyAsync(sm.pol, pol.data(), 9 * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_planewaves<T>(N, 3, r->g.nvox, sm.vox, sm.pol, s);
+  apply_M_blk<T>(r, N, MN, 3, false, c, s);
+  BW_HIP(hipStreamSynchronize(s));
+}
+
+// FP64 Rayleigh-Ritz on span(U) and residual bounds (M^-1 norm).  U is
+// replaced by the Ritz vectors.  Returns lam (q) and the relative omega bound
+// of the first n_want.
+static void rr64_bounds(bw_rve* r, const double* dq, cplx<double>*& U, int q, int n_want, std::vector<double>& lam,
+                        std::vector<double>& bound, bool do_rr, const cplx<double>* KUin, const cplx<double>* MUin,
+                        Counters& cnt, hipStream_t s) {
+  Workspace<double>& w = ws<double>(r);
+  const long n3 = r->g.nvox * 3;
+  Small sm = small_bufs(r);
+  const cplx<double>* KU = KUin;
+  const cplx<double>* MU = MUin;
+  cplx<double>* R = w.vec(9, (size_t)q * n3);
+  cplx<double>* Z = w.vec(11, (size_t)q * n3);
+  lam.resize(q);
+  if (do_rr) {
+    cplx<double>* U2 = w.vec(4, (size_t)q * n3);
+    cplx<double>* KU0 = w.vec(5, (size_t)q * n3);
+    cplx<double>* MU0 = w.vec(6, (size_t)q * n3);
+    cplx<double>* KU1 = w.vec(7, (size_t)q * n3);
+    cplx<double>* MU1 = w.vec(8, (size_t)q * n3);
+    apply_K_blk<double>(r, dq, U, KU0, q, cnt, s);
+    apply_M_blk<double>(r, U, MU0, q, false, cnt, s);
+    launch_gram<double>(U, q, KU0, q, n3, n3, sm.Kq, r->ws_red, r->d_ctr, s);
+    launch_gram<double>(U, q, MU0, q, n3, n3, sm.Mq, r->ws_red, r->d_ctr, s);
+    launch_small_geig(sm.Kq, sm.Mq, q, sm.lam, sm.Q, sm.info, s);
+    launch_ritz<double>(U, q, sm.Q, q, U2, q, n3, n3, s);
+    launch_ritz<double>(KU0, q, sm.Q, q, KU1, n_want, n3, n3, s);
+    launch_ritz<double>(MU0, q, sm.Q, q, MU1, n_want, n3, n3, s);
+    std::swap(w.v[3], w.v[4]);
+    U = (cplx<double>*)w.v[3].p;
+    KU = KU1;
+    MU = MU1;
+  } else {
+    BW_HIP(hipMemcpyAsync(sm.lam, lam.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  launch_lincomb<double>(KU, MU, sm.lam, R, n_want, n3, n3, s);
+  apply_M_blk<double>(r, R, Z, n_want, true, cnt, s);
+  launch_dots<double>(R, Z, n_want, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
+  std::vector<double2> rn(n_want);
+  int info = 0;
+  if (do_rr) {
+    BW_HIP(hipMemcpyAsync(lam.data(), sm.lam, q * sizeof(double), hipMemcpyDeviceToHost, s));
+    BW_HIP(hipMemcpyAsync(&info, sm.info, sizeof(int), hipMemcpyDeviceToHost, s));
+  }
+  BW_HIP(hipMemcpyAsync(rn.data(), sm.dots, n_want * sizeof(double2), hipMemcpyDeviceToHost, s));
+  BW_HIP(hipStreamSynchronize(s));
+  BW_REQUIRE(info == 0, BW_EINVAL, "Rayleigh-Ritz Gram matrix not positive definite");
+  bound.assign(n_want, 0.0);
+  for (int p = 0; p < n_want; ++p) {
+    const double res = std::sqrt(std::max(rn[p].x, 0.0));  // ||r||_{M^-1}
+    double gap = INFINITY;
+    for (int j = 0; j < q; ++j)
+      if (j != p) gap = std::min(gap, std::fabs(lam[j] - lam[p]));
+    double dl = res;
+    if (gap > 2 * res) dl = std::min(res, res * res / (gap - res));
+    bound[p] = lam[p] > 0 ? 0.5 * dl / lam[p] : dl;
+  }
+}
+
+template <typename T>
+static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigOpts& o, bool& have_start,
+                       std::vector<double>& lam_prev, Counters& cnt, hipStream_t s) {
+  const Geom& g = r->g;
+  const long n3 = g.nvox * 3;
+  Workspace<T>& w = ws<T>(r);
+  Small sm = small_bufs(r);
+  KOut out;
+  std::vector<double> ks((size_t)q * 3);
+  for (int v = 0; v < q; ++v)
+    for (int a = 0; a < 3; ++a) ks[3 * v + a] = k[a];
+  QTable qt = make_qtable(r, ks.data(), q);
+  const double* dq = upload_qtable(r, qt, r->ws_q2, s);
+  out.jstar = qt.null_index[0];
+  out.n_want = nmodes - (out.jstar >= 0 ? 3 : 0);
+  const int nw = out.n_want;
+  BW_REQUIRE(nw >= 0 && nw < q, BW_EINVAL, "block must exceed the number of wanted modes");
+  cplx<T>* U = w.vec(3, (size_t)q * n3);
+  cplx<T>* Ub = w.vec(4, (size_t)q * n3);
+  cplx<T>* V = w.vec(5, (size_t)q * n3);
+  cplx<T>* MUb = w.vec(6, (size_t)q * n3);
+  cplx<T>* KU = w.vec(7, (size_t)q * n3);
+  cplx<T>* MU = w.vec(8, (size_t)q * n3);
+  cplx<T>* R = w.vec(9, (size_t)q * n3);
+  cplx<T>* MN = w.vec(10, (size_t)3 * n3);
+  if (out.jstar >= 0) rigid_MN<T>(r, out.jstar, R, MN, sm, cnt, s);
+  if (!have_start) {
+    std::vector<long> vox;
+    std::vector<double> pol;
+    reference_start(r, qt, q, vox, pol);
+    BW_HIP(hipMemcpyAsync(sm.vox, vox.data(), q * sizeof(long), hipMemcpyHostToDevice, s));
+    BW_HIP(hipMemcpyAsync(sm.pol, pol.data(), 3 * q * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_planewaves<T>(U, q, g.nvox, sm.vox, sm.pol, s);
+    BW_HIP(hipStreamSynchronize(s));
+    lam_prev.clear();
+  }
+  const bool fp32 = sizeof(T) == 4;
+  const double tol = fp32 ? std::max(o.tol_eig, 5e-6) : o.tol_eig;
+  const double tol_lin = fp32 ? std::max(o.tol_lin, 2e-6) : o.tol_lin;
+  std::vector<double> lam(q), lam_old, inv(q);
+  bool conv = false;
+  int it = 0;
+  for (; it < o.maxit_outer; ++it) {
+    apply_M_blk<T>(r, U, V, q, false, cnt, s);  // v_p = M U_p
+    if (out.jstar >= 0) launch_deflate<T>(U, V, MN, q, g.nvox, out.jstar, sm.coef, s);
+    const bool warm = (int)lam_prev.size() == q;
+    if (warm) {
+      for (int p = 0; p < q; ++p) inv[p] = lam_prev[p] > 0 ? 1.0 / lam_prev[p] : 0.0;
+      BW_HIP(hipMemcpyAsync(sm.sc, inv.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_scale_cols<T>(U, sm.sc, Ub, q, n3, n3, s);  // x0 = U / lambda
+    } else {
+      BW_HIP(hipMemsetAsync(Ub, 0, (size_t)q * n3 * sizeof(cplx<T>), s));
+    }
+    PcgResult pr = pcg_run<T>(r, dq, qt, V, Ub, q, tol_lin, o.maxit_lin, !warm, s);  // Ubar = K^-1 v
+    cnt.pcg_iters += pr.total_iters;
+    cnt.block_iters += pr.block_iters;
+    cnt.kap += pr.total_iters + 2 * q;
+    apply_M_blk<T>(r, Ub, MUb, q, false, cnt, s);
+    if (out.jstar >= 0) launch_deflate<T>(Ub, MUb, MN, q, g.nvox, out.jstar, sm.coef, s);
+    launch_gram<T>(Ub, q, V, q, n3, n3, sm.Kq, r->ws_red, r->d_ctr, s);    // Kq = Ubar^H Kn
+    launch_gram<T>(Ub, q, MUb, q, n3, n3, sm.Mq, r->ws_red, r->d_ctr, s);  // Mq = Ubar^H Mn
+    launch_small_geig(sm.Kq, sm.Mq, q, sm.lam, sm.Q, sm.info, s);
+    launch_ritz<T>(Ub, q, sm.Q, q, U, q, n3, n3, s);                       // U = Ubar Q
+    launch_ritz<T>(MUb, q, sm.Q, q, MU, nw, n3, n3, s);                    // M U (first n)
+    apply_K_blk<T>(r, dq, U, KU, nw, cnt, s);
+    launch_lincomb<T>(KU, MU, sm.lam, R, nw, n3, n3, s);
+    launch_dots<T>(R, R, nw, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
+    launch_dots<T>(MU, MU, nw, n3, n3, sm.dots + 128, r->ws_red2, r->d_ctr + 320, s);
+    std::vector<double2> rr(nw), mm(nw);
+    int info = 0;
+    BW_HIP(hipMemcpyAsync(lam.data(), sm.lam, q * sizeof(double), hipMemcpyDeviceToHost, s));
+    BW_HIP(hipMemcpyAsync(&info, sm.info, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (nw > 0) {
+      BW_HIP(hipMemcpyAsync(rr.data(), sm.dots, nw * sizeof(double2), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipMemcpyAsync(mm.data(), sm.dots + 128, nw * sizeof(double2), hipMemcpyDeviceToHost, s));
+    }
+    BW_HIP(hipStreamSynchronize(s));
+    BW_REQUIRE(info == 0, BW_EINVAL, "subspace Gram matrix lost positive definiteness (block rank deficient)");
+    double err1 = INFINITY, err2 = 0;
+    if (!lam_old.empty()) {
+      double num = 0, den = 0;
+      for (int p = 0; p < nw; ++p) {
+        num += (lam[p] - lam_old[p]) * (lam[p] - lam_old[p]);
+        den += lam_old[p] * lam_old[p];
+      }
+      err1 = den > 0 ? std::sqrt(num / den) : 0.0;
+    }
+    for (int p = 0; p < nw; ++p)
+      err2 = std::max(err2, std::sqrt(std::max(rr[p].x, 0.0)) / (lam[p] * std::sqrt(std::max(mm[p].x, 1e-300))));
+    lam_old = lam;
+    lam_prev = lam;
+    have_start = true;
+    cnt.outer += 1;
+    if (nw == 0 || (err1 <= tol && err2 <= 10.0 * tol)) {
+      conv = true;
+      ++it;
+      break;
+    }
+  }
+  out.outer = it;
+  out.converged = conv;
+  out.lam.assign(lam.begin(), lam.begin() + nw);
+  // error bounds in FP64 (and, for FP32 vectors, an FP64 Rayleigh-Ritz first)
+  if (nw > 0) {
+    std::vector<double> lam64, bnd;
+    if (fp32) {
+      Workspace<double>& w64 = ws<double>(r);
+      cplx<double>* U64 = w64.vec(3, (size_t)q * n3);
+      launch_convert<float, double>((const cplx<float>*)U, U64, (size_t)q * n3, s);
+      rr64_bounds(r, dq, U64, q, nw, lam64, bnd, true, nullptr, nullptr, cnt, s);
+      // carry the refined block back to the FP32 warm start
+      launch_convert<double, float>(U64, (cplx<float>*)U, (size_t)q * n3, s);
+      lam_prev = lam64;
+    } else {
+      lam64 = lam;
+      cplx<double>* Ud = (cplx<double>*)U;
+      rr64_bounds(r, dq, Ud, q, nw, lam64, bnd, false, (const cplx<double>*)KU, (const cplx<double>*)MU, cnt, s);
+    }
+    out.lam.assign(lam64.begin(), lam64.begin() + nw);
+    out.bound = bnd;
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// modes output (SI M-normalization: U_SI = U' / sqrt(rho_bar))
+// ---------------------------------------------------------------------------
+template <typename T>
+static void write_modes(bw_rve* r, const KOut& ko, int nmodes, void* modes, int kidx, hipStream_t s) {
+  if (!modes) return;
+  const long n3 = r->g.nvox * 3;
+  cplx<T>* dst = (cplx<T>*)modes + (size_t)kidx * nmodes * n3;
+  Small sm = small_bufs(r);
+  int off = 0;
+  const double a = 1.0 / std::sqrt(r->rho_bar);
+  std::vector<long> vox = {ko.jstar, ko.jstar, ko.jstar};
+  std::vector<double> pol = {a, 0, 0, 0, a, 0, 0, 0, a};
+  std::vector<double> sc(std::max(ko.n_want, 1), a);
+  if (ko.jstar >= 0) {
+    BW_HIP(hipMemcpyAsync(sm.vox, vox.data(), 3 * sizeof(long), hipMemcpyHostToDevice, s));
+    BW_HIP(hipMemcpyAsync(sm.pol, pol.data(), 9 * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_planewaves<T>(dst, 3, r->g.nvox, sm.vox, sm.pol, s);
+    off = 3;
+  }
+  if (ko.n_want > 0) {
+    // the FP64 Ritz block (refined) lives in the FP64 workspace slot 3 for both paths
+    const cplx<double>* U = (const cplx<double>*)ws<double>(r).v[3].p;
+    BW_HIP(hipMemcpyAsync(sm.sc, sc.data(), ko.n_want * sizeof(double), hipMemcpyHostToDevice, s));
+    if (sizeof(T) == 8) {
+      launch_scale_cols<double>(U, sm.sc, (cplx<double>*)(dst + (size_t)off * n3), ko.n_want, n3, n3, s);
+    } else {
+      cplx<double>* tmp = ws<double>(r).vec(4, (size_t)ko.n_want * n3);
+      launch_scale_cols<double>(U, sm.sc, tmp, ko.n_want, n3, n3, s);
+      launch_convert<double, float>(tmp, (cplx<float>*)(dst + (size_t)off * n3), (size_t)ko.n_want * n3, s);
+    }
+  }
+  BW_HIP(hipStreamSynchronize(s));
+}
+
+template <typename T>
+static int lowest_modes_impl(bw_rve* r, const double* k_list, int nk, int nmodes, const EigOpts& o, double* omega,
+                             double* err, void* modes, Counters& cnt, hipStream_t s) {
+  const int q = o.block;
+  bool have_start = false;
+  std::vector<double> lam_prev;
+  const double lscale = r->Cref / (r->rho_bar * r->ell * r->ell);
+  int status = BW_OK;
+  for (int ik = 0; ik < nk; ++ik) {
+    if (!o.warm) have_start = false;
+    KOut ko = subspace_k<T>(r, k_list + 3 * ik, nmodes, q, o, have_start, lam_prev, cnt, s);
+    if (!ko.converged) status = BW_ENOTCONV;
+    int off = 0;
+    if (ko.jstar >= 0) {
+      for (int i = 0; i < 3; ++i) {
+        omega[ik * nmodes + i] = 0.0;
+        if (err) err[ik * nmodes + i] = 0.0;
+      }
+      off = 3;
+    }
+    for (int p = 0; p < ko.n_want; ++p) {
+      omega[ik * nmodes + off + p] = std::sqrt(std::max(ko.lam[p], 0.0) * lscale);
+      if (err) err[ik * nmodes + off + p] = ko.bound[p];
+    }
+    write_modes<T>(r, ko, nmodes, modes, ik, s);
+  }
+  return status;
+}
+
+}  // namespace bw
+
+using namespace bw;
+
+extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int32_t nmodes, const bw_eig_opts* opts,
+                               double* omega, double* err, void* modes, bw_stats* stats, void* stream) {
+  try {
+    BW_REQUIRE(r && k_list && omega, BW_EINVAL, "null argument");
+    BW_REQUIRE(nk >= 0, BW_EINVAL, "nk < 0");
+    BW_REQUIRE(nmodes >= 1, BW_EINVAL, "nmodes must be >= 1");
+    BW_REQUIRE((long)nmodes <= 3 * r->g.nvox, BW_EINVAL, "more modes than degrees of freedom");
+    EigOpts o{};
+    if (opts) {
+      o.method = opts->method;
+      o.block = opts->block;
+      o.ncv = opts->ncv;
+      o.maxit_outer = opts->maxit_outer;
+      o.maxit_lin = opts->maxit_lin;
+      o.warm = opts->warm_start;
+      o.tol_eig = opts->tol_eig;
+      o.tol_lin = opts->tol_lin;
+    } else {
+      o.warm = 1;
+    }
+    BW_REQUIRE(o.method == BW_SUBSPACE || o.method == BW_LANCZOS, BW_EINVAL, "unknown method");
+    if (o.block <= 0) o.block = std::min(2 * nmodes, nmodes + 8);
+    if (o.maxit_outer <= 0) o.maxit_outer = 200;
+    if (o.maxit_lin <= 0) o.maxit_lin = 20000;
+    if (o.tol_eig <= 0) o.tol_eig = 1e-10;
+    if (o.tol_lin <= 0) o.tol_lin = r->precision == BW_FP64 ? 1e-10 : 1e-6;
+    BW_REQUIRE(o.block > nmodes && o.block <= GRAM_QMAX, BW_EINVAL, "block must satisfy nmodes < block <= 32");
+    BW_REQUIRE((long)o.block <= 3 * r->g.nvox, BW_EINVAL, "block larger than the number of degrees of freedom");
+    if (o.method == BW_LANCZOS) {
+      set_error("bw_lowest_modes: the Lanczos driver is not available in this build");
+      return BW_EUNSUPPORTED;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    r->ws_red.get(16u << 20);
+    r->ws_red2.get(16u << 20);
+    Counters cnt;
+    auto t0 = std::chrono::steady_clock::now();
+    int st = r->precision == BW_FP64 ? lowest_modes_impl<double>(r, k_list, nk, nmodes, o, omega, err, modes, cnt, s)
+                                     : lowest_modes_impl<float>(r, k_list, nk, nmodes, o, omega, err, modes, cnt, s);
+    BW_HIP(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    if (stats) {
+      stats->pcg_iterations = cnt.pcg_iters;
+      stats->block_iterations = cnt.block_iters;
+      stats->outer_iterations = cnt.outer;
+      stats->k_applies = cnt.kap;
+      stats->m_applies = cnt.map;
+      stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+    }
+    if (st == BW_ENOTCONV) set_error("bw_lowest_modes: some k hit maxit_outer; see the error bounds");
+    return st;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal: ") + e.what());
+    return BW_EINVAL;
+  }
 }

@@ -1,0 +1,573 @@
+// Block kernels of the eigen-solvers (declarations in bw_block.h).
+#include "bw_block.h"
+#include "bw_ops_impl.h"
+
+namespace bw {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+template <typename T> __device__ __forceinline__ cplx<T> from_d2(double2 v);
+template <> __device__ __forceinline__ cplx<float> from_d2<float>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+template <> __device__ __forceinline__ cplx<double> from_d2<double>(double2 v) { return v; }
+
+// ---------------------------------------------------------------------------
+// Gram product on FP64 MFMA (v_mfma_f64_16x16x4f64).
+// Lane layout of the instruction (checked on gfx950): A[i][k] from lane
+// i + 16 k, B[k][j] from lane j + 16 k, result D[4 r + l / 16][l % 16] in
+// register r of lane l.  Re(X^H Y) = Xr^T Yr + Xi^T Yi and
+// Im(X^H Y) = Xr^T Yi - Xi^T Yr: four MFMAs per 4-row step and 16x16 block.
+// ---------------------------------------------------------------------------
+constexpr int GKC = 64;  // rows per LDS tile (16 per wave)
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram(const cplx<T>* __restrict__ X, int qx, const cplx<T>* __restrict__ Y,
+                                              int qy, long n, long vstride, long rows_per_blk,
+                                              double* __restrict__ partial, double2* __restrict__ G,
+                                              unsigned* counter) {
+  __shared__ double2 smem[2 * GRAM_QMAX * (GKC + 1)];
+  __shared__ int is_last;
+  double2* Xs = smem;
+  double2* Ys = smem + GRAM_QMAX * (GKC + 1);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long r0 = (long)blockIdx.x * rows_per_blk;
+  const long r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
+  const int qm = qx > qy ? qx : qy;
+  d4_t accr[2][2], acci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      accr[a][b] = d4_t{0, 0, 0, 0};
+      acci[a][b] = d4_t{0, 0, 0, 0};
+    }
+  for (long t0 = r0; t0 < r1; t0 += GKC) {
+    for (int idx = tid; idx < qm * GKC; idx += 256) {
+      const int p = idx / GKC, k = idx - p * GKC;
+      const long e = t0 + k;
+      const bool in = e < r1;
+      Xs[p * (GKC + 1) + k] = (p < qx && in) ? to_d2(X[(size_t)p * vstride + e]) : make_double2(0, 0);
+      Ys[p * (GKC + 1) + k] = (p < qy && in) ? to_d2(Y[(size_t)p * vstride + e]) : make_double2(0, 0);
+    }
+    for (int idx = qm * GKC + tid; idx < GRAM_QMAX * GKC; idx += 256) {
+      const int p = idx / GKC, k = idx - p * GKC;
+      Xs[p * (GKC + 1) + k] = make_double2(0, 0);
+      Ys[p * (GKC + 1) + k] = make_double2(0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int kb = wave * 16 + st * 4 + (lane >> 4);
+#pragma unroll
+      for (int bp = 0; bp < 2; ++bp) {
+        const double2 a = Xs[(bp * 16 + (lane & 15)) * (GKC + 1) + kb];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          const double2 b = Ys[(bj * 16 + (lane & 15)) * (GKC + 1) + kb];
+          accr[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accr[bp][bj], 0, 0, 0);
+          accr[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, accr[bp][bj], 0, 0, 0);
+          acci[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acci[bp][bj], 0, 0, 0);
+          acci[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.x, acci[bp][bj], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // sum the four waves' partial blocks through LDS
+  double* red = reinterpret_cast<double*>(smem);
+  const int nq = qx * qy;
+#pragma unroll
+  for (int bp = 0; bp < 2; ++bp)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = bp * 16 + 4 * r + (lane >> 4), j = bj * 16 + (lane & 15);
+        if (i < qx && j < qy) {
+          red[((size_t)wave * nq + i * qy + j) * 2] = accr[bp][bj][r];
+          red[((size_t)wave * nq + i * qy + j) * 2 + 1] = acci[bp][bj][r];
+        }
+      }
+  __syncthreads();
+  for (int t = tid; t < 2 * nq; t += 256) {
+    const double v = red[t] + red[2 * nq + t] + red[4 * nq + t] + red[6 * nq + t];
+    __hip_atomic_store(&partial[(size_t)blockIdx.x * 2 * nq + t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  for (int t = tid; t < 2 * nq; t += 256) {
+    double acc = 0;
+    for (unsigned b = 0; b < gridDim.x; ++b) acc += coherent_load(&partial[(size_t)b * 2 * nq + t]);
+    reinterpret_cast<double*>(G)[t] = acc;
+  }
+  if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+void launch_gram(const cplx<T>* X, int qx, const cplx<T>* Y, int qy, long n, long vstride, double2* G,
+                 DevBuf& scratch, unsigned* counter, hipStream_t s) {
+  BW_REQUIRE(qx >= 1 && qy >= 1 && qx <= GRAM_QMAX && qy <= GRAM_QMAX, BW_EINVAL, "Gram block exceeds 32 vectors");
+  long nblk = (n + 4 * GKC - 1) / (4 * GKC);
+  if (nblk > 1024) nblk = 1024;
+  if (nblk < 1) nblk = 1;
+  long rows = (n + nblk - 1) / nblk;
+  rows = (rows + GKC - 1) / GKC * GKC;
+  nblk = (n + rows - 1) / rows;
+  const size_t part_bytes = (size_t)nblk * 2 * qx * qy * sizeof(double);
+  char* base = (char*)scratch.get(part_bytes);
+  hipLaunchKernelGGL((k_gram<T>), dim3((unsigned)nblk), dim3(256), 0, s, X, qx, Y, qy, n, vstride, rows,
+                     (double*)base, G, counter);
+}
+
+// ---------------------------------------------------------------------------
+// Ritz update Y_j = sum_p X_p Q[p][j]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_ritz(const cplx<T>* __restrict__ X, int q, const double2* __restrict__ Q,
+                                              int ldq, cplx<T>* __restrict__ Y, int qout, long n, long vstride) {
+  __shared__ double2 Qs[GEIG_QMAX * GRAM_QMAX];
+  for (int idx = threadIdx.x; idx < q * qout; idx += 256) {
+    const int p = idx / qout, j = idx - p * qout;
+    Qs[idx] = Q[(size_t)p * ldq + j];
+  }
+  __syncthreads();
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+    double2 acc[GRAM_QMAX];
+#pragma unroll
+    for (int j = 0; j < GRAM_QMAX; ++j) acc[j] = make_double2(0, 0);
+    for (int p = 0; p < q; ++p) {
+      const double2 x = to_d2(X[(size_t)p * vstride + e]);
+#pragma unroll
+      for (int j = 0; j < GRAM_QMAX; ++j) {
+        if (j < qout) {
+          const double2 c = Qs[p * qout + j];
+          acc[j].x += x.x * c.x - x.y * c.y;
+          acc[j].y += x.x * c.y + x.y * c.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < GRAM_QMAX; ++j)
+      if (j < qout) Y[(size_t)j * vstride + e] = from_d2<T>(acc[j]);
+  }
+}
+
+template <typename T>
+void launch_ritz(const cplx<T>* X, int q, const double2* Q, int ldq, cplx<T>* Y, int qout, long n, long vstride,
+                 hipStream_t s) {
+  BW_REQUIRE(q <= GEIG_QMAX && qout <= GRAM_QMAX, BW_EINVAL, "Ritz block too large");
+  long nb = (n + 255) / 256;
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL((k_ritz<T>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y, qout, n, vstride);
+}
+
+// ---------------------------------------------------------------------------
+// batched inner products
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dots(const cplx<T>* __restrict__ X, const cplx<T>* __restrict__ Y, long n,
+                                             long vstride, int bpv, double* partial, double2* out, unsigned* counters,
+                                             int maxb) {
+  __shared__ double sh[NT / 64];
+  const int p = blockIdx.x / bpv;
+  const int b = blockIdx.x - p * bpv;
+  double sr = 0, si = 0;
+  for (long e = (long)b * NT + threadIdx.x; e < n; e += (long)bpv * NT) {
+    const double2 x = to_d2(X[(size_t)p * vstride + e]);
+    const double2 y = to_d2(Y[(size_t)p * vstride + e]);
+    sr += x.x * y.x + x.y * y.y;
+    si += x.x * y.y - x.y * y.x;
+  }
+  double vals[2] = {sr, si}, tot[2];
+  if (reduce_partials<2>(vals, tot, partial, counters, p, b, bpv, maxb, sh))
+    if (threadIdx.x == 0) out[p] = make_double2(tot[0], tot[1]);
+}
+
+template <typename T>
+void launch_dots(const cplx<T>* X, const cplx<T>* Y, int nv, long n, long vstride, double2* out, DevBuf& scratch,
+                 unsigned* counters, hipStream_t s) {
+  BW_REQUIRE(nv <= 256, BW_EINVAL, "too many vectors for one dot-product launch");
+  const int bpv = pw_blocks(n);
+  const size_t part_bytes = (size_t)nv * bpv * 2 * sizeof(double);
+  char* base = (char*)scratch.get(part_bytes);
+  hipLaunchKernelGGL((k_dots<T>), dim3(nv * bpv), dim3(NT), 0, s, X, Y, n, vstride, bpv, (double*)base, out,
+                     counters, bpv);
+}
+
+// ---------------------------------------------------------------------------
+// vector utilities
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_lincomb(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ B, const double* __restrict__ lam,
+                          cplx<T>* __restrict__ R, long n, long vstride) {
+  const int p = blockIdx.y;
+  const double l = lam[p];
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const double2 a = to_d2(A[(size_t)p * vstride + e]), b = to_d2(B[(size_t)p * vstride + e]);
+    R[(size_t)p * vstride + e] = from_d2<T>(make_double2(a.x - l * b.x, a.y - l * b.y));
+  }
+}
+
+template <typename T>
+void launch_lincomb(const cplx<T>* A, const cplx<T>* B, const double* lam, cplx<T>* R, int nv, long n, long vstride,
+                    hipStream_t s) {
+  if (nv <= 0) return;
+  long nb = (n + 255) / 256;
+  if (nb > 512) nb = 512;
+  hipLaunchKernelGGL((k_lincomb<T>), dim3((unsigned)nb, nv), dim3(256), 0, s, A, B, lam, R, n, vstride);
+}
+
+template <typename T>
+__global__ void k_scale_cols(const cplx<T>* __restrict__ X, const double* __restrict__ sc, cplx<T>* __restrict__ Y,
+                             long n, long vstride) {
+  const int p = blockIdx.y;
+  const double f = sc[p];
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const double2 a = to_d2(X[(size_t)p * vstride + e]);
+    Y[(size_t)p * vstride + e] = from_d2<T>(make_double2(a.x * f, a.y * f));
+  }
+}
+
+template <typename T>
+void launch_scale_cols(const cplx<T>* X, const double* sc, cplx<T>* Y, int nv, long n, long vstride, hipStream_t s) {
+  if (nv <= 0) return;
+  long nb = (n + 255) / 256;
+  if (nb > 512) nb = 512;
+  hipLaunchKernelGGL((k_scale_cols<T>), dim3((unsigned)nb, nv), dim3(256), 0, s, X, sc, Y, n, vstride);
+}
+
+template <typename TS, typename TD>
+__global__ void k_convert(const cplx<TS>* __restrict__ src, cplx<TD>* __restrict__ dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = from_d2<TD>(to_d2(src[i]));
+}
+
+template <typename TS, typename TD>
+void launch_convert(const cplx<TS>* src, cplx<TD>* dst, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  size_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL((k_convert<TS, TD>), dim3((unsigned)nb), dim3(256), 0, s, src, dst, n);
+}
+
+// Gamma deflation, step 1: a_c = MX_p(c, j*) / MN_c(c, j*), X_p(c, j*) -= a_c
+template <typename T>
+__global__ void k_deflate_coef(cplx<T>* X, const cplx<T>* MX, const cplx<T>* MN, int nv, long nvox, long jstar,
+                               double2* coef) {
+  const int t = threadIdx.x;
+  if (t >= nv * 3) return;
+  const int p = t / 3, c = t - 3 * p;
+  const double2 m = to_d2(MX[((size_t)p * 3 + c) * nvox + jstar]);
+  const double2 d = to_d2(MN[((size_t)c * 3 + c) * nvox + jstar]);
+  const double den = d.x * d.x + d.y * d.y;
+  const double2 a = make_double2((m.x * d.x + m.y * d.y) / den, (m.y * d.x - m.x * d.y) / den);
+  coef[t] = a;
+  const double2 x = to_d2(X[((size_t)p * 3 + c) * nvox + jstar]);
+  X[((size_t)p * 3 + c) * nvox + jstar] = from_d2<T>(make_double2(x.x - a.x, x.y - a.y));
+}
+
+// step 2: MX_p(c, :) -= a_c MN_c(c, :)
+template <typename T>
+__global__ void k_deflate_apply(cplx<T>* MX, const cplx<T>* MN, long nvox, const double2* coef) {
+  const int p = blockIdx.y / 3, c = blockIdx.y - 3 * (blockIdx.y / 3);
+  const double2 a = coef[p * 3 + c];
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nvox; e += (long)gridDim.x * blockDim.x) {
+    const double2 mn = to_d2(MN[((size_t)c * 3 + c) * nvox + e]);
+    const double2 m = to_d2(MX[((size_t)p * 3 + c) * nvox + e]);
+    MX[((size_t)p * 3 + c) * nvox + e] =
+        from_d2<T>(make_double2(m.x - (a.x * mn.x - a.y * mn.y), m.y - (a.x * mn.y + a.y * mn.x)));
+  }
+}
+
+template <typename T>
+void launch_deflate(cplx<T>* X, cplx<T>* MX, const cplx<T>* MN, int nv, long nvox, long jstar, double2* coef,
+                    hipStream_t s) {
+  BW_REQUIRE(nv * 3 <= 256, BW_EINVAL, "deflation block too large");
+  hipLaunchKernelGGL((k_deflate_coef<T>), dim3(1), dim3(256), 0, s, X, (const cplx<T>*)MX, MN, nv, nvox, jstar, coef);
+  long nb = (nvox + 255) / 256;
+  if (nb > 256) nb = 256;
+  hipLaunchKernelGGL((k_deflate_apply<T>), dim3((unsigned)nb, nv * 3), dim3(256), 0, s, MX, MN, nvox,
+                     (const double2*)coef);
+}
+
+template <typename T>
+__global__ void k_planewaves(cplx<T>* U, int nv, long nvox, const long* vox, const double* pol) {
+  const int t = threadIdx.x;
+  if (t >= nv * 3) return;
+  const int p = t / 3, c = t - 3 * p;
+  U[((size_t)p * 3 + c) * nvox + vox[p]] = from_d2<T>(make_double2(pol[t], 0.0));
+}
+
+template <typename T>
+void launch_planewaves(cplx<T>* U, int nv, long nvox, const long* vox, const double* pol, hipStream_t s) {
+  BW_REQUIRE(nv * 3 <= 256, BW_EINVAL, "too many start vectors");
+  BW_HIP(hipMemsetAsync(U, 0, (size_t)nv * 3 * nvox * sizeof(cplx<T>), s));
+  hipLaunchKernelGGL((k_planewaves<T>), dim3(1), dim3(256), 0, s, U, nv, nvox, vox, pol);
+}
+
+// ---------------------------------------------------------------------------
+// small generalized Hermitian eigenproblem, one workgroup of 64 threads:
+// diagonal scaling, Cholesky of Mq, A = L^-1 Kq L^-H, cyclic Jacobi with the
+// round-robin ordering (q/2 disjoint rotations per step), Q = D L^-H Z.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cm(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmc(double2 a, double2 b) {  // a * conj(b)
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+__global__ __launch_bounds__(64) void k_small_geig(const double2* __restrict__ Kq, const double2* __restrict__ Mq,
+                                                   int q, double* lam, double2* Qout, int* info) {
+  constexpr int QE = GEIG_QMAX;
+  __shared__ double2 A[QE * QE];
+  __shared__ double2 Z[QE * QE];
+  __shared__ double2 Lm[QE * QE];
+  __shared__ double dsc[QE];
+  __shared__ double rc[QE / 2], rs[QE / 2];
+  __shared__ double2 rph[QE / 2];
+  __shared__ int rp[QE / 2], rq[QE / 2], perm[QE];
+  __shared__ int flag;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    flag = 0;
+    info[0] = 0;
+  }
+  for (int i = tid; i < q; i += 64) dsc[i] = 1.0 / sqrt(Mq[i * q + i].x);
+  __syncthreads();
+  for (int idx = tid; idx < q * q; idx += 64) {
+    const int i = idx / q, j = idx - i * q;
+    const double s = dsc[i] * dsc[j];
+    const double2 k1 = Kq[i * q + j], k2 = Kq[j * q + i];
+    const double2 m1 = Mq[i * q + j], m2 = Mq[j * q + i];
+    A[idx] = make_double2(0.5 * (k1.x + k2.x) * s, 0.5 * (k1.y - k2.y) * s);  // Hermitian part
+    Lm[idx] = make_double2(0.5 * (m1.x + m2.x) * s, 0.5 * (m1.y - m2.y) * s);
+  }
+  __syncthreads();
+  // Cholesky Lm = L L^H (lower), in place
+  for (int j = 0; j < q; ++j) {
+    if (tid == 0) {
+      double d = Lm[j * q + j].x;
+      for (int k = 0; k < j; ++k) d -= Lm[j * q + k].x * Lm[j * q + k].x + Lm[j * q + k].y * Lm[j * q + k].y;
+      if (!(d > 0)) {
+        flag = 1;
+        d = 1e-300;
+      }
+      Lm[j * q + j] = make_double2(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < q; i += 64) {
+      double2 v = Lm[i * q + j];
+      for (int k = 0; k < j; ++k) {
+        const double2 t = cmc(Lm[i * q + k], Lm[j * q + k]);
+        v.x -= t.x;
+        v.y -= t.y;
+      }
+      const double inv = 1.0 / Lm[j * q + j].x;
+      Lm[i * q + j] = make_double2(v.x * inv, v.y * inv);
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && flag) info[0] = 1;
+  // B = L^-1 A (column c per thread), kept in Z
+  for (int c = tid; c < q; c += 64) {
+    for (int i = 0; i < q; ++i) {
+      double2 v = A[i * q + c];
+      for (int k = 0; k < i; ++k) {
+        const double2 t = cm(Lm[i * q + k], Z[k * q + c]);
+        v.x -= t.x;
+        v.y -= t.y;
+      }
+      const double inv = 1.0 / Lm[i * q + i].x;
+      Z[i * q + c] = make_double2(v.x * inv, v.y * inv);
+    }
+  }
+  __syncthreads();
+  // A = B L^-H: column c of C = L^-1 B^H gives row c of A = C^H
+  for (int c = tid; c < q; c += 64) {
+    for (int i = 0; i < q; ++i) {
+      const double2 b = Z[c * q + i];
+      double2 v = make_double2(b.x, -b.y);
+      for (int k = 0; k < i; ++k) {
+        const double2 ck = A[c * q + k];  // A[c][k] holds conj(C[k][c])
+        const double2 t = cm(Lm[i * q + k], make_double2(ck.x, -ck.y));
+        v.x -= t.x;
+        v.y -= t.y;
+      }
+      const double inv = 1.0 / Lm[i * q + i].x;
+      A[c * q + i] = make_double2(v.x * inv, -v.y * inv);
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < q * q; idx += 64) {
+    const int i = idx / q, j = idx - i * q;
+    Z[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < q * q; idx += 64) {  // re-Hermitize
+    const int i = idx / q, j = idx - i * q;
+    if (i < j) {
+      const double2 a = A[i * q + j], b = A[j * q + i];
+      const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+      A[i * q + j] = h;
+      A[j * q + i] = make_double2(h.x, -h.y);
+    } else if (i == j) {
+      A[idx].y = 0.0;
+    }
+  }
+  __syncthreads();
+  const int m = (q + 1) & ~1;
+  const int npair = m / 2;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) {
+      double off = 0, dia = 0;
+      for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) {
+          const double v = A[i * q + j].x * A[i * q + j].x + A[i * q + j].y * A[i * q + j].y;
+          if (i == j)
+            dia += v;
+          else
+            off += v;
+        }
+      flag = off <= 1e-30 * dia ? 1 : 0;
+    }
+    __syncthreads();
+    if (flag) break;
+    for (int step = 0; step < m - 1; ++step) {
+      if (tid < npair) {
+        int a, b;
+        if (tid == 0) {
+          a = m - 1;
+          b = step;
+        } else {
+          a = (step + tid) % (m - 1);
+          b = (step - tid + (m - 1)) % (m - 1);
+        }
+        int p = a < b ? a : b, qq = a < b ? b : a;
+        double cs = 1.0, sn = 0.0;
+        double2 ph = make_double2(1.0, 0.0);
+        if (qq < q) {
+          const double2 c = A[p * q + qq];
+          const double ac = sqrt(c.x * c.x + c.y * c.y);
+          const double app = A[p * q + p].x, aqq = A[qq * q + qq].x;
+          if (ac > 1e-300 && ac > 1e-18 * (fabs(app) + fabs(aqq))) {
+            ph = make_double2(c.x / ac, c.y / ac);
+            const double tau = (aqq - app) / (2.0 * ac);
+            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            cs = 1.0 / sqrt(1.0 + t * t);
+            sn = t * cs;
+          }
+        } else {
+          qq = p;  // dummy partner: identity
+        }
+        rp[tid] = p;
+        rq[tid] = qq;
+        rc[tid] = cs;
+        rs[tid] = sn;
+        rph[tid] = ph;
+      }
+      __syncthreads();
+      // rows: A <- J^H A
+      for (int w = tid; w < npair * q; w += 64) {
+        const int i = w / q, j = w - i * q;
+        const int p = rp[i], qq = rq[i];
+        if (p == qq || rs[i] == 0.0) continue;
+        const double cs = rc[i], sn = rs[i];
+        const double2 ph = rph[i];
+        const double2 ap = A[p * q + j], aq = A[qq * q + j];
+        const double2 e = cm(ph, aq);  // e^{i phi} a_q
+        A[p * q + j] = make_double2(cs * ap.x - sn * e.x, cs * ap.y - sn * e.y);
+        A[qq * q + j] = make_double2(sn * ap.x + cs * e.x, sn * ap.y + cs * e.y);
+      }
+      __syncthreads();
+      // columns: A <- A J, Z <- Z J
+      for (int w = tid; w < npair * q; w += 64) {
+        const int i = w / q, j = w - i * q;
+        const int p = rp[i], qq = rq[i];
+        if (p == qq || rs[i] == 0.0) continue;
+        const double cs = rc[i], sn = rs[i];
+        const double2 phc = make_double2(rph[i].x, -rph[i].y);
+        {
+          const double2 ap = A[j * q + p], aq = A[j * q + qq];
+          const double2 e = cm(phc, aq);
+          A[j * q + p] = make_double2(cs * ap.x - sn * e.x, cs * ap.y - sn * e.y);
+          A[j * q + qq] = make_double2(sn * ap.x + cs * e.x, sn * ap.y + cs * e.y);
+        }
+        {
+          const double2 zp = Z[j * q + p], zq = Z[j * q + qq];
+          const double2 e = cm(phc, zq);
+          Z[j * q + p] = make_double2(cs * zp.x - sn * e.x, cs * zp.y - sn * e.y);
+          Z[j * q + qq] = make_double2(sn * zp.x + cs * e.x, sn * zp.y + cs * e.y);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // sort eigenvalues ascending
+  if (tid == 0) {
+    for (int i = 0; i < q; ++i) perm[i] = i;
+    for (int i = 0; i < q; ++i) {
+      int best = i;
+      for (int j = i + 1; j < q; ++j)
+        if (A[perm[j] * q + perm[j]].x < A[perm[best] * q + perm[best]].x) best = j;
+      const int t = perm[i];
+      perm[i] = perm[best];
+      perm[best] = t;
+    }
+  }
+  __syncthreads();
+  // Q = D L^-H Z (back substitution per column)
+  for (int c = tid; c < q; c += 64) {
+    const int src = perm[c];
+    lam[c] = A[src * q + src].x;
+    for (int i = q - 1; i >= 0; --i) {
+      double2 v = Z[i * q + src];
+      for (int k = i + 1; k < q; ++k) {
+        // conj(L[k][i]) * X[k]
+        const double2 l = Lm[k * q + i];
+        const double2 x = A[k * q + src];  // A column src reused as scratch for X
+        v.x -= l.x * x.x + l.y * x.y;
+        v.y -= l.x * x.y - l.y * x.x;
+      }
+      const double inv = 1.0 / Lm[i * q + i].x;
+      A[i * q + src] = make_double2(v.x * inv, v.y * inv);
+    }
+    for (int i = 0; i < q; ++i) {
+      const double2 x = A[i * q + src];
+      Qout[i * q + c] = make_double2(x.x * dsc[i], x.y * dsc[i]);
+    }
+  }
+}
+
+void launch_small_geig(const double2* Kq, const double2* Mq, int q, double* lam, double2* Q, int* info,
+                       hipStream_t s) {
+  BW_REQUIRE(q >= 1 && q <= GEIG_QMAX, BW_EINVAL, "small eigenproblem larger than 48");
+  hipLaunchKernelGGL(k_small_geig, dim3(1), dim3(64), 0, s, Kq, Mq, q, lam, Q, info);
+}
+
+#define BW_INST_BLOCK(T)                                                                                          \
+  template void launch_gram<T>(const cplx<T>*, int, const cplx<T>*, int, long, long, double2*, DevBuf&,            \
+                               unsigned*, hipStream_t);                                                                      \
+  template void launch_ritz<T>(const cplx<T>*, int, const double2*, int, cplx<T>*, int, long, long, hipStream_t); \
+  template void launch_dots<T>(const cplx<T>*, const cplx<T>*, int, long, long, double2*, DevBuf&, unsigned*,     \
+                               hipStream_t);                                                                      \
+  template void launch_lincomb<T>(const cplx<T>*, const cplx<T>*, const double*, cplx<T>*, int, long, long,       \
+                                  hipStream_t);                                                                   \
+  template void launch_scale_cols<T>(const cplx<T>*, const double*, cplx<T>*, int, long, long, hipStream_t);      \
+  template void launch_deflate<T>(cplx<T>*, cplx<T>*, const cplx<T>*, int, long, long, double2*, hipStream_t);    \
+  template void launch_planewaves<T>(cplx<T>*, int, long, const long*, const double*, hipStream_t);
+
+BW_INST_BLOCK(double)
+BW_INST_BLOCK(float)
+template void launch_convert<float, double>(const cplx<float>*, cplx<double>*, size_t, hipStream_t);
+template void launch_convert<double, float>(const cplx<double>*, cplx<float>*, size_t, hipStream_t);
+
+}  // namespace bw

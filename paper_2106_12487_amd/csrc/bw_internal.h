@@ -120,10 +120,11 @@ struct bw_rve {
   float* d_rho32 = nullptr;
   double* d_tw64[3] = {nullptr, nullptr, nullptr};
   float* d_tw32[3] = {nullptr, nullptr, nullptr};
-  double* d_C0s = nullptr;      // 21 scaled (double)
-  float* d_C0s32 = nullptr;     // 21 scaled (float)
+  double* d_rhoinv64 = nullptr;  // 1 / rho' per grain
+  float* d_rhoinv32 = nullptr;
+  unsigned* d_ctr = nullptr;      // last-block counters (zero between launches)
   // workspaces
-  bw::DevBuf ws_q, ws_pcg, ws_misc;
+  bw::DevBuf ws_q, ws_q2, ws_pcg, ws_misc, ws_red, ws_red2;
   bw::Workspace<double> ws64;
   bw::Workspace<float> ws32;
   double qcache_k[3] = {0, 0, 0};
@@ -144,6 +145,10 @@ void launch_apply_K(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cpl
 template <typename T>
 void launch_apply_M(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, double scale,
                     cplx<T>* W, hipStream_t s);
+// y = scale * M u, or scale * M^-1 u when `inverse` (Sec. 3.3 eq. def_invM)
+template <typename T>
+void launch_apply_Minv_or_M(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, bool inverse, cplx<T>* W,
+                            hipStream_t s);
 template <typename T>
 void launch_apply_P(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<T>* y, int nvec,
                     double scale, hipStream_t s);

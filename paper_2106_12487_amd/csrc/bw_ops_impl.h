@@ -747,7 +747,8 @@ inline int pw_blocks(long nvox) {
 // ---------------------------------------------------------------------------
 // Middle passes shared by K and M: inverse axis 1, axis-0 op, forward axis 1.
 template <typename T, int OP>
-void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* active, hipStream_t s) {
+void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* active, hipStream_t s,
+                   const T* tab_override = nullptr) {
   const Geom& g = r->g;
   constexpr int NC = OP == 0 ? 6 : 3;
   const long n12 = (long)g.n1 * g.n2;
@@ -760,7 +761,7 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
   }
   with_n(g.n0, [&](auto N0) {
     ColTile ct = axis0_tile<T>(N0, n12);
-    const T* tab = OP == 0 ? ctab<T>(r) : rhotab<T>(r);
+    const T* tab = tab_override ? tab_override : (OP == 0 ? ctab<T>(r) : rhotab<T>(r));
     hipLaunchKernelGGL((k_axis0_op<T, decltype(N0)::value, OP>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, n12,
                        g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
   });
@@ -809,9 +810,13 @@ void launch_apply_K(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cpl
   apply_K_impl<T>(r, d_qtab, u, y, nvec, scale, W, s, 0, nullptr, nullptr);
 }
 
+template <typename T> const T* rhoinvtab(const bw_rve* r);
+template <> inline const double* rhoinvtab<double>(const bw_rve* r) { return r->d_rhoinv64; }
+template <> inline const float* rhoinvtab<float>(const bw_rve* r) { return r->d_rhoinv32; }
+
 template <typename T>
-void launch_apply_M(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, double scale, cplx<T>* W,
-                    hipStream_t s) {
+void apply_M_impl(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, double scale, cplx<T>* W, hipStream_t s,
+                  const T* tab) {
   const Geom& g = r->g;
   const long rows = 3L * g.n0 * g.n1;
   with_n(g.n2, [&](auto N2) {
@@ -820,13 +825,25 @@ void launch_apply_M(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, dou
     hipLaunchKernelGGL((k_row_plain<T, n2c, true>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, W, rt, (int)rows,
                        twiddles<T>(r, 2), (const int*)nullptr);
   });
-  launch_middle<T, 1>(r, W, nvec, (T)(scale / (double)g.nvox), nullptr, s);
+  launch_middle<T, 1>(r, W, nvec, (T)(scale / (double)g.nvox), nullptr, s, tab);
   with_n(g.n2, [&](auto N2) {
     constexpr int n2c = decltype(N2)::value;
     RowTile rt = row_tile<T>(n2c, rows);
     hipLaunchKernelGGL((k_row_plain<T, n2c, false>), dim3(nvec * rt.tpv), dim3(NT), 0, s, (const cplx<T>*)W, y, rt,
                        (int)rows, twiddles<T>(r, 2), (const int*)nullptr);
   });
+}
+
+template <typename T>
+void launch_apply_M(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, double scale, cplx<T>* W,
+                    hipStream_t s) {
+  apply_M_impl<T>(r, u, y, nvec, scale, W, s, nullptr);
+}
+
+template <typename T>
+void launch_apply_Minv_or_M(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, bool inverse, cplx<T>* W,
+                            hipStream_t s) {
+  apply_M_impl<T>(r, u, y, nvec, 1.0, W, s, inverse ? rhoinvtab<T>(r) : rhotab<T>(r));
 }
 
 template <typename T>
@@ -900,6 +917,7 @@ template <typename T> void zero_voxel(cplx<T>* x, int nvec, long nvox, long vox,
   template void launch_apply_K<T>(const bw_rve*, const double*, const cplx<T>*, cplx<T>*, int, double, cplx<T>*,    \
                                   hipStream_t);                                                                    \
   template void launch_apply_M<T>(const bw_rve*, const cplx<T>*, cplx<T>*, int, double, cplx<T>*, hipStream_t);     \
+  template void launch_apply_Minv_or_M<T>(const bw_rve*, const cplx<T>*, cplx<T>*, int, bool, cplx<T>*, hipStream_t); \
   template void launch_apply_P<T>(const bw_rve*, const double*, const cplx<T>*, cplx<T>*, int, double, hipStream_t); \
   template void launch_pcg_apply<T>(const bw_rve*, const double*, const cplx<T>*, cplx<T>*, cplx<T>*, cplx<T>*,     \
                                     int, const PcgDev&, hipStream_t);                                              \

@@ -1,0 +1,112 @@
+"""GPU parity of bw_lowest_modes against the CPU oracle.
+
+Bar (relative eigenfrequency error): 1e-9 on the FP64 path, 1e-5 on the mixed
+path.  At omega = 0 (the rigid translations at Gamma) the error is measured
+against omega_ref = (2 pi / L) sqrt(C0_44 / rho_bar), the first folded
+transverse scale.  Eigenvectors are compared as cluster subspaces (principal
+angles in the M inner product), since degenerate clusters have no unique basis.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2106_12487_amd import inputs
+from oracle.operators import Operators
+from oracle import solvers
+
+pytestmark = pytest.mark.gpu
+L = 1e-3
+HERE = os.path.dirname(os.path.abspath(__file__))
+BAR = {0: 1e-9, 1: 1e-5}
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _omega_ref(rve):
+    ops = Operators(rve, [0, 0, 0])
+    return 2 * np.pi / rve.L[0] * np.sqrt(ops.C0[3, 3] / ops.rho_bar)
+
+
+def _relerr(w, w_o, wref):
+    return np.abs(w - w_o) / np.maximum(w_o, wref)
+
+
+def _subspace_angles(ops, Xo, Xg, lam, rel=1e-6):
+    """Largest principal angle (radians) over clusters of nearly equal eigenvalues."""
+    worst = 0.0
+    i = 0
+    n = len(lam)
+    floor = 1e-8 * max(abs(lam).max(), 1e-300)     # the rigid modes cluster at 0
+    while i < n:
+        j = i + 1
+        while j < n and abs(lam[j] - lam[i]) <= max(rel * abs(lam[i]), floor):
+            j += 1
+        A = Xo[i:j].reshape(j - i, -1)
+        B = Xg[i:j]
+        MB = ops.apply_M(B).reshape(j - i, -1)
+        s = np.linalg.svd(A.conj() @ MB.T, compute_uv=False)
+        worst = max(worst, float(np.arccos(np.clip(s.min(), -1, 1))))
+        i = j
+    return worst
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lowest_modes_match_dense_oracle_8cube(lib, prec):
+    torch = _torch()
+    rve = inputs.polycrystal((8, 8, 8), (L, L, L), 6, 95, 0)
+    ks = np.array([[0.0, 0.0, 0.0], [0.23, 0.11, -0.05], [1.0, 0.0, 0.0], [1.0, 1.0, 1.0]]) * np.pi / L
+    nm = 6
+    print(f"\n[case] lowest_modes 8^3 prec={prec}", flush=True)
+    R = lib.Rve.from_inputs(rve, prec)
+    modes = torch.zeros((len(ks), nm, 3, 8, 8, 8), dtype=R.complex_dtype, device="cuda")
+    w, err, code, st = lib.bw_lowest_modes(R, ks, nm, block=12, tol_eig=1e-11, tol_lin=1e-11, modes=modes)
+    assert code == 0
+    wref = _omega_ref(rve)
+    for i, k in enumerate(ks):
+        ops = Operators(rve, k)
+        lam_o, X_o = solvers.dense_modes(ops, nm)
+        w_o = solvers.lowest_modes(rve, k[None], nm, method="dense")[0]
+        e = _relerr(w[i], w_o, wref)
+        print(f"k={k * L / np.pi} max rel err {e.max():.2e} bound {err[i].max():.2e}", flush=True)
+        assert e.max() <= BAR[prec]
+        # the reported a-posteriori bounds hold (with a little rounding slack)
+        nz = w_o > 1e-6 * wref
+        assert np.all(e[nz] <= err[i][nz] * 1.5 + 1e-12)
+        Xg = modes[i].cpu().numpy().astype(np.complex128)
+        ang = _subspace_angles(ops, X_o, Xg, lam_o)
+        print(f"   max principal angle {ang:.2e}", flush=True)
+        assert ang <= (1e-6 if prec == 0 else 1e-2)
+    assert st["pcg_iterations"] > 0 and st["outer_iterations"] >= len(ks)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cu16_config_against_stored_oracle(lib, prec):
+    path = os.path.join(HERE, "golden", "cu16.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values not generated")
+    g = json.load(open(path))
+    rve = inputs.workload_rve(1, 0)
+    w_o = np.array(g["omega"])
+    ks = np.array(g["k"])[: len(w_o)]
+    print(f"\n[case] cu16 config prec={prec}", flush=True)
+    R = lib.Rve.from_inputs(rve, prec)
+    w, err, code, st = lib.bw_lowest_modes(R, ks, g["nmodes"], block=g["block"], tol_eig=1e-11, tol_lin=1e-10)
+    assert code == 0
+    e = _relerr(w, w_o, _omega_ref(rve))
+    print(f"max rel err {e.max():.2e}; stats {st}", flush=True)
+    assert e.max() <= BAR[prec]
+
+
+def test_lowest_modes_argument_errors(lib):
+    rve = inputs.polycrystal((8, 8, 8), (L, L, L), 4, 95, 1)
+    R = lib.Rve.from_inputs(rve, 0)
+    with pytest.raises(lib.BlochwaveError):
+        lib.bw_lowest_modes(R, np.zeros((1, 3)), 12, block=8)            # block <= nmodes
+    with pytest.raises(lib.BlochwaveError):
+        lib.bw_lowest_modes(R, np.zeros((1, 3)), 6, block=40)            # block > 32
