@@ -1,0 +1,189 @@
+"""Benchmark: Bloch-wave dispersion throughput on one MI355X.
+
+Workload (one "step"): the lowest 12 branches at the 40 wave vectors of the
+simple-cubic path Gamma-X-M-Gamma-R for a 64^3 periodic Voronoi polycrystal
+(64 grains, Cu cubic constants, Haar-random orientations, L = 1 mm), subspace
+block 16, every result carrying an FP64 a-posteriori bound on its relative
+omega error of at most 1e-5.  Inputs (cell, k list) are resident on the GPU
+before the timed region.
+
+Arms: "mixed" (FP32 FFTs / contraction / PCG vectors, FP64 reductions,
+Rayleigh-Ritz and eigen-residuals; the reported value) and "fp64" (the plain
+method in FP64, PCG tolerance 1e-8), run back to back on the same GPU.
+
+Prints ONE JSON line (rank 0).  Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic HBM bytes per voxel and per vector of each kernel, in words of one
+# complex number (8 B FP32 / 16 B FP64) plus the uint16 grain index where read.
+KERNEL_WORDS = {
+    "k_strain_row_pcg": (15, 0),     # read r, p; write p and 6 strain components
+    "k_strain_row": (9, 0),
+    "k_axis1_inv_pcg": (12, 0), "k_axis1_fwd_pcg": (12, 0),
+    "k_axis1_inv": (12, 0), "k_axis1_fwd": (12, 0),
+    "k_axis0_contract_pcg": (12, 2), "k_axis0_contract": (12, 2),
+    "k_row_div_pcg": (12, 0),        # read 6 stress components and p; write K p
+    "k_row_div": (9, 0),
+    "k_pcg_update": (18, 0),         # read x, r, p, Kp; write x, r
+    "k_axis1_inv_mass": (6, 0), "k_axis1_fwd_mass": (6, 0), "k_axis0_mass": (6, 2),
+    "k_row_inv_mass": (6, 0), "k_row_fwd_mass": (6, 0),
+}
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nk", type=int, default=40, help="wave vectors per step (the workload uses 40)")
+    ap.add_argument("--skip-fp64", action="store_true", help="do not run the plain FP64 arm")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+TOL_OMEGA = 5e-6   # a-posteriori bound target on the relative omega error (metric: 1e-5)
+
+
+def run_arm(bw, rve_in, ks, precision, steps, warmup, tol_lin, tol_eig, timing=False):
+    import torch
+    R = bw.Rve.from_inputs(rve_in, precision)
+    kw = dict(block=16, tol_eig=tol_eig, tol_lin=tol_lin, tol_omega=TOL_OMEGA)
+    for _ in range(warmup):
+        _, _, _, st = bw.bw_lowest_modes(R, ks, 12, **kw)
+        print(f"[bench] precision {precision} warmup: {st['seconds']:.2f} s, outer {st['outer_iterations']}, "
+              f"pcg {st['pcg_iterations']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    if timing:
+        bw.bw_timing_enable(True)
+    t0 = time.perf_counter()
+    stats = []
+    maxb = 0.0
+    for i in range(steps):
+        w, err, code, st = bw.bw_lowest_modes(R, ks, 12, **kw)
+        stats.append(st)
+        maxb = max(maxb, float(err.max()))
+        print(f"[bench] precision {precision} step {i}: {st['seconds']:.2f} s, outer {st['outer_iterations']}, "
+              f"pcg {st['pcg_iterations']}, max bound {float(err.max()):.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rep = None
+    if timing:
+        rep = bw.bw_timing_report()
+        bw.bw_timing_enable(False)
+    R.close()
+    return dict(seconds=dt, stats=stats, max_bound=maxb, omega=w, code=code, timing=rep)
+
+
+def roofline(rep, nvox, word_bytes):
+    best = max(((k, v) for k, v in rep.items() if k in KERNEL_WORDS), key=lambda kv: kv[1]["ms"])
+    name, v = best
+    words, extra = KERNEL_WORDS[name]
+    bytes_total = v["units"] * nvox * (words * word_bytes + extra)
+    per_launch = bytes_total / max(v["launches"], 1)
+    avg_s = v["ms"] / max(v["launches"], 1) / 1e3
+    achieved = per_launch / avg_s / 1e9
+    return dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None,
+                bytes_per_launch=int(per_launch), avg_launch_us=round(avg_s * 1e6, 2),
+                launches=v["launches"], bytes_per_voxel_vector=words * word_bytes + extra)
+
+
+def cpu_baseline(rve_in, ks, budget_s):
+    """Oracle PCG on the workload (one RHS at the first k != 0) for about budget_s
+    seconds, scaled by the oracle's own PCG-iteration count per k-point from its
+    full run on the same workload (tests/golden/cu64.json)."""
+    import numpy as np
+    from oracle.operators import Operators
+    from oracle import solvers
+    cores = len(os.sched_getaffinity(0))
+    ops = Operators(rve_in, ks[1])
+    rng = np.random.default_rng(0)
+    b = rng.standard_normal((3,) + rve_in.n) + 1j * rng.standard_normal((3,) + rve_in.n)
+    t0 = time.perf_counter()
+    ops.apply_K(b)
+    t_apply = time.perf_counter() - t0
+    n_it = max(3, int(budget_s / max(t_apply, 1e-3)))
+    t0 = time.perf_counter()
+    _, its, _ = solvers.pcg(ops, b, 1e-30, maxit=n_it)     # tolerance never met: exactly n_it iterations
+    dt = time.perf_counter() - t0
+    sec_per_it = dt / max(its, 1)
+    gpath = os.path.join(ROOT, "tests", "golden", "cu64.json")
+    src = "oracle full run (tests/golden/cu64.json)"
+    its_per_k = None
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        if g.get("pcg_iters"):
+            its_per_k = float(np.mean(g["pcg_iters"]))
+    if its_per_k is None:
+        return dict(value=None, unit="k-points/s", cores=cores, kind="oracle",
+                    sample=f"{its} oracle PCG iterations at 64^3 in {dt:.1f} s; no stored iteration count")
+    return dict(value=1.0 / (sec_per_it * its_per_k), unit="k-points/s", cores=cores, kind="oracle",
+                sample=(f"{its} oracle PCG iterations (1 RHS, 64^3, k index 1) in {dt:.1f} s = "
+                        f"{sec_per_it:.3f} s/iteration, times {its_per_k:.0f} PCG iterations per k-point "
+                        f"of the oracle's subspace iteration from its {src}; extrapolated"))
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2106_12487_amd import blochwave as bw
+    from paper_2106_12487_amd import inputs
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    rve_in = inputs.workload_rve(2, 0)
+    ks = inputs.workload_kpoints(2)[: a.nk]
+    nvox = int(np.prod(rve_in.n))
+    mixed = run_arm(bw, rve_in, ks, bw.BW_MIXED, a.steps, a.warmup, 1e-6, 1e-6, timing=True)
+    out = {
+        "metric": "k-points/s (12 modes, omega rel err 1e-5)",
+        "value": round(len(ks) * a.steps / mixed["seconds"], 4),
+        "unit": "k-points/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(1e3 * mixed["seconds"] / a.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "cu64_64g_gxmgr", "grid": list(rve_in.n), "grains": rve_in.n_grains,
+                   "material": "Cu cubic 168.4/121.4/75.4 GPa, Haar texture", "k_points": len(ks),
+                   "path": "G-X-M-G-R", "modes": 12, "block": 16, "method": "subspace",
+                   "precision": "FP32 FFT/contraction/PCG vectors, FP64 reductions and Rayleigh-Ritz"},
+        "max_error_bound": mixed["max_bound"],
+        "solver_stats": mixed["stats"][-1],
+    }
+    out["roofline"] = roofline(mixed["timing"], nvox, 8)
+    for kname, v in sorted(mixed["timing"].items(), key=lambda kv: -kv[1]["ms"]):
+        print(f"[bench] kernel {kname:24s} launches {v['launches']:6d} total {v['ms']:9.1f} ms units {v['units']}",
+              file=sys.stderr, flush=True)
+    if not a.skip_fp64:
+        fp = run_arm(bw, rve_in, ks, bw.BW_FP64, max(1, a.steps // 2), min(a.warmup, 1), 1e-8, 1e-6)
+        v64 = len(ks) * max(1, a.steps // 2) / fp["seconds"]
+        dw = np.abs(mixed["omega"] - fp["omega"]) / np.maximum(fp["omega"], 1.0)
+        out["arms"] = {"fp64_plain": {"value": round(v64, 4), "unit": "k-points/s",
+                                      "max_error_bound": fp["max_bound"],
+                                      "solver_stats": fp["stats"][-1]},
+                       "mixed_over_fp64": round(out["value"] / v64, 3),
+                       "max_rel_diff_mixed_vs_fp64": float(dw.max())}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(rve_in, ks, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -80,6 +80,12 @@ typedef struct bw_eig_opts {
   double tol_eig;      /* eigen tolerance TOL_eig; 0 -> 1e-10                    */
   double tol_lin;      /* PCG relative tolerance TOL_lin; 0 -> 1e-10 (FP64),
                           1e-6 (MIXED inner solves)                              */
+  double tol_omega;    /* > 0: stop a wave vector as soon as every wanted mode
+                          carries an a-posteriori bound on its relative omega
+                          error <= tol_omega (the inner PCG tolerance then adapts
+                          to the outer residual, never looser than 1e-2 nor
+                          tighter than tol_lin); 0: the err1 / err2 rule of the
+                          subspace algorithm with TOL_eig                        */
 } bw_eig_opts;
 
 /* Statistics of the last solver call (all optional outputs). */
@@ -164,6 +170,18 @@ int bw_pcg_solve(bw_rve* rve, const double k_host[3], const void* b, void* x, in
 int bw_lowest_modes(bw_rve* rve, const double* k_list_host, int32_t nk, int32_t nmodes,
                     const bw_eig_opts* opts, double* omega_host, double* err_host,
                     void* modes, bw_stats* stats_host, void* stream);
+
+/* Diagnostics: opt-in kernel timing.  bw_timing_enable(1) clears the totals
+ * and brackets every subsequent kernel launch of the library with HIP events
+ * on the launch stream; bw_timing_enable(0) stops recording.  Adds a few
+ * microseconds of event overhead per launch. */
+int bw_timing_enable(int32_t enable);
+
+/* Writes a JSON object {"kernel": {"launches": n, "ms": total, "units": u}}
+ * into buf (len bytes, NUL-terminated, truncated if needed) after waiting for
+ * the recorded events; `units` counts the vectors each kernel processed.
+ * Returns the length the full report needs (including the NUL). */
+int64_t bw_timing_report(char* buf, int64_t len);
 
 /* Thread-local message describing the last non-zero status. */
 const char* bw_last_error(void);

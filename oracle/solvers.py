@@ -275,10 +275,11 @@ def dense_modes(ops: Operators, nmodes: int):
 
 def lowest_modes(rve, k_list, nmodes: int, method: str = "subspace", block=None,
                  tol_eig: float = 1e-12, tol_lin: float = 1e-12, dense_max: int = 3072,
-                 warm_start: bool = True):
+                 warm_start: bool = True, stats=None):
     """omega (rad/s) of the lowest nmodes branches at every k (Algorithm "Full algorithm").
 
     Uses the dense pencil when 3 N^3 <= dense_max, else the chosen iteration.
+    If `stats` is a list, one dict of iteration counts per k is appended to it.
     """
     nvox = int(np.prod(rve.n))
     block = block or min(2 * nmodes, nmodes + 8)
@@ -296,11 +297,13 @@ def lowest_modes(rve, k_list, nmodes: int, method: str = "subspace", block=None,
         else:
             defl = Deflation(ops)
             if method == "subspace":
-                lam, U, _ = subspace(ops, nmodes, block, tol_eig, tol_lin,
-                                     U0=U_prev if warm_start else None)
+                lam, U, info = subspace(ops, nmodes, block, tol_eig, tol_lin,
+                                        U0=U_prev if warm_start else None)
                 U_prev = U
             else:
-                lam, _, _ = lanczos(ops, nmodes, tol_eig, tol_lin)
+                lam, _, info = lanczos(ops, nmodes, tol_eig, tol_lin)
+            if stats is not None:
+                stats.append(dict(info))
             if defl.active:
                 lam = np.concatenate([np.zeros(3), lam])
         out[r] = np.sqrt(np.maximum(lam[:nmodes], 0.0))

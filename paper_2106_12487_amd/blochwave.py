@@ -35,7 +35,7 @@ class bw_eig_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("block", ctypes.c_int32), ("ncv", ctypes.c_int32),
                 ("maxit_outer", ctypes.c_int32), ("maxit_lin", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("tol_eig", ctypes.c_double),
-                ("tol_lin", ctypes.c_double)]
+                ("tol_lin", ctypes.c_double), ("tol_omega", ctypes.c_double)]
 
 
 class bw_stats(ctypes.Structure):
@@ -65,6 +65,8 @@ _SIGS = {
     "bw_lowest_modes": (_I, [_P, _DP, _I, _I, ctypes.POINTER(bw_eig_opts), _DP, _DP, _P,
                              ctypes.POINTER(bw_stats), _P]),
     "bw_last_error": (ctypes.c_char_p, []),
+    "bw_timing_enable": (_I, [_I]),
+    "bw_timing_report": (ctypes.c_int64, [ctypes.c_char_p, ctypes.c_int64]),
 }
 
 
@@ -93,6 +95,18 @@ def lib() -> ctypes.CDLL:
 
 def bw_last_error() -> str:
     return lib().bw_last_error().decode()
+
+
+def bw_timing_enable(enable: bool) -> None:
+    lib().bw_timing_enable(int(bool(enable)))
+
+
+def bw_timing_report() -> dict:
+    import json
+    need = lib().bw_timing_report(None, 0)
+    buf = ctypes.create_string_buffer(int(need) + 16)
+    lib().bw_timing_report(buf, len(buf))
+    return json.loads(buf.value.decode())
 
 
 def _check(code: int) -> int:
@@ -194,13 +208,15 @@ def bw_pcg_solve(rve: Rve, k, b, x, rtol: float, maxit: int = 0, stream=None):
 
 def bw_lowest_modes(rve: Rve, k_list, nmodes: int, method: int = BW_SUBSPACE, block: int = 0, ncv: int = 0,
                     tol_eig: float = 0.0, tol_lin: float = 0.0, maxit_outer: int = 0, maxit_lin: int = 0,
-                    warm_start: bool = True, modes=None, want_err: bool = True, stream=None):
+                    warm_start: bool = True, modes=None, want_err: bool = True, tol_omega: float = 0.0,
+                    stream=None):
     """omega (nk x nmodes, rad/s), error bounds, status and statistics."""
     k_arr, k_p = _darr(np.asarray(k_list).reshape(-1, 3))
     nk = int(k_arr.shape[0])
     om = np.zeros((nk, nmodes))
     er = np.zeros((nk, nmodes))
-    opts = bw_eig_opts(method, block, ncv, maxit_outer, maxit_lin, int(bool(warm_start)), tol_eig, tol_lin)
+    opts = bw_eig_opts(method, block, ncv, maxit_outer, maxit_lin, int(bool(warm_start)), tol_eig, tol_lin,
+                       tol_omega)
     st = bw_stats()
     code = _check(lib().bw_lowest_modes(rve.handle, k_p, nk, int(nmodes), ctypes.byref(opts),
                                         om.ctypes.data_as(_DP), er.ctypes.data_as(_DP) if want_err else None,

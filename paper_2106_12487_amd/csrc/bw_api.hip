@@ -3,6 +3,9 @@
 #include <chrono>
 #include <cmath>
 #include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
 #include <cstring>
 
 #include "bw_ops_impl.h"
@@ -11,6 +14,73 @@ namespace bw {
 
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------------------
+// kernel timing registry
+// ---------------------------------------------------------------------------
+namespace {
+struct Pending {
+  const char* name;
+  hipEvent_t e0, e1;
+  long units;
+};
+struct Totals {
+  long launches = 0, units = 0;
+  double ms = 0;
+};
+std::mutex g_tmu;
+std::atomic<bool> g_timing{false};
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+std::map<std::string, Totals> g_tot;
+
+hipEvent_t pool_get() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+void drain_locked() {
+  for (auto& p : g_pending) {
+    float ms = 0;
+    if (p.e0 && p.e1 && hipEventSynchronize(p.e1) == hipSuccess && hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+      Totals& t = g_tot[p.name];
+      t.launches += 1;
+      t.ms += ms;
+      t.units += p.units;
+    }
+    if (p.e0) g_pool.push_back(p.e0);
+    if (p.e1) g_pool.push_back(p.e1);
+  }
+  g_pending.clear();
+}
+}  // namespace
+
+bool timing_enabled() { return g_timing.load(std::memory_order_relaxed); }
+
+KTimer::KTimer(const char* n, hipStream_t st, long u) : name(n), s(st), units(u) {
+  if (!timing_enabled()) return;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  e0 = pool_get();
+  if (e0) (void)hipEventRecord(e0, s);
+}
+KTimer::~KTimer() {
+  if (!e0) return;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  hipEvent_t e1 = pool_get();
+  if (e1) (void)hipEventRecord(e1, s);
+  g_pending.push_back(Pending{name, e0, e1, units});
+  if (g_pending.size() > 4096) drain_locked();
+}
+void timing_add_units(const char* name, long units) {
+  if (!timing_enabled()) return;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_tot[name].units += units;
+}
 
 // ---------------------------------------------------------------------------
 // discrete frequencies (Sec. 3.1 eq. "frequencies", Sec. 3.2)
@@ -83,7 +153,7 @@ double M_scale(const bw_rve* r) { return r->rho_bar; }
 // ---------------------------------------------------------------------------
 template <typename T>
 PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<T>* b, cplx<T>* x, int nvec,
-                  double tol, int maxit, bool x0_zero, hipStream_t s) {
+                  double tol, int maxit, bool x0_zero, hipStream_t s, bool r_ready, bool true_check) {
   const Geom& g = r->g;
   const size_t n3 = (size_t)g.nvox * 3;
   PcgResult res;
@@ -96,8 +166,13 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
   cplx<T>* W = w.work((size_t)nvec * 6 * g.nvox);
   PcgDev pd = pcg_dev(r, nvec);
 
-  launch_residual<T>(r, d_qtab, b, x0_zero ? nullptr : x, rv, Ap, W, nvec, pd.rr, pd.rz /* ||b||^2 */, pd.partial,
-                     pd.counter, pd.max_blocks, s);
+  if (r_ready) {
+    launch_norms2<T>(r, b, rv, nvec, pd.rr, pd.rz /* ||b||^2 */, pd.partial, pd.max_blocks, s);
+  } else {
+    launch_residual<T>(r, d_qtab, b, x0_zero ? nullptr : x, rv, Ap, W, nvec, pd.rr, pd.rz /* ||b||^2 */,
+                       pd.partial, pd.counter, pd.max_blocks, s);
+    if (!x0_zero) res.k_applies += nvec;
+  }
   std::vector<double> rr(nvec), bb(nvec), thr(nvec);
   BW_HIP(hipMemcpyAsync(rr.data(), pd.rr, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
   BW_HIP(hipMemcpyAsync(bb.data(), pd.rz, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -115,7 +190,7 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
   BW_HIP(hipStreamSynchronize(s));
 
   const int chunk = g.nvox >= (1 << 18) ? 4 : 8;
-  std::vector<int> its(nvec), mask(nvec, 0);
+  std::vector<int> its(nvec), mask(nvec, 0), its_prev(nvec, 0);
   int restarts = 0;
   for (;;) {
     bool any = false;
@@ -129,6 +204,14 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
       BW_HIP(hipMemcpyAsync(act.data(), pd.active, nvec * sizeof(int), hipMemcpyDeviceToHost, s));
       BW_HIP(hipMemcpyAsync(its.data(), pd.iters, nvec * sizeof(int), hipMemcpyDeviceToHost, s));
       BW_HIP(hipStreamSynchronize(s));
+      if (timing_enabled()) {
+        long d = 0;
+        for (int v = 0; v < nvec; ++v) d += its[v] - its_prev[v];
+        its_prev = its;
+        for (const char* nm : {"k_strain_row_pcg", "k_axis1_inv_pcg", "k_axis0_contract_pcg", "k_axis1_fwd_pcg",
+                               "k_row_div_pcg", "k_pcg_update"})
+          timing_add_units(nm, d);
+      }
       bool cap = false;
       for (int v = 0; v < nvec; ++v)
         if (act[v] && its[v] >= maxit) {
@@ -140,14 +223,18 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
       for (int v = 0; v < nvec; ++v) any |= act[v] != 0;
       if (any) continue;
     }
-    // every vector stopped: check the true residual
-    launch_residual<T>(r, d_qtab, b, x, rv, Ap, W, nvec, pd.rr, nullptr, pd.partial, pd.counter, pd.max_blocks, s);
+    // every vector stopped: check the true residual (or take the recurrence's)
+    if (true_check) {
+      launch_residual<T>(r, d_qtab, b, x, rv, Ap, W, nvec, pd.rr, nullptr, pd.partial, pd.counter, pd.max_blocks,
+                         s);
+      res.k_applies += nvec;
+    }
     BW_HIP(hipMemcpyAsync(rr.data(), pd.rr, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
     BW_HIP(hipMemcpyAsync(its.data(), pd.iters, nvec * sizeof(int), hipMemcpyDeviceToHost, s));
     BW_HIP(hipStreamSynchronize(s));
     bool again = false;
     std::fill(mask.begin(), mask.end(), 0);
-    for (int v = 0; v < nvec; ++v) {
+    for (int v = 0; v < nvec && true_check; ++v) {
       if (rr[v] > thr[v] && its[v] < maxit && restarts < 8) {
         mask[v] = 1;
         again = true;
@@ -167,13 +254,14 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
     if (rr[v] > thr[v]) res.converged = false;
     res.total_iters += its[v];
   }
+  res.k_applies += res.total_iters;
   return res;
 }
 
 template PcgResult pcg_run<double>(bw_rve*, const double*, const QTable&, const cplx<double>*, cplx<double>*, int,
-                                   double, int, bool, hipStream_t);
+                                   double, int, bool, hipStream_t, bool, bool);
 template PcgResult pcg_run<float>(bw_rve*, const double*, const QTable&, const cplx<float>*, cplx<float>*, int,
-                                  double, int, bool, hipStream_t);
+                                  double, int, bool, hipStream_t, bool, bool);
 
 PcgDev pcg_dev(bw_rve* r, int nvec) {
   const Geom& g = r->g;
@@ -230,6 +318,35 @@ using namespace bw;
   }
 
 extern "C" const char* bw_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int bw_timing_enable(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  drain_locked();
+  g_tot.clear();
+  g_timing.store(enable != 0);
+  return BW_OK;
+}
+
+extern "C" int64_t bw_timing_report(char* buf, int64_t len) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  drain_locked();
+  std::string js = "{";
+  bool first = true;
+  for (auto& kv : g_tot) {
+    char tmp[256];
+    snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"units\": %ld}", first ? "" : ", ",
+             kv.first.c_str(), kv.second.launches, kv.second.ms, kv.second.units);
+    js += tmp;
+    first = false;
+  }
+  js += "}";
+  if (buf && len > 0) {
+    const size_t n = std::min<size_t>(js.size(), (size_t)len - 1);
+    std::memcpy(buf, js.data(), n);
+    buf[n] = 0;
+  }
+  return (int64_t)js.size() + 1;
+}
 
 static bool spd6(const double* c21) {
   // Cholesky of the symmetric 6x6
@@ -299,9 +416,11 @@ extern "C" int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3]
     for (int i = 0; i < 21; ++i) r->C0s[i] = r->C0_si[i] / r->Cref;
     r->C21s_host.resize((size_t)n_grains * 21);
     r->rhos_host.resize(n_grains);
+    r->rho_min_s = INFINITY;
     for (int gi = 0; gi < n_grains; ++gi) {
       for (int i = 0; i < 21; ++i) r->C21s_host[gi * 21 + i] = C21_host[gi * 21 + i] / r->Cref;
       r->rhos_host[gi] = rho_host[gi] / r->rho_bar;
+      if (count[gi] > 0) r->rho_min_s = std::min(r->rho_min_s, r->rhos_host[gi]);
     }
     std::vector<float> c32(r->C21s_host.begin(), r->C21s_host.end());
     std::vector<float> r32(r->rhos_host.begin(), r->rhos_host.end());

@@ -6,6 +6,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 #include "bw_block.h"
@@ -13,10 +15,30 @@
 
 namespace bw {
 
+static bool verbose() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("BW_VERBOSE");
+    v = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+
 struct EigOpts {
   int method, block, ncv, maxit_outer, maxit_lin, warm;
-  double tol_eig, tol_lin;
+  double tol_eig, tol_lin, tol_omega;
 };
+
+// Relative omega bound from a residual norm in the M^-1 norm: Kato-Temple when
+// the Ritz gap allows it, else the residual bound itself.
+static double omega_bound(double res, const std::vector<double>& lam, int p, int q) {
+  double gap = INFINITY;
+  for (int j = 0; j < q; ++j)
+    if (j != p) gap = std::min(gap, std::fabs(lam[j] - lam[p]));
+  double dl = res;
+  if (gap > 2 * res) dl = std::min(res, res * res / (gap - res));
+  return lam[p] > 0 ? 0.5 * dl / lam[p] : dl;
+}
 
 struct Counters {
   long pcg_iters = 0, block_iters = 0, outer = 0, kap = 0, map = 0;
@@ -230,15 +252,7 @@ static void rr64_bounds(bw_rve* r, const double* dq, cplx<double>*& U, int q, in
   BW_HIP(hipStreamSynchronize(s));
   BW_REQUIRE(info == 0, BW_EINVAL, "Rayleigh-Ritz Gram matrix not positive definite");
   bound.assign(n_want, 0.0);
-  for (int p = 0; p < n_want; ++p) {
-    const double res = std::sqrt(std::max(rn[p].x, 0.0));  // ||r||_{M^-1}
-    double gap = INFINITY;
-    for (int j = 0; j < q; ++j)
-      if (j != p) gap = std::min(gap, std::fabs(lam[j] - lam[p]));
-    double dl = res;
-    if (gap > 2 * res) dl = std::min(res, res * res / (gap - res));
-    bound[p] = lam[p] > 0 ? 0.5 * dl / lam[p] : dl;
-  }
+  for (int p = 0; p < n_want; ++p) bound[p] = omega_bound(std::sqrt(std::max(rn[p].x, 0.0)), lam, p, q);
 }
 
 template <typename T>
@@ -278,35 +292,64 @@ static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigO
     lam_prev.clear();
   }
   const bool fp32 = sizeof(T) == 4;
-  const double tol = fp32 ? std::max(o.tol_eig, 5e-6) : o.tol_eig;
-  const double tol_lin = fp32 ? std::max(o.tol_lin, 2e-6) : o.tol_lin;
-  std::vector<double> lam(q), lam_old, inv(q);
+  // FP32 stage: the eigenvalue change must settle to tol (at least 1e-6) and the
+  // residual err2 must either reach 10 tol or stop improving (it floors at the
+  // FP32 round-off of K, about eps * lambda_max / lambda); the FP64
+  // Rayleigh-Ritz step and its bounds then decide the accuracy.
+  const double tol = fp32 ? std::max(o.tol_eig, 1e-6) : o.tol_eig;
+  const double tol_lin = fp32 ? std::max(o.tol_lin, 1e-6) : o.tol_lin;
+  const double bound_target = o.tol_omega > 0 ? o.tol_omega : 5.0 * o.tol_eig;
+  std::vector<double> lam(q), lam_old, inv(q), err2_hist;
   bool conv = false;
   int it = 0;
+  int round = 0;
+  // After the first iteration at this k the Ritz step already provides M U
+  // (next right-hand sides) and R = K U - lambda M U for the whole block, so the
+  // PCG initial residual for x0 = U / lambda is -R / lambda: no extra applies.
+  bool have_KU = false;
+  std::vector<double> ninv(q);
   for (; it < o.maxit_outer; ++it) {
-    apply_M_blk<T>(r, U, V, q, false, cnt, s);  // v_p = M U_p
-    if (out.jstar >= 0) launch_deflate<T>(U, V, MN, q, g.nvox, out.jstar, sm.coef, s);
+    if (have_KU) {
+      std::swap(V, MU);                          // v_p = M U_p from the Ritz step
+    } else {
+      apply_M_blk<T>(r, U, V, q, false, cnt, s);  // v_p = M U_p
+      if (out.jstar >= 0) launch_deflate<T>(U, V, MN, q, g.nvox, out.jstar, sm.coef, s);
+    }
     const bool warm = (int)lam_prev.size() == q;
+    bool r_ready = false;
     if (warm) {
-      for (int p = 0; p < q; ++p) inv[p] = lam_prev[p] > 0 ? 1.0 / lam_prev[p] : 0.0;
+      for (int p = 0; p < q; ++p) {
+        inv[p] = lam_prev[p] > 0 ? 1.0 / lam_prev[p] : 0.0;
+        ninv[p] = -inv[p];
+      }
       BW_HIP(hipMemcpyAsync(sm.sc, inv.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
       launch_scale_cols<T>(U, sm.sc, Ub, q, n3, n3, s);  // x0 = U / lambda
+      if (have_KU) {
+        BW_HIP(hipMemcpyAsync(sm.sc + 128, ninv.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_scale_cols<T>(R, sm.sc + 128, w.vec(0, (size_t)q * n3), q, n3, n3, s);  // r0 = -R / lambda
+        r_ready = true;
+      }
     } else {
       BW_HIP(hipMemsetAsync(Ub, 0, (size_t)q * n3 * sizeof(cplx<T>), s));
     }
-    PcgResult pr = pcg_run<T>(r, dq, qt, V, Ub, q, tol_lin, o.maxit_lin, !warm, s);  // Ubar = K^-1 v
+    double tl = tol_lin;
+    if (o.tol_omega > 0) tl = std::max(tol_lin, std::min(1e-2, err2_hist.empty() ? 1e-3 : 0.05 * err2_hist.back()));
+    // Ubar = K^-1 v; the outer residual check uses the true K, so the inner
+    // solve stops on its recurrence residual
+    PcgResult pr = pcg_run<T>(r, dq, qt, V, Ub, q, tl, o.maxit_lin, !warm, s, r_ready, false);
     cnt.pcg_iters += pr.total_iters;
     cnt.block_iters += pr.block_iters;
-    cnt.kap += pr.total_iters + 2 * q;
+    cnt.kap += pr.k_applies;
     apply_M_blk<T>(r, Ub, MUb, q, false, cnt, s);
     if (out.jstar >= 0) launch_deflate<T>(Ub, MUb, MN, q, g.nvox, out.jstar, sm.coef, s);
     launch_gram<T>(Ub, q, V, q, n3, n3, sm.Kq, r->ws_red, r->d_ctr, s);    // Kq = Ubar^H Kn
     launch_gram<T>(Ub, q, MUb, q, n3, n3, sm.Mq, r->ws_red, r->d_ctr, s);  // Mq = Ubar^H Mn
     launch_small_geig(sm.Kq, sm.Mq, q, sm.lam, sm.Q, sm.info, s);
     launch_ritz<T>(Ub, q, sm.Q, q, U, q, n3, n3, s);                       // U = Ubar Q
-    launch_ritz<T>(MUb, q, sm.Q, q, MU, nw, n3, n3, s);                    // M U (first n)
-    apply_K_blk<T>(r, dq, U, KU, nw, cnt, s);
-    launch_lincomb<T>(KU, MU, sm.lam, R, nw, n3, n3, s);
+    launch_ritz<T>(MUb, q, sm.Q, q, MU, q, n3, n3, s);                     // M U
+    apply_K_blk<T>(r, dq, U, KU, q, cnt, s);
+    launch_lincomb<T>(KU, MU, sm.lam, R, q, n3, n3, s);                    // R = K U - lambda M U
+    have_KU = true;
     launch_dots<T>(R, R, nw, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
     launch_dots<T>(MU, MU, nw, n3, n3, sm.dots + 128, r->ws_red2, r->d_ctr + 320, s);
     std::vector<double2> rr(nw), mm(nw);
@@ -330,35 +373,68 @@ static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigO
     }
     for (int p = 0; p < nw; ++p)
       err2 = std::max(err2, std::sqrt(std::max(rr[p].x, 0.0)) / (lam[p] * std::sqrt(std::max(mm[p].x, 1e-300))));
+    err2_hist.push_back(err2);
     lam_old = lam;
     lam_prev = lam;
     have_start = true;
     cnt.outer += 1;
-    if (nw == 0 || (err1 <= tol && err2 <= 10.0 * tol)) {
-      conv = true;
-      ++it;
-      break;
+    if (verbose())
+      fprintf(stderr, "[bw] k=(%.4g,%.4g,%.4g) outer %d err1 %.3e err2 %.3e pcg %ld (block %ld) lam0 %.6e\n", k[0],
+              k[1], k[2], it, err1, err2, pr.total_iters, pr.block_iters, lam[0]);
+    const size_t h = err2_hist.size();
+    const bool stalled = fp32 && h >= 4 && err2 > 0.8 * err2_hist[h - 4];
+    // bound-based test: ||r||_{M^-1} <= ||r|| / sqrt(min rho') for M-normalized Ritz vectors
+    bool bounds_ok = false;
+    if (o.tol_omega > 0 && nw > 0) {
+      double worst = 0;
+      for (int p = 0; p < nw; ++p)
+        worst = std::max(worst, omega_bound(std::sqrt(std::max(rr[p].x, 0.0) / r->rho_min_s), lam, p, q));
+      bounds_ok = worst <= o.tol_omega && std::isfinite(err1);
     }
-  }
-  out.outer = it;
-  out.converged = conv;
-  out.lam.assign(lam.begin(), lam.begin() + nw);
-  // error bounds in FP64 (and, for FP32 vectors, an FP64 Rayleigh-Ritz first)
-  if (nw > 0) {
-    std::vector<double> lam64, bnd;
-    if (fp32) {
+    const bool rule = o.tol_omega > 0 ? (bounds_ok || (fp32 && stalled && err1 <= tol))
+                                      : (err1 <= tol && (err2 <= 10.0 * tol || stalled));
+    if (nw == 0 || rule) {
+      if (!fp32 || nw == 0) {
+        conv = true;
+        ++it;
+        break;
+      }
+      // FP64 Rayleigh-Ritz on the FP32 block and the a-posteriori bounds
+      std::vector<double> lam64, bnd;
       Workspace<double>& w64 = ws<double>(r);
       cplx<double>* U64 = w64.vec(3, (size_t)q * n3);
       launch_convert<float, double>((const cplx<float>*)U, U64, (size_t)q * n3, s);
       rr64_bounds(r, dq, U64, q, nw, lam64, bnd, true, nullptr, nullptr, cnt, s);
-      // carry the refined block back to the FP32 warm start
       launch_convert<double, float>(U64, (cplx<float>*)U, (size_t)q * n3, s);
       lam_prev = lam64;
-    } else {
-      lam64 = lam;
-      cplx<double>* Ud = (cplx<double>*)U;
-      rr64_bounds(r, dq, Ud, q, nw, lam64, bnd, false, (const cplx<double>*)KU, (const cplx<double>*)MU, cnt, s);
+      have_KU = false;
+      lam_old.clear();
+      err2_hist.clear();
+      out.lam.assign(lam64.begin(), lam64.begin() + nw);
+      out.bound = bnd;
+      const double worst = *std::max_element(bnd.begin(), bnd.end());
+      if (verbose()) fprintf(stderr, "[bw]   FP64 Rayleigh-Ritz: worst bound %.3e\n", worst);
+      if (worst <= bound_target || ++round >= 4) {
+        conv = worst <= bound_target;
+        ++it;
+        break;
+      }
     }
+  }
+  out.outer = it;
+  out.converged = conv;
+  if (nw > 0 && !fp32) {
+    std::vector<double> lam64 = lam, bnd;
+    cplx<double>* Ud = (cplx<double>*)U;
+    rr64_bounds(r, dq, Ud, q, nw, lam64, bnd, false, (const cplx<double>*)KU, (const cplx<double>*)MU, cnt, s);
+    out.lam.assign(lam64.begin(), lam64.begin() + nw);
+    out.bound = bnd;
+  } else if (nw > 0 && out.lam.empty()) {
+    // FP32 stage hit maxit before its Rayleigh-Ritz step
+    std::vector<double> lam64, bnd;
+    cplx<double>* U64 = ws<double>(r).vec(3, (size_t)q * n3);
+    launch_convert<float, double>((const cplx<float>*)U, U64, (size_t)q * n3, s);
+    rr64_bounds(r, dq, U64, q, nw, lam64, bnd, true, nullptr, nullptr, cnt, s);
     out.lam.assign(lam64.begin(), lam64.begin() + nw);
     out.bound = bnd;
   }
@@ -450,6 +526,7 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
       o.warm = opts->warm_start;
       o.tol_eig = opts->tol_eig;
       o.tol_lin = opts->tol_lin;
+      o.tol_omega = opts->tol_omega;
     } else {
       o.warm = 1;
     }

@@ -24,10 +24,8 @@ constexpr int GKC = 64;  // rows per LDS tile (16 per wave)
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram(const cplx<T>* __restrict__ X, int qx, const cplx<T>* __restrict__ Y,
                                               int qy, long n, long vstride, long rows_per_blk,
-                                              double* __restrict__ partial, double2* __restrict__ G,
-                                              unsigned* counter) {
+                                              double* __restrict__ partial) {
   __shared__ double2 smem[2 * GRAM_QMAX * (GKC + 1)];
-  __shared__ int is_last;
   double2* Xs = smem;
   double2* Ys = smem + GRAM_QMAX * (GKC + 1);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -90,25 +88,18 @@ __global__ __launch_bounds__(256) void k_gram(const cplx<T>* __restrict__ X, int
         }
       }
   __syncthreads();
-  for (int t = tid; t < 2 * nq; t += 256) {
-    const double v = red[t] + red[2 * nq + t] + red[4 * nq + t] + red[6 * nq + t];
-    __hip_atomic_store(&partial[(size_t)blockIdx.x * 2 * nq + t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  for (int t = tid; t < 2 * nq; t += 256) {
-    double acc = 0;
-    for (unsigned b = 0; b < gridDim.x; ++b) acc += coherent_load(&partial[(size_t)b * 2 * nq + t]);
-    reinterpret_cast<double*>(G)[t] = acc;
-  }
-  if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int t = tid; t < 2 * nq; t += 256)
+    partial[(size_t)blockIdx.x * 2 * nq + t] = red[t] + red[2 * nq + t] + red[4 * nq + t] + red[6 * nq + t];
+}
+
+// second phase of the Gram product: sum the per-block partials in block order
+__global__ __launch_bounds__(256) void k_gram_finalize(const double* __restrict__ partial, int nblk, int n2q,
+                                                       double* __restrict__ G) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n2q) return;
+  double acc = 0;
+  for (int b = 0; b < nblk; ++b) acc += partial[(size_t)b * n2q + t];
+  G[t] = acc;
 }
 
 template <typename T>
@@ -123,8 +114,12 @@ void launch_gram(const cplx<T>* X, int qx, const cplx<T>* Y, int qy, long n, lon
   nblk = (n + rows - 1) / rows;
   const size_t part_bytes = (size_t)nblk * 2 * qx * qy * sizeof(double);
   char* base = (char*)scratch.get(part_bytes);
-  hipLaunchKernelGGL((k_gram<T>), dim3((unsigned)nblk), dim3(256), 0, s, X, qx, Y, qy, n, vstride, rows,
-                     (double*)base, G, counter);
+  BW_LAUNCH("k_gram_mfma", (long)qx * qy, (k_gram<T>), dim3((unsigned)nblk), dim3(256), 0, s, X, qx, Y, qy, n,
+            vstride, rows, (double*)base);
+  const int n2q = 2 * qx * qy;
+  hipLaunchKernelGGL(k_gram_finalize, dim3((n2q + 255) / 256), dim3(256), 0, s, (const double*)base, (int)nblk, n2q,
+                     (double*)G);
+  (void)counter;
 }
 
 // ---------------------------------------------------------------------------
@@ -166,7 +161,8 @@ void launch_ritz(const cplx<T>* X, int q, const double2* Q, int ldq, cplx<T>* Y,
   BW_REQUIRE(q <= GEIG_QMAX && qout <= GRAM_QMAX, BW_EINVAL, "Ritz block too large");
   long nb = (n + 255) / 256;
   if (nb > 2048) nb = 2048;
-  hipLaunchKernelGGL((k_ritz<T>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y, qout, n, vstride);
+  BW_LAUNCH("k_ritz", (long)q * qout, (k_ritz<T>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y, qout, n,
+            vstride);
 }
 
 // ---------------------------------------------------------------------------
@@ -174,8 +170,7 @@ void launch_ritz(const cplx<T>* X, int q, const double2* Q, int ldq, cplx<T>* Y,
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(NT) void k_dots(const cplx<T>* __restrict__ X, const cplx<T>* __restrict__ Y, long n,
-                                             long vstride, int bpv, double* partial, double2* out, unsigned* counters,
-                                             int maxb) {
+                                             long vstride, int bpv, double* partial, int maxb) {
   __shared__ double sh[NT / 64];
   const int p = blockIdx.x / bpv;
   const int b = blockIdx.x - p * bpv;
@@ -186,9 +181,15 @@ __global__ __launch_bounds__(NT) void k_dots(const cplx<T>* __restrict__ X, cons
     sr += x.x * y.x + x.y * y.y;
     si += x.x * y.y - x.y * y.x;
   }
-  double vals[2] = {sr, si}, tot[2];
-  if (reduce_partials<2>(vals, tot, partial, counters, p, b, bpv, maxb, sh))
-    if (threadIdx.x == 0) out[p] = make_double2(tot[0], tot[1]);
+  const double vals[2] = {sr, si};
+  store_partials<2>(vals, partial, p, b, maxb, sh);
+}
+
+__global__ __launch_bounds__(NT) void k_dots_finalize(const double* __restrict__ partial, int bpv, double2* out) {
+  __shared__ double sh[NT / 64];
+  double tot[2];
+  sum_partials<2>(tot, partial, blockIdx.x, bpv, bpv, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = make_double2(tot[0], tot[1]);
 }
 
 template <typename T>
@@ -198,8 +199,9 @@ void launch_dots(const cplx<T>* X, const cplx<T>* Y, int nv, long n, long vstrid
   const int bpv = pw_blocks(n);
   const size_t part_bytes = (size_t)nv * bpv * 2 * sizeof(double);
   char* base = (char*)scratch.get(part_bytes);
-  hipLaunchKernelGGL((k_dots<T>), dim3(nv * bpv), dim3(NT), 0, s, X, Y, n, vstride, bpv, (double*)base, out,
-                     counters, bpv);
+  hipLaunchKernelGGL((k_dots<T>), dim3(nv * bpv), dim3(NT), 0, s, X, Y, n, vstride, bpv, (double*)base, bpv);
+  hipLaunchKernelGGL(k_dots_finalize, dim3(nv), dim3(NT), 0, s, (const double*)base, bpv, out);
+  (void)counters;
 }
 
 // ---------------------------------------------------------------------------

@@ -39,6 +39,26 @@ struct Error {
   } while (0)
 
 // ---------------------------------------------------------------------------
+// opt-in kernel timing: HIP events around each launch, totals per kernel name
+// (name, launches, milliseconds, work units = vectors processed)
+// ---------------------------------------------------------------------------
+bool timing_enabled();
+struct KTimer {
+  const char* name;
+  hipStream_t s;
+  long units;
+  hipEvent_t e0 = nullptr;
+  KTimer(const char* n, hipStream_t st, long u);
+  ~KTimer();
+};
+void timing_add_units(const char* name, long units);
+#define BW_LAUNCH(name, units, kern, grid, block, shm, s, ...)  \
+  do {                                                         \
+    ::bw::KTimer kt_((name), (s), (units));                    \
+    hipLaunchKernelGGL(kern, grid, block, shm, s, __VA_ARGS__); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
 // device buffer with grow-on-demand semantics
 // ---------------------------------------------------------------------------
 struct DevBuf {
@@ -94,6 +114,7 @@ struct PcgResult {
   bool converged = false;
   long total_iters = 0;
   long block_iters = 0;
+  long k_applies = 0;  // single-vector K applies, residual checks included
 };
 
 }  // namespace bw
@@ -107,6 +128,7 @@ struct bw_rve {
   int device;
   // nondimensionalization: C' = C / Cref, q' = q * ell, rho' = rho / rho_bar
   double Cref, ell, rho_bar;
+  double rho_min_s;  // smallest scaled density (bounds the M^-1 norm)
   double C0_si[21];     // volume-averaged stiffness (Pa)
   double C0s[21];       // scaled
   std::vector<double> C21s_host;  // G x 21 scaled
@@ -174,6 +196,10 @@ template <typename T>
 void launch_pcg_update(const bw_rve* r, const double* d_qtab, cplx<T>* x, cplx<T>* rv,
                        const cplx<T>* p, const cplx<T>* Ap, int nvec, const PcgDev& pd,
                        hipStream_t s);
+// ||r||^2 and ||b||^2 of a given residual (no writes)
+template <typename T>
+void launch_norms2(const bw_rve* r, const cplx<T>* b, const cplx<T>* rv, int nvec, double* d_rr, double* d_bb,
+                   double* d_partial, int max_blocks, hipStream_t s);
 // r = b - K x stored in rv (K x computed into tmp), with ||r||^2, ||b||^2 (FP64)
 template <typename T>
 void launch_residual(const bw_rve* r, const double* d_qtab, const cplx<T>* b, const cplx<T>* x,
@@ -198,8 +224,11 @@ PcgDev pcg_dev(bw_rve* r, int nvec);
 const double* upload_qtable(bw_rve* r, const QTable& t, DevBuf& buf, hipStream_t s);
 double K_scale(const bw_rve* r);
 double M_scale(const bw_rve* r);
+// x0_zero: x is ignored and taken as 0.  r_ready: the caller already wrote the
+// initial residual b - K x into workspace vector 0.  true_check: confirm the
+// recurrence residual with a true residual before returning.
 template <typename T>
 PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<T>* b, cplx<T>* x, int nvec,
-                  double tol, int maxit, bool x0_zero, hipStream_t s);
+                  double tol, int maxit, bool x0_zero, hipStream_t s, bool r_ready = false, bool true_check = true);
 
 }  // namespace bw

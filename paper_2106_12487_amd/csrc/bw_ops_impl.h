@@ -120,38 +120,75 @@ __device__ __forceinline__ double coherent_load(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Publishes NV partial sums of this block for vector v and returns true in
-// the block that arrives last; that block then holds, in `tot`, the sums over
-// all blocks taken in block order (independent of arrival order).
+// Writes this block's NV partial sums for vector v (plain stores).  A finalize
+// kernel launched afterwards sums them in block order, so the result does not
+// depend on scheduling and no device-wide fence is needed inside the kernel.
 template <int NV>
-__device__ __forceinline__ bool reduce_partials(double (&vals)[NV], double (&tot)[NV], double* partial,
-                                                unsigned* counter, int v, int blk, int nblk, int maxb,
-                                                double* sh) {
-  __shared__ int is_last;
+__device__ __forceinline__ void store_partials(const double (&vals)[NV], double* partial, int v, int blk, int maxb,
+                                               double* sh) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    double s = block_sum(vals[i], sh);
-    if (threadIdx.x == 0)
-      __hip_atomic_store(&partial[((size_t)v * maxb + blk) * NV + i], s, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+    const double s = block_sum(vals[i], sh);
+    if (threadIdx.x == 0) partial[((size_t)v * maxb + blk) * NV + i] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(&counter[v], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == (unsigned)(nblk - 1));
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
+}
+
+// Sum of the NV partials of vector v over nblk blocks in block order (valid in
+// thread 0 of a one-block-per-vector finalize kernel).
+template <int NV>
+__device__ __forceinline__ void sum_partials(double (&tot)[NV], const double* partial, int v, int nblk, int maxb,
+                                             double* sh) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double acc = 0;
-    for (int b = threadIdx.x; b < nblk; b += NT) acc += coherent_load(&partial[((size_t)v * maxb + b) * NV + i]);
+    for (int b = threadIdx.x; b < nblk; b += NT) acc += partial[((size_t)v * maxb + b) * NV + i];
     tot[i] = block_sum(acc, sh);
   }
-  if (threadIdx.x == 0) __hip_atomic_store(&counter[v], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
+}
+
+// finalize ops
+enum FinOp { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RESID = 2, FIN_RESTART = 3 };
+
+static __global__ __launch_bounds__(NT) void k_finalize(int op, int nblk, PcgDev pd, const int* __restrict__ mask,
+                                                 double* rr_out, double* bb_out) {
+  __shared__ double sh[NT / 64];
+  const int v = blockIdx.x;
+  if (op == FIN_ALPHA) {
+    if (!pd.active[v]) return;
+    double tot[1];
+    sum_partials<1>(tot, pd.partial, v, nblk, pd.max_blocks, sh);
+    if (threadIdx.x == 0) {
+      pd.pAp[v] = tot[0];
+      pd.alpha[v] = tot[0] > 0 ? pd.rz[v] / tot[0] : 0.0;
+    }
+  } else if (op == FIN_BETA) {
+    if (!pd.active[v]) return;
+    double tot[2];
+    sum_partials<2>(tot, pd.partial, v, nblk, pd.max_blocks, sh);
+    if (threadIdx.x == 0) {
+      const double old = pd.rz[v];
+      pd.beta[v] = old != 0.0 ? tot[0] / old : 0.0;
+      pd.rz[v] = tot[0];
+      pd.rr[v] = tot[1];
+      pd.iters[v] += 1;
+      if (tot[1] <= pd.bb[v]) pd.active[v] = 0;
+    }
+  } else if (op == FIN_RESID) {
+    double tot[2];
+    sum_partials<2>(tot, pd.partial, v, nblk, pd.max_blocks, sh);
+    if (threadIdx.x == 0) {
+      rr_out[v] = tot[0];
+      if (bb_out) bb_out[v] = tot[1];
+    }
+  } else {
+    if (!mask[v]) return;
+    double tot[1];
+    sum_partials<1>(tot, pd.partial, v, nblk, pd.max_blocks, sh);
+    if (threadIdx.x == 0) {
+      pd.rz[v] = tot[0];
+      pd.beta[v] = 0.0;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -343,13 +380,8 @@ __global__ __launch_bounds__(NT) void k_row_div(const cplx<T>* __restrict__ W, c
     }
   }
   if (MODE == 1) {
-    double vals[1] = {part}, tot[1];
-    if (reduce_partials<1>(vals, tot, pd.partial, pd.counter, v, tile, rt.tpv, pd.max_blocks, sh)) {
-      if (threadIdx.x == 0) {
-        pd.pAp[v] = tot[0];
-        pd.alpha[v] = tot[0] > 0 ? pd.rz[v] / tot[0] : 0.0;
-      }
-    }
+    const double vals[1] = {part};
+    store_partials<1>(vals, pd.partial, v, tile, pd.max_blocks, sh);
   }
 }
 
@@ -588,24 +620,15 @@ __global__ __launch_bounds__(NT) void k_pcg_update(cplx<T>* __restrict__ x, cplx
       rr += (double)rv[c].x * rv[c].x + (double)rv[c].y * rv[c].y;
     }
   }
-  double vals[2] = {rz, rr}, tot[2];
-  if (reduce_partials<2>(vals, tot, pd.partial, pd.counter, v, b, bpv, pd.max_blocks, sh)) {
-    if (threadIdx.x == 0) {
-      const double old = pd.rz[v];
-      pd.beta[v] = old != 0.0 ? tot[0] / old : 0.0;
-      pd.rz[v] = tot[0];
-      pd.rr[v] = tot[1];
-      pd.iters[v] += 1;
-      if (tot[1] <= pd.bb[v]) pd.active[v] = 0;
-    }
-  }
+  const double vals[2] = {rz, rr};
+  store_partials<2>(vals, pd.partial, v, b, pd.max_blocks, sh);
 }
 
 // r = b - Kx (Kx given), ||r||^2 and ||b||^2 per vector (FP64).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_residual(const cplx<T>* __restrict__ bv, const cplx<T>* __restrict__ Kx,
-                                                 cplx<T>* __restrict__ r, long nvox3, int bpv, double* rrv,
-                                                 double* bbv, double* partial, unsigned* counter, int maxb) {
+                                                 cplx<T>* __restrict__ r, long nvox3, int bpv, double* partial,
+                                                 int maxb) {
   using V = cplx<T>;
   __shared__ double sh[NT / 64];
   const int v = blockIdx.x / bpv;
@@ -619,13 +642,26 @@ __global__ __launch_bounds__(NT) void k_residual(const cplx<T>* __restrict__ bv,
     rr += (double)rv.x * rv.x + (double)rv.y * rv.y;
     bb += (double)bb_.x * bb_.x + (double)bb_.y * bb_.y;
   }
-  double vals[2] = {rr, bb}, tot[2];
-  if (reduce_partials<2>(vals, tot, partial, counter, v, b, bpv, maxb, sh)) {
-    if (threadIdx.x == 0) {
-      rrv[v] = tot[0];
-      if (bbv) bbv[v] = tot[1];
-    }
+  const double vals[2] = {rr, bb};
+  store_partials<2>(vals, partial, v, b, maxb, sh);
+}
+
+// ||r||^2, ||b||^2 per vector of a given residual (read only)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_norms2(const cplx<T>* __restrict__ bv, const cplx<T>* __restrict__ r,
+                                               long nvox3, int bpv, double* partial, int maxb) {
+  __shared__ double sh[NT / 64];
+  const int v = blockIdx.x / bpv;
+  const int b = blockIdx.x - v * bpv;
+  double rr = 0, bb = 0;
+  for (long i = (long)b * NT + threadIdx.x; i < nvox3; i += (long)bpv * NT) {
+    const size_t o = (size_t)v * nvox3 + i;
+    const cplx<T> rv = r[o], b_ = bv[o];
+    rr += (double)rv.x * rv.x + (double)rv.y * rv.y;
+    bb += (double)b_.x * b_.x + (double)b_.y * b_.y;
   }
+  const double vals[2] = {rr, bb};
+  store_partials<2>(vals, partial, v, b, maxb, sh);
 }
 
 // restart of the selected vectors: rz = <r, P^ r>, beta = 0
@@ -650,13 +686,8 @@ __global__ __launch_bounds__(NT) void k_pcg_restart(const cplx<T>* __restrict__ 
 #pragma unroll
     for (int c = 0; c < 3; ++c) rz += (double)rv[c].x * z[c].x + (double)rv[c].y * z[c].y;
   }
-  double vals[1] = {rz}, tot[1];
-  if (reduce_partials<1>(vals, tot, pd.partial, pd.counter, v, b, bpv, pd.max_blocks, sh)) {
-    if (threadIdx.x == 0) {
-      pd.rz[v] = tot[0];
-      pd.beta[v] = 0.0;
-    }
-  }
+  const double vals[1] = {rz};
+  store_partials<1>(vals, pd.partial, v, b, pd.max_blocks, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -755,20 +786,23 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
   if (g.n1 > 1) {
     with_n(g.n1, [&](auto N1) {
       ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2);
-      hipLaunchKernelGGL((k_axis1<T, decltype(N1)::value, true>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2,
+      BW_LAUNCH(OP == 0 ? (active ? "k_axis1_inv_pcg" : "k_axis1_inv") : "k_axis1_inv_mass", active ? 0 : nvec,
+                (k_axis1<T, decltype(N1)::value, true>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2,
                          (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
     });
   }
   with_n(g.n0, [&](auto N0) {
     ColTile ct = axis0_tile<T>(N0, n12);
     const T* tab = tab_override ? tab_override : (OP == 0 ? ctab<T>(r) : rhotab<T>(r));
-    hipLaunchKernelGGL((k_axis0_op<T, decltype(N0)::value, OP>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, n12,
+    BW_LAUNCH(OP == 0 ? (active ? "k_axis0_contract_pcg" : "k_axis0_contract") : "k_axis0_mass", active ? 0 : nvec,
+              (k_axis0_op<T, decltype(N0)::value, OP>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, n12,
                        g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
   });
   if (g.n1 > 1) {
     with_n(g.n1, [&](auto N1) {
       ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2);
-      hipLaunchKernelGGL((k_axis1<T, decltype(N1)::value, false>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2,
+      BW_LAUNCH(OP == 0 ? (active ? "k_axis1_fwd_pcg" : "k_axis1_fwd") : "k_axis1_fwd_mass", active ? 0 : nvec,
+                (k_axis1<T, decltype(N1)::value, false>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2,
                          (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
     });
   }
@@ -784,11 +818,13 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
     constexpr int n2c = decltype(N2)::value;
     RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1);
     if (mode == 0)
-      hipLaunchKernelGGL((k_strain_row<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, (cplx<T>*)nullptr, W,
+      BW_LAUNCH("k_strain_row", nvec, (k_strain_row<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u,
+                (cplx<T>*)nullptr, W,
                          d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active, (const double*)nullptr,
                          c0v<T>(r));
     else
-      hipLaunchKernelGGL((k_strain_row<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, pp, W, d_qtab, g.n0,
+      BW_LAUNCH("k_strain_row_pcg", 0, (k_strain_row<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, pp, W,
+                d_qtab, g.n0,
                          g.n1, g.nvox, rt, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
   });
   launch_middle<T, 0>(r, W, nvec, (T)(1.0 / (double)g.nvox), active, s);
@@ -796,11 +832,16 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
     constexpr int n2c = decltype(N2)::value;
     RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1);
     if (mode == 0)
-      hipLaunchKernelGGL((k_row_div<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab, g.n0, g.n1,
+      BW_LAUNCH("k_row_div", nvec, (k_row_div<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab,
+                g.n0, g.n1,
                          g.nvox, rt, twiddles<T>(r, 2), active, (const cplx<T>*)nullptr, dummy, (T)scale);
     else
-      hipLaunchKernelGGL((k_row_div<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab, g.n0, g.n1,
+      BW_LAUNCH("k_row_div_pcg", 0, (k_row_div<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab,
+                g.n0, g.n1,
                          g.nvox, rt, twiddles<T>(r, 2), active, (const cplx<T>*)pp, *pd, (T)scale);
+    if (mode == 1)
+      hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_ALPHA, rt.tpv, *pd, (const int*)nullptr,
+                         (double*)nullptr, (double*)nullptr);
   });
 }
 
@@ -822,14 +863,16 @@ void apply_M_impl(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, doubl
   with_n(g.n2, [&](auto N2) {
     constexpr int n2c = decltype(N2)::value;
     RowTile rt = row_tile<T>(n2c, rows);
-    hipLaunchKernelGGL((k_row_plain<T, n2c, true>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, W, rt, (int)rows,
+    BW_LAUNCH("k_row_inv_mass", nvec, (k_row_plain<T, n2c, true>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, W, rt,
+              (int)rows,
                        twiddles<T>(r, 2), (const int*)nullptr);
   });
   launch_middle<T, 1>(r, W, nvec, (T)(scale / (double)g.nvox), nullptr, s, tab);
   with_n(g.n2, [&](auto N2) {
     constexpr int n2c = decltype(N2)::value;
     RowTile rt = row_tile<T>(n2c, rows);
-    hipLaunchKernelGGL((k_row_plain<T, n2c, false>), dim3(nvec * rt.tpv), dim3(NT), 0, s, (const cplx<T>*)W, y, rt,
+    BW_LAUNCH("k_row_fwd_mass", nvec, (k_row_plain<T, n2c, false>), dim3(nvec * rt.tpv), dim3(NT), 0, s,
+              (const cplx<T>*)W, y, rt,
                        (int)rows, twiddles<T>(r, 2), (const int*)nullptr);
   });
 }
@@ -866,8 +909,10 @@ void launch_pcg_update(const bw_rve* r, const double* d_qtab, cplx<T>* x, cplx<T
                        const cplx<T>* Ap, int nvec, const PcgDev& pd, hipStream_t s) {
   const Geom& g = r->g;
   const int bpv = pw_blocks(g.nvox);
-  hipLaunchKernelGGL((k_pcg_update<T>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
+  BW_LAUNCH("k_pcg_update", 0, (k_pcg_update<T>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
                      VoxIdx{g.n0, g.n1, g.n2}, g.nvox, bpv, c0v<T>(r), pd);
+  hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_BETA, bpv, pd, (const int*)nullptr,
+                     (double*)nullptr, (double*)nullptr);
 }
 
 template <typename T>
@@ -878,7 +923,25 @@ void launch_residual(const bw_rve* r, const double* d_qtab, const cplx<T>* b, co
   if (x) launch_apply_K<T>(r, d_qtab, x, tmp, nvec, 1.0, W, s);
   const int bpv = pw_blocks(g.nvox * 3);
   hipLaunchKernelGGL((k_residual<T>), dim3(nvec * bpv), dim3(NT), 0, s, b, x ? (const cplx<T>*)tmp : nullptr, rv,
-                     g.nvox * 3, bpv, d_rr, d_bb, d_partial, d_counter, max_blocks);
+                     g.nvox * 3, bpv, d_partial, max_blocks);
+  PcgDev pd{};
+  pd.partial = d_partial;
+  pd.max_blocks = max_blocks;
+  hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_RESID, bpv, pd, (const int*)nullptr, d_rr,
+                     d_bb);
+}
+
+template <typename T>
+void launch_norms2(const bw_rve* r, const cplx<T>* b, const cplx<T>* rv, int nvec, double* d_rr, double* d_bb,
+                   double* d_partial, int max_blocks, hipStream_t s) {
+  const Geom& g = r->g;
+  const int bpv = pw_blocks(g.nvox * 3);
+  hipLaunchKernelGGL((k_norms2<T>), dim3(nvec * bpv), dim3(NT), 0, s, b, rv, g.nvox * 3, bpv, d_partial, max_blocks);
+  PcgDev pd{};
+  pd.partial = d_partial;
+  pd.max_blocks = max_blocks;
+  hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_RESID, bpv, pd, (const int*)nullptr, d_rr,
+                     d_bb);
 }
 
 template <typename T>
@@ -888,6 +951,8 @@ void launch_pcg_restart(const bw_rve* r, const double* d_qtab, const cplx<T>* rv
   const int bpv = pw_blocks(g.nvox);
   hipLaunchKernelGGL((k_pcg_restart<T>), dim3(nvec * bpv), dim3(NT), 0, s, rv, d_qtab, VoxIdx{g.n0, g.n1, g.n2},
                      g.nvox, bpv, c0v<T>(r), pd, d_mask);
+  hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_RESTART, bpv, pd, d_mask, (double*)nullptr,
+                     (double*)nullptr);
 }
 
 template <typename T>
@@ -927,6 +992,8 @@ template <typename T> void zero_voxel(cplx<T>* x, int nvec, long nvox, long vox,
                                    cplx<T>*, cplx<T>*, int, double*, double*, double*, unsigned*, int, hipStream_t); \
   template void launch_pcg_restart<T>(const bw_rve*, const double*, const cplx<T>*, int, const PcgDev&, const int*, \
                                       hipStream_t);                                                                 \
+  template void launch_norms2<T>(const bw_rve*, const cplx<T>*, const cplx<T>*, int, double*, double*, double*, int, \
+                                 hipStream_t);                                                                      \
   template void scale_vectors<T>(cplx<T>*, size_t, double, hipStream_t);                                           \
   template void zero_voxel<T>(cplx<T>*, int, long, long, hipStream_t);
 

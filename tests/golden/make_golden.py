@@ -46,13 +46,16 @@ def run(name):
     rve = inputs.workload_rve(cfg, 0)
     ks = inputs.workload_kpoints(cfg)[idx]
     out = dict(name=name, config=cfg, nmodes=nmodes, block=block, tol_eig=1e-12, tol_lin=1e-12,
-               k_index=idx, k=ks.tolist(), omega=[], seconds=[])
+               k_index=idx, k=ks.tolist(), omega=[], seconds=[], pcg_iters=[], outer=[])
     path = os.path.join(HERE, f"{name}.json")
     for i, k in enumerate(ks):
         t = time.time()
+        st = []
         w = solvers.lowest_modes(rve, k[None], nmodes, method="subspace", block=block,
-                                 tol_eig=1e-12, tol_lin=1e-12, dense_max=0, warm_start=False)
+                                 tol_eig=1e-12, tol_lin=1e-12, dense_max=0, warm_start=False, stats=st)
         out["omega"].append(w[0].tolist())
+        out["pcg_iters"].append(int(st[0]["pcg_iters"]))
+        out["outer"].append(int(st[0]["outer"]))
         out["seconds"].append(time.time() - t)
         print(f"{name} k[{idx[i]}] {time.time() - t:.1f}s omega[:3]={w[0][:3]}", flush=True)
         with open(path, "w") as f:

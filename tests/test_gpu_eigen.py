@@ -96,8 +96,10 @@ def test_cu16_config_against_stored_oracle(lib, prec):
     ks = np.array(g["k"])[: len(w_o)]
     print(f"\n[case] cu16 config prec={prec}", flush=True)
     R = lib.Rve.from_inputs(rve, prec)
-    w, err, code, st = lib.bw_lowest_modes(R, ks, g["nmodes"], block=g["block"], tol_eig=1e-11, tol_lin=1e-10)
+    w, err, code, st = lib.bw_lowest_modes(R, ks, g["nmodes"], block=g["block"],
+                                           tol_eig=1e-11 if prec == 0 else 1e-7, tol_lin=1e-10)
     assert code == 0
+    assert err.max() <= (1e-9 if prec == 0 else 1e-6)
     e = _relerr(w, w_o, _omega_ref(rve))
     print(f"max rel err {e.max():.2e}; stats {st}", flush=True)
     assert e.max() <= BAR[prec]
