@@ -177,6 +177,9 @@ int bw_lowest_modes(bw_rve* rve, const double* k_list_host, int32_t nk, int32_t 
  * microseconds of event overhead per launch. */
 int bw_timing_enable(int32_t enable);
 
+/* Restricts the timing to the kernel of that name (NULL or "" = all kernels). */
+int bw_timing_filter(const char* kernel_name);
+
 /* Writes a JSON object {"kernel": {"launches": n, "ms": total, "units": u}}
  * into buf (len bytes, NUL-terminated, truncated if needed) after waiting for
  * the recorded events; `units` counts the vectors each kernel processed.

@@ -67,6 +67,7 @@ _SIGS = {
     "bw_last_error": (ctypes.c_char_p, []),
     "bw_timing_enable": (_I, [_I]),
     "bw_timing_report": (ctypes.c_int64, [ctypes.c_char_p, ctypes.c_int64]),
+    "bw_timing_filter": (_I, [ctypes.c_char_p]),
 }
 
 
@@ -99,6 +100,10 @@ def bw_last_error() -> str:
 
 def bw_timing_enable(enable: bool) -> None:
     lib().bw_timing_enable(int(bool(enable)))
+
+
+def bw_timing_filter(name) -> None:
+    lib().bw_timing_filter(name.encode() if name else None)
 
 
 def bw_timing_report() -> dict:

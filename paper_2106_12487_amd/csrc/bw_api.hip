@@ -30,6 +30,7 @@ struct Totals {
 };
 std::mutex g_tmu;
 std::atomic<bool> g_timing{false};
+std::string g_filter;  // time only this kernel name when non-empty
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::map<std::string, Totals> g_tot;
@@ -65,6 +66,7 @@ bool timing_enabled() { return g_timing.load(std::memory_order_relaxed); }
 KTimer::KTimer(const char* n, hipStream_t st, long u) : name(n), s(st), units(u) {
   if (!timing_enabled()) return;
   std::lock_guard<std::mutex> lk(g_tmu);
+  if (!g_filter.empty() && g_filter != n) return;
   e0 = pool_get();
   if (e0) (void)hipEventRecord(e0, s);
 }
@@ -79,6 +81,7 @@ KTimer::~KTimer() {
 void timing_add_units(const char* name, long units) {
   if (!timing_enabled()) return;
   std::lock_guard<std::mutex> lk(g_tmu);
+  if (!g_filter.empty() && g_filter != name) return;
   g_tot[name].units += units;
 }
 
@@ -327,6 +330,12 @@ extern "C" int bw_timing_enable(int32_t enable) {
   return BW_OK;
 }
 
+extern "C" int bw_timing_filter(const char* kernel_name) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_filter = kernel_name ? kernel_name : "";
+  return BW_OK;
+}
+
 extern "C" int64_t bw_timing_report(char* buf, int64_t len) {
   std::lock_guard<std::mutex> lk(g_tmu);
   drain_locked();
@@ -495,6 +504,9 @@ extern "C" void bw_destroy_rve(bw_rve* r) {
   r->ws_misc.release();
   r->ws64.release();
   r->ws32.release();
+  r->wl64.release();
+  r->wl32.release();
+  r->ws_q3.release();
   delete r;
 }
 

@@ -41,6 +41,26 @@ void launch_deflate(cplx<T>* X, cplx<T>* MX, const cplx<T>* MN, int nv, long nvo
 // plane-wave start vectors: vector p = pol[p] at voxel vox[p] (others zero)
 template <typename T>
 void launch_planewaves(cplx<T>* U, int nv, long nvox, const long* vox, const double* pol, hipStream_t s);
+// Per-k bases (batched Lanczos): basis vector i of wave vector k sits at
+// X + k * xk + i * xi; the batch vector of k at Y + k * yk.
+// out[k * ldo + i] = <X_k[i], Y_k> for i < J (skipped, left untouched, where act[k] == 0)
+template <typename T>
+void launch_mdot(const cplx<T>* X, long xk, long xi, int J, const cplx<T>* Y, long yk, int nk, long n,
+                 const int* act, double2* out, int ldo, DevBuf& scratch, hipStream_t s);
+// Y_k += sign * sum_{i < J} X_k[i] c[k * ldc + i]   (FP64 accumulation)
+template <typename T>
+void launch_mlincomb(cplx<T>* Y, long yk, const cplx<T>* X, long xk, long xi, int J, const double2* c, int ldc,
+                     double sign, int nk, long n, const int* act, hipStream_t s);
+// Y_k = sc[k] * X_k with independent strides
+template <typename T>
+void launch_scale_copy(const cplx<T>* X, long xk, cplx<T>* Y, long yk, const double* sc, int nk, long n,
+                       const int* act, hipStream_t s);
+
+// U[vec[e] * vstride + c * nvox + vox[e]] = val[3 e + c] (real) for e < nent
+template <typename T>
+void launch_set_entries(cplx<T>* U, long vstride, long nvox, int nent, const long* vec, const long* vox,
+                        const double* val, hipStream_t s);
+
 // small generalized Hermitian eigenproblem Kq z = lam Mq z (q <= GEIG_QMAX):
 // lam ascending, Q with Q^H Mq Q = I.  info[0] != 0 if Mq is not positive definite.
 void launch_small_geig(const double2* Kq, const double2* Mq, int q, double* lam, double2* Q, int* info,

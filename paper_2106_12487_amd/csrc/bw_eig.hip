@@ -476,6 +476,268 @@ static void write_modes(bw_rve* r, const KOut& ko, int nmodes, void* modes, int 
   BW_HIP(hipStreamSynchronize(s));
 }
 
+// ---------------------------------------------------------------------------
+// batched thick-restart shift-invert Lanczos (Sec. 3.3, implicitly restarted
+// Lanczos on the shifted-inverse operator).  Every wave vector of the batch
+// runs its own Lanczos process on OP = K(k)^-1 M in the M inner product with
+// full re-orthogonalization; the solves of one Lanczos step of all of them
+// share one batched PCG (one right-hand side per wave vector).  A restart
+// keeps the leading Ritz vectors and the residual direction (thick restart:
+// the same subspace as implicit restarts with the unwanted Ritz values as
+// exact shifts).  Converged wave vectors leave the batch.
+// ---------------------------------------------------------------------------
+template <typename T>
+static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, const EigOpts& o, double* omega,
+                         double* err, void* modes, int kofs, Counters& cnt, hipStream_t s) {
+  const Geom& g = r->g;
+  const long n3 = g.nvox * 3;
+  Small sm = small_bufs(r);
+  const bool fp32 = sizeof(T) == 4;
+  QTable qt = make_qtable(r, k_list, nk);
+  const double* dq = upload_qtable(r, qt, r->ws_q2, s);
+  std::vector<int> nwk(nk);
+  int nwmax = 0;
+  for (int k = 0; k < nk; ++k) {
+    nwk[k] = nmodes - (qt.null_index[k] >= 0 ? 3 : 0);
+    nwmax = std::max(nwmax, nwk[k]);
+  }
+  const int m = o.ncv > 0 ? o.ncv : std::max(2 * nwmax + 1, 20);
+  BW_REQUIRE(m <= GEIG_QMAX && m >= nwmax + 2, BW_EINVAL, "ncv must satisfy nmodes + 2 <= ncv <= 48");
+  const int kk = std::min({m - 1, nwmax + (m - nwmax) / 2, GRAM_QMAX});  // vectors kept at a restart
+  const int qsel = std::min(m, nwmax + 2);                                // Ritz vectors refined in FP64
+  Workspace<T>& w = wl<T>(r);
+  const long xk = (long)(m + 1) * n3;
+  cplx<T>* V = w.vec(0, (size_t)nk * xk);
+  cplx<T>* MV = w.vec(1, (size_t)nk * xk);
+  cplx<T>* B = w.vec(2, (size_t)nk * n3);
+  cplx<T>* X = w.vec(3, (size_t)nk * n3);
+  cplx<T>* MF = w.vec(4, (size_t)nk * n3);
+  cplx<T>* TMP = w.vec(5, (size_t)std::max(kk, qsel) * n3);
+  cplx<T>* MN = w.vec(6, (size_t)3 * n3);
+  cplx<T>* N3 = w.vec(7, (size_t)3 * n3);
+  const size_t hcount = (size_t)nk * (m + 1);
+  char* sb = (char*)w.v[8].get(2 * hcount * sizeof(double2) + nk * (sizeof(double) + sizeof(int)) + 1024);
+  double2* hd = (double2*)sb;
+  double2* hd2 = hd + hcount;
+  double* scd = (double*)(hd2 + hcount);
+  int* actd = (int*)(scd + nk);
+  long jcache = -1;
+  auto ensure_MN = [&](long j) {
+    if (j != jcache) {
+      rigid_MN<T>(r, j, N3, MN, sm, cnt, s);
+      jcache = j;
+    }
+  };
+  auto deflate_batch = [&](cplx<T>* Xb, cplx<T>* MXb, const std::vector<int>& act) {
+    for (int k = 0; k < nk; ++k)
+      if (act[k] && qt.null_index[k] >= 0) {
+        ensure_MN(qt.null_index[k]);
+        launch_deflate<T>(Xb + (size_t)k * n3, MXb + (size_t)k * n3, MN, 1, g.nvox, qt.null_index[k], sm.coef, s);
+      }
+  };
+  std::vector<int> act(nk, 1);
+  std::vector<double> sc(nk), beta(nk, 0.0), tolk(nk), best(nk, INFINITY);
+  for (int k = 0; k < nk; ++k) tolk[k] = fp32 ? std::max(o.tol_omega > 0 ? o.tol_omega : o.tol_eig, 1e-6)
+                                               : (o.tol_omega > 0 ? o.tol_omega : o.tol_eig);
+  const double bound_target = o.tol_omega > 0 ? o.tol_omega : 5.0 * o.tol_eig;
+  const double lscale = r->Cref / (r->rho_bar * r->ell * r->ell);
+  auto upload_act = [&]() { BW_HIP(hipMemcpyAsync(actd, act.data(), nk * sizeof(int), hipMemcpyHostToDevice, s)); };
+  auto upload_sc = [&]() { BW_HIP(hipMemcpyAsync(scd, sc.data(), nk * sizeof(double), hipMemcpyHostToDevice, s)); };
+
+  // start vectors: the lowest reference plane wave plus a little of the next three
+  BW_HIP(hipMemsetAsync(B, 0, (size_t)nk * n3 * sizeof(cplx<T>), s));
+  {
+    std::vector<long> vec, vox;
+    std::vector<double> val;
+    for (int k = 0; k < nk; ++k) {
+      QTable q1 = make_qtable(r, k_list + 3 * k, 1);
+      std::vector<long> vx;
+      std::vector<double> pl;
+      reference_start(r, q1, 4, vx, pl);
+      for (int e = 0; e < 4; ++e) {
+        vec.push_back(k);
+        vox.push_back(vx[e]);
+        for (int c = 0; c < 3; ++c) val.push_back(pl[3 * e + c] * (e == 0 ? 1.0 : 0.1));
+      }
+    }
+    for (size_t e0 = 0; e0 < vec.size(); e0 += 80) {
+      const int ne = (int)std::min<size_t>(80, vec.size() - e0);
+      BW_HIP(hipMemcpyAsync(sm.vox, vox.data() + e0, ne * sizeof(long), hipMemcpyHostToDevice, s));
+      BW_HIP(hipMemcpyAsync(sm.pol, val.data() + 3 * e0, 3 * ne * sizeof(double), hipMemcpyHostToDevice, s));
+      BW_HIP(hipMemcpyAsync(sm.vox + 128, vec.data() + e0, ne * sizeof(long), hipMemcpyHostToDevice, s));
+      launch_set_entries<T>(B, n3, g.nvox, ne, sm.vox + 128, sm.vox, sm.pol, s);
+      BW_HIP(hipStreamSynchronize(s));
+    }
+  }
+  apply_M_blk<T>(r, B, MF, nk, false, cnt, s);
+  deflate_batch(B, MF, act);
+  launch_dots<T>(B, MF, nk, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
+  std::vector<double2> bb(nk);
+  BW_HIP(hipMemcpyAsync(bb.data(), sm.dots, nk * sizeof(double2), hipMemcpyDeviceToHost, s));
+  BW_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < nk; ++k) sc[k] = 1.0 / std::sqrt(bb[k].x);
+  upload_sc();
+  launch_scale_copy<T>(B, n3, V, xk, scd, nk, n3, nullptr, s);
+  launch_scale_copy<T>(MF, n3, MV, xk, scd, nk, n3, nullptr, s);
+
+  std::vector<std::vector<double>> H(nk, std::vector<double>((size_t)m * m, 0.0));
+  std::vector<double2> hh(hcount), hh2(hcount);
+  std::vector<double> Hd((size_t)m * m * 2), Id((size_t)m * m * 2, 0.0), thv(m);
+  std::vector<double2> Sm((size_t)m * m);
+  for (int i = 0; i < m; ++i) Id[2 * (i * m + i)] = 1.0;
+  int j0 = 0;
+  int status = BW_OK;
+  int cycles = 0;
+  for (;;) {
+    int nact = 0;
+    for (int k = 0; k < nk; ++k) nact += act[k];
+    if (nact == 0) break;
+    upload_act();
+    for (int j = j0; j < m; ++j) {
+      // B_k = M v_j (zero for finished wave vectors), X = K^-1 B
+      for (int k = 0; k < nk; ++k) sc[k] = act[k] ? 1.0 : 0.0;
+      upload_sc();
+      launch_scale_copy<T>(MV + (size_t)j * n3, xk, B, n3, scd, nk, n3, nullptr, s);
+      BW_HIP(hipMemsetAsync(X, 0, (size_t)nk * n3 * sizeof(cplx<T>), s));
+      PcgResult pr = pcg_run<T>(r, dq, qt, B, X, nk, fp32 ? std::max(o.tol_lin, 1e-6) : o.tol_lin, o.maxit_lin,
+                                true, s, false, false);
+      cnt.pcg_iters += pr.total_iters;
+      cnt.block_iters += pr.block_iters;
+      cnt.kap += pr.k_applies;
+      // full re-orthogonalization (twice) in the M inner product
+      launch_mdot<T>(MV, xk, n3, j + 1, X, n3, nk, n3, actd, hd, m + 1, r->ws_red, s);
+      launch_mlincomb<T>(X, n3, V, xk, n3, j + 1, hd, m + 1, -1.0, nk, n3, actd, s);
+      launch_mdot<T>(MV, xk, n3, j + 1, X, n3, nk, n3, actd, hd2, m + 1, r->ws_red, s);
+      launch_mlincomb<T>(X, n3, V, xk, n3, j + 1, hd2, m + 1, -1.0, nk, n3, actd, s);
+      apply_M_blk<T>(r, X, MF, nk, false, cnt, s);
+      deflate_batch(X, MF, act);
+      launch_dots<T>(X, MF, nk, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
+      BW_HIP(hipMemcpyAsync(hh.data(), hd, hcount * sizeof(double2), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipMemcpyAsync(hh2.data(), hd2, hcount * sizeof(double2), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipMemcpyAsync(bb.data(), sm.dots, nk * sizeof(double2), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipStreamSynchronize(s));
+      for (int k = 0; k < nk; ++k) {
+        if (!act[k]) {
+          sc[k] = 0.0;
+          continue;
+        }
+        for (int i = 0; i <= j; ++i) {
+          const double h = hh[(size_t)k * (m + 1) + i].x + hh2[(size_t)k * (m + 1) + i].x;
+          H[k][(size_t)i * m + j] = h;
+          H[k][(size_t)j * m + i] = h;
+        }
+        beta[k] = std::sqrt(std::max(bb[k].x, 0.0));
+        if (j + 1 < m) {
+          H[k][(size_t)(j + 1) * m + j] = beta[k];
+          H[k][(size_t)j * m + j + 1] = beta[k];
+        }
+        sc[k] = beta[k] > 0 ? 1.0 / beta[k] : 0.0;
+      }
+      upload_sc();
+      launch_scale_copy<T>(X, n3, V + (size_t)(j + 1) * n3, xk, scd, nk, n3, actd, s);
+      launch_scale_copy<T>(MF, n3, MV + (size_t)(j + 1) * n3, xk, scd, nk, n3, actd, s);
+    }
+    ++cycles;
+    cnt.outer += 1;
+    // projected eigenproblems, convergence, restart
+    for (int k = 0; k < nk; ++k) {
+      if (!act[k]) continue;
+      for (size_t i = 0; i < (size_t)m * m; ++i) {
+        Hd[2 * i] = H[k][i];
+        Hd[2 * i + 1] = 0.0;
+      }
+      BW_HIP(hipMemcpyAsync(sm.Kq, Hd.data(), m * m * sizeof(double2), hipMemcpyHostToDevice, s));
+      BW_HIP(hipMemcpyAsync(sm.Mq, Id.data(), m * m * sizeof(double2), hipMemcpyHostToDevice, s));
+      launch_small_geig(sm.Kq, sm.Mq, m, sm.lam, sm.Q, sm.info, s);
+      BW_HIP(hipMemcpyAsync(thv.data(), sm.lam, m * sizeof(double), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipMemcpyAsync(Sm.data(), sm.Q, m * m * sizeof(double2), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipStreamSynchronize(s));
+      const int nw = nwk[k];
+      bool conv = true;
+      double worst = 0;
+      for (int i = 0; i < nw; ++i) {
+        const int c = m - 1 - i;  // largest theta first
+        const double res = beta[k] * std::hypot(Sm[(size_t)(m - 1) * m + c].x, Sm[(size_t)(m - 1) * m + c].y);
+        worst = std::max(worst, res / std::fabs(thv[c]));
+        if (res > tolk[k] * std::fabs(thv[c])) conv = false;
+      }
+      if (verbose())
+        fprintf(stderr, "[bw] lanczos k#%d cycle %d worst |beta s|/theta %.3e\n", kofs + k, cycles, worst);
+      const bool last = cycles >= o.maxit_outer;
+      if (conv || last) {
+        // Ritz vectors of the wanted (and two more) values, then FP64 Rayleigh-Ritz and bounds
+        std::vector<double2> Qs((size_t)m * qsel);
+        for (int p = 0; p < m; ++p)
+          for (int c = 0; c < qsel; ++c) Qs[(size_t)p * qsel + c] = Sm[(size_t)p * m + (m - 1 - c)];
+        BW_HIP(hipMemcpyAsync(sm.Q, Qs.data(), Qs.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+        cplx<double>* U64 = ws<double>(r).vec(3, (size_t)qsel * n3);
+        if (fp32) {
+          launch_ritz<T>(V + (size_t)k * xk, m, sm.Q, qsel, TMP, qsel, n3, n3, s);
+          launch_convert<float, double>((const cplx<float>*)TMP, U64, (size_t)qsel * n3, s);
+        } else {
+          launch_ritz<T>(V + (size_t)k * xk, m, sm.Q, qsel, (cplx<T>*)U64, qsel, n3, n3, s);
+        }
+        std::vector<double> k1((size_t)qsel * 3);
+        for (int v = 0; v < qsel; ++v)
+          for (int a = 0; a < 3; ++a) k1[3 * v + a] = k_list[3 * k + a];
+        QTable qk = make_qtable(r, k1.data(), qsel);
+        const double* dqk = upload_qtable(r, qk, r->ws_q3, s);
+        std::vector<double> lam64, bnd;
+        rr64_bounds(r, dqk, U64, qsel, nw, lam64, bnd, true, nullptr, nullptr, cnt, s);
+        const double wb = nw > 0 ? *std::max_element(bnd.begin(), bnd.end()) : 0.0;
+        if (verbose()) fprintf(stderr, "[bw] lanczos k#%d FP64 bound %.3e\n", kofs + k, wb);
+        const bool stalled = wb > 0.5 * best[k];  // the bound stopped improving (precision floor)
+        best[k] = std::min(best[k], wb);
+        if (wb <= bound_target || last || stalled) {
+          if (wb > bound_target) status = BW_ENOTCONV;
+          KOut ko;
+          ko.n_want = nw;
+          ko.jstar = qt.null_index[k];
+          ko.lam.assign(lam64.begin(), lam64.begin() + nw);
+          ko.bound = bnd;
+          const int ik = kofs + k;
+          int off = 0;
+          if (ko.jstar >= 0) {
+            for (int i = 0; i < 3; ++i) {
+              omega[ik * nmodes + i] = 0.0;
+              if (err) err[ik * nmodes + i] = 0.0;
+            }
+            off = 3;
+          }
+          for (int p = 0; p < nw; ++p) {
+            omega[ik * nmodes + off + p] = std::sqrt(std::max(ko.lam[p], 0.0) * lscale);
+            if (err) err[ik * nmodes + off + p] = ko.bound[p];
+          }
+          write_modes<T>(r, ko, nmodes, modes, ik, s);
+          act[k] = 0;
+          continue;
+        }
+        tolk[k] *= 0.1;  // tighten and keep iterating this wave vector
+      }
+      // thick restart: keep the kk leading Ritz vectors and the residual direction
+      std::vector<double2> Qk((size_t)m * kk);
+      for (int p = 0; p < m; ++p)
+        for (int c = 0; c < kk; ++c) Qk[(size_t)p * kk + c] = Sm[(size_t)p * m + (m - 1 - c)];
+      BW_HIP(hipMemcpyAsync(sm.Q, Qk.data(), Qk.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+      cplx<T>* Vk = V + (size_t)k * xk;
+      cplx<T>* MVk = MV + (size_t)k * xk;
+      launch_ritz<T>(Vk, m, sm.Q, kk, TMP, kk, n3, n3, s);
+      BW_HIP(hipMemcpyAsync(Vk, TMP, (size_t)kk * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
+      launch_ritz<T>(MVk, m, sm.Q, kk, TMP, kk, n3, n3, s);
+      BW_HIP(hipMemcpyAsync(MVk, TMP, (size_t)kk * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
+      BW_HIP(hipMemcpyAsync(Vk + (size_t)kk * n3, Vk + (size_t)m * n3, n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice,
+                            s));
+      BW_HIP(hipMemcpyAsync(MVk + (size_t)kk * n3, MVk + (size_t)m * n3, n3 * sizeof(cplx<T>),
+                            hipMemcpyDeviceToDevice, s));
+      std::fill(H[k].begin(), H[k].end(), 0.0);
+      for (int c = 0; c < kk; ++c) H[k][(size_t)c * m + c] = thv[m - 1 - c];
+      BW_HIP(hipStreamSynchronize(s));
+    }
+    j0 = kk;
+  }
+  return status;
+}
+
 template <typename T>
 static int lowest_modes_impl(bw_rve* r, const double* k_list, int nk, int nmodes, const EigOpts& o, double* omega,
                              double* err, void* modes, Counters& cnt, hipStream_t s) {
@@ -536,19 +798,34 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
     if (o.maxit_lin <= 0) o.maxit_lin = 20000;
     if (o.tol_eig <= 0) o.tol_eig = 1e-10;
     if (o.tol_lin <= 0) o.tol_lin = r->precision == BW_FP64 ? 1e-10 : 1e-6;
-    BW_REQUIRE(o.block > nmodes && o.block <= GRAM_QMAX, BW_EINVAL, "block must satisfy nmodes < block <= 32");
-    BW_REQUIRE((long)o.block <= 3 * r->g.nvox, BW_EINVAL, "block larger than the number of degrees of freedom");
-    if (o.method == BW_LANCZOS) {
-      set_error("bw_lowest_modes: the Lanczos driver is not available in this build");
-      return BW_EUNSUPPORTED;
+    if (o.method == BW_SUBSPACE) {
+      BW_REQUIRE(o.block > nmodes && o.block <= GRAM_QMAX, BW_EINVAL, "block must satisfy nmodes < block <= 32");
+      BW_REQUIRE((long)o.block <= 3 * r->g.nvox, BW_EINVAL, "block larger than the number of degrees of freedom");
     }
     hipStream_t s = (hipStream_t)stream;
     r->ws_red.get(16u << 20);
     r->ws_red2.get(16u << 20);
     Counters cnt;
     auto t0 = std::chrono::steady_clock::now();
-    int st = r->precision == BW_FP64 ? lowest_modes_impl<double>(r, k_list, nk, nmodes, o, omega, err, modes, cnt, s)
-                                     : lowest_modes_impl<float>(r, k_list, nk, nmodes, o, omega, err, modes, cnt, s);
+    int st = BW_OK;
+    if (o.method == BW_LANCZOS) {
+      // wave vectors per batch: the bases (2 (ncv + 1) vectors each) within ~48 GB
+      const int nwm = nmodes;
+      const int m = o.ncv > 0 ? o.ncv : std::max(2 * nwm + 1, 20);
+      const double vbytes = (double)r->g.nvox * 3 * (r->precision == BW_FP64 ? 16 : 8);
+      int kb = (int)std::max(1.0, std::floor(48e9 / (vbytes * (2.0 * (m + 1) + 3))));
+      kb = std::min({kb, nk, 64});
+      for (int k0 = 0; k0 < nk; k0 += kb) {
+        const int nb = std::min(kb, nk - k0);
+        const int s1 = r->precision == BW_FP64
+                           ? lanczos_batch<double>(r, k_list + 3 * k0, nb, nmodes, o, omega, err, modes, k0, cnt, s)
+                           : lanczos_batch<float>(r, k_list + 3 * k0, nb, nmodes, o, omega, err, modes, k0, cnt, s);
+        if (s1 != BW_OK) st = s1;
+      }
+    } else {
+      st = r->precision == BW_FP64 ? lowest_modes_impl<double>(r, k_list, nk, nmodes, o, omega, err, modes, cnt, s)
+                                   : lowest_modes_impl<float>(r, k_list, nk, nmodes, o, omega, err, modes, cnt, s);
+    }
     BW_HIP(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
     if (stats) {

@@ -19,19 +19,22 @@ template <> __device__ __forceinline__ cplx<double> from_d2<double>(double2 v) {
 // register r of lane l.  Re(X^H Y) = Xr^T Yr + Xi^T Yi and
 // Im(X^H Y) = Xr^T Yi - Xi^T Yr: four MFMAs per 4-row step and 16x16 block.
 // ---------------------------------------------------------------------------
-constexpr int GKC = 64;  // rows per LDS tile (16 per wave)
+constexpr int GKC = 64;  // rows per wave step (16 MFMA k-steps of 4 rows)
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram(const cplx<T>* __restrict__ X, int qx, const cplx<T>* __restrict__ Y,
                                               int qy, long n, long vstride, long rows_per_blk,
                                               double* __restrict__ partial) {
-  __shared__ double2 smem[2 * GRAM_QMAX * (GKC + 1)];
-  double2* Xs = smem;
-  double2* Ys = smem + GRAM_QMAX * (GKC + 1);
+  __shared__ double red[4 * 2 * GRAM_QMAX * GRAM_QMAX];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long r0 = (long)blockIdx.x * rows_per_blk;
   const long r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
-  const int qm = qx > qy ? qx : qy;
+  const int col = lane & 15, kk = lane >> 4;
+  const bool hx0 = col < qx, hx1 = col + 16 < qx, hy0 = col < qy, hy1 = col + 16 < qy;
+  const cplx<T>* x0 = X + (size_t)col * vstride;
+  const cplx<T>* x1 = X + (size_t)(col + 16) * vstride;
+  const cplx<T>* y0 = Y + (size_t)col * vstride;
+  const cplx<T>* y1 = Y + (size_t)(col + 16) * vstride;
   d4_t accr[2][2], acci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -40,40 +43,34 @@ __global__ __launch_bounds__(256) void k_gram(const cplx<T>* __restrict__ X, int
       accr[a][b] = d4_t{0, 0, 0, 0};
       acci[a][b] = d4_t{0, 0, 0, 0};
     }
-  for (long t0 = r0; t0 < r1; t0 += GKC) {
-    for (int idx = tid; idx < qm * GKC; idx += 256) {
-      const int p = idx / GKC, k = idx - p * GKC;
-      const long e = t0 + k;
+  // the four waves interleave 4-row steps; operands come straight from global
+  // memory (consecutive steps of a wave reuse the same cache lines)
+  for (long e0 = r0 + wave * 4; e0 < r1; e0 += 16 * 4) {
+    double2 a[4][2], bb[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long e = e0 + (long)u * 16 + kk;
       const bool in = e < r1;
-      Xs[p * (GKC + 1) + k] = (p < qx && in) ? to_d2(X[(size_t)p * vstride + e]) : make_double2(0, 0);
-      Ys[p * (GKC + 1) + k] = (p < qy && in) ? to_d2(Y[(size_t)p * vstride + e]) : make_double2(0, 0);
+      a[u][0] = (in && hx0) ? to_d2(x0[e]) : make_double2(0, 0);
+      a[u][1] = (in && hx1) ? to_d2(x1[e]) : make_double2(0, 0);
+      bb[u][0] = (in && hy0) ? to_d2(y0[e]) : make_double2(0, 0);
+      bb[u][1] = (in && hy1) ? to_d2(y1[e]) : make_double2(0, 0);
     }
-    for (int idx = qm * GKC + tid; idx < GRAM_QMAX * GKC; idx += 256) {
-      const int p = idx / GKC, k = idx - p * GKC;
-      Xs[p * (GKC + 1) + k] = make_double2(0, 0);
-      Ys[p * (GKC + 1) + k] = make_double2(0, 0);
-    }
-    __syncthreads();
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int kb = wave * 16 + st * 4 + (lane >> 4);
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int bp = 0; bp < 2; ++bp) {
-        const double2 a = Xs[(bp * 16 + (lane & 15)) * (GKC + 1) + kb];
+      for (int bp = 0; bp < 2; ++bp)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-          const double2 b = Ys[(bj * 16 + (lane & 15)) * (GKC + 1) + kb];
-          accr[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accr[bp][bj], 0, 0, 0);
-          accr[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, accr[bp][bj], 0, 0, 0);
-          acci[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acci[bp][bj], 0, 0, 0);
-          acci[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.x, acci[bp][bj], 0, 0, 0);
+          if ((bp == 1 && qx <= 16) || (bj == 1 && qy <= 16)) continue;
+          const double2 av = a[u][bp], bv = bb[u][bj];
+          accr[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, accr[bp][bj], 0, 0, 0);
+          accr[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, accr[bp][bj], 0, 0, 0);
+          acci[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, acci[bp][bj], 0, 0, 0);
+          acci[bp][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.x, acci[bp][bj], 0, 0, 0);
         }
-      }
-    }
-    __syncthreads();
   }
   // sum the four waves' partial blocks through LDS
-  double* red = reinterpret_cast<double*>(smem);
   const int nq = qx * qy;
 #pragma unroll
   for (int bp = 0; bp < 2; ++bp)
@@ -92,14 +89,16 @@ __global__ __launch_bounds__(256) void k_gram(const cplx<T>* __restrict__ X, int
     partial[(size_t)blockIdx.x * 2 * nq + t] = red[t] + red[2 * nq + t] + red[4 * nq + t] + red[6 * nq + t];
 }
 
-// second phase of the Gram product: sum the per-block partials in block order
+// second phase of the Gram product: one workgroup per matrix entry sums the
+// per-block partials in block order
 __global__ __launch_bounds__(256) void k_gram_finalize(const double* __restrict__ partial, int nblk, int n2q,
                                                        double* __restrict__ G) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= n2q) return;
+  __shared__ double sh[4];
+  const int t = blockIdx.x;
   double acc = 0;
-  for (int b = 0; b < nblk; ++b) acc += partial[(size_t)b * n2q + t];
-  G[t] = acc;
+  for (int b = threadIdx.x; b < nblk; b += 256) acc += partial[(size_t)b * n2q + t];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) G[t] = acc;
 }
 
 template <typename T>
@@ -107,7 +106,7 @@ void launch_gram(const cplx<T>* X, int qx, const cplx<T>* Y, int qy, long n, lon
                  DevBuf& scratch, unsigned* counter, hipStream_t s) {
   BW_REQUIRE(qx >= 1 && qy >= 1 && qx <= GRAM_QMAX && qy <= GRAM_QMAX, BW_EINVAL, "Gram block exceeds 32 vectors");
   long nblk = (n + 4 * GKC - 1) / (4 * GKC);
-  if (nblk > 1024) nblk = 1024;
+  if (nblk > 512) nblk = 512;
   if (nblk < 1) nblk = 1;
   long rows = (n + nblk - 1) / nblk;
   rows = (rows + GKC - 1) / GKC * GKC;
@@ -117,8 +116,7 @@ void launch_gram(const cplx<T>* X, int qx, const cplx<T>* Y, int qy, long n, lon
   BW_LAUNCH("k_gram_mfma", (long)qx * qy, (k_gram<T>), dim3((unsigned)nblk), dim3(256), 0, s, X, qx, Y, qy, n,
             vstride, rows, (double*)base);
   const int n2q = 2 * qx * qy;
-  hipLaunchKernelGGL(k_gram_finalize, dim3((n2q + 255) / 256), dim3(256), 0, s, (const double*)base, (int)nblk, n2q,
-                     (double*)G);
+  hipLaunchKernelGGL(k_gram_finalize, dim3(n2q), dim3(256), 0, s, (const double*)base, (int)nblk, n2q, (double*)G);
   (void)counter;
 }
 
@@ -555,6 +553,120 @@ void launch_small_geig(const double2* Kq, const double2* Mq, int q, double* lam,
   hipLaunchKernelGGL(k_small_geig, dim3(1), dim3(64), 0, s, Kq, Mq, q, lam, Q, info);
 }
 
+// ---------------------------------------------------------------------------
+// batched per-k basis products (Lanczos)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mdot(const cplx<T>* __restrict__ X, long xk, long xi,
+                                             const cplx<T>* __restrict__ Y, long yk, long n, const int* act,
+                                             double* partial, int bpv) {
+  __shared__ double sh[NT / 64];
+  const int b = blockIdx.x, i = blockIdx.y, k = blockIdx.z;
+  if (act && !act[k]) return;
+  const cplx<T>* x = X + (size_t)k * xk + (size_t)i * xi;
+  const cplx<T>* y = Y + (size_t)k * yk;
+  double sr = 0, si = 0;
+  for (long e = (long)b * NT + threadIdx.x; e < n; e += (long)bpv * NT) {
+    const double2 a = to_d2(x[e]), c = to_d2(y[e]);
+    sr += a.x * c.x + a.y * c.y;
+    si += a.x * c.y - a.y * c.x;
+  }
+  const double vals[2] = {sr, si};
+  store_partials<2>(vals, partial, (int)(k * gridDim.y + i), b, bpv, sh);
+}
+
+__global__ __launch_bounds__(NT) void k_mdot_finalize(const double* __restrict__ partial, int bpv, int J,
+                                                      const int* act, double2* out, int ldo) {
+  __shared__ double sh[NT / 64];
+  const int idx = blockIdx.x;  // k * J + i
+  const int k = idx / J, i = idx - k * J;
+  if (act && !act[k]) return;
+  double tot[2];
+  sum_partials<2>(tot, partial, idx, bpv, bpv, sh);
+  if (threadIdx.x == 0) out[(size_t)k * ldo + i] = make_double2(tot[0], tot[1]);
+}
+
+template <typename T>
+void launch_mdot(const cplx<T>* X, long xk, long xi, int J, const cplx<T>* Y, long yk, int nk, long n,
+                 const int* act, double2* out, int ldo, DevBuf& scratch, hipStream_t s) {
+  if (J <= 0 || nk <= 0) return;
+  int bpv = pw_blocks(n);
+  if (bpv > 256) bpv = 256;
+  double* partial = (double*)scratch.get((size_t)nk * J * bpv * 2 * sizeof(double));
+  BW_LAUNCH("k_mdot", (long)nk * J, (k_mdot<T>), dim3(bpv, J, nk), dim3(NT), 0, s, X, xk, xi, Y, yk, n, act, partial,
+            bpv);
+  hipLaunchKernelGGL(k_mdot_finalize, dim3(nk * J), dim3(NT), 0, s, (const double*)partial, bpv, J, act, out, ldo);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mlincomb(cplx<T>* __restrict__ Y, long yk, const cplx<T>* __restrict__ X,
+                                                  long xk, long xi, int J, const double2* __restrict__ c, int ldc,
+                                                  double sign, long n, const int* act) {
+  const int k = blockIdx.z;
+  if (act && !act[k]) return;
+  const cplx<T>* x = X + (size_t)k * xk;
+  cplx<T>* y = Y + (size_t)k * yk;
+  const double2* ck = c + (size_t)k * ldc;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+    double ar = 0, ai = 0;
+    for (int i = 0; i < J; ++i) {
+      const double2 a = to_d2(x[(size_t)i * xi + e]);
+      const double2 cc = ck[i];
+      ar += a.x * cc.x - a.y * cc.y;
+      ai += a.x * cc.y + a.y * cc.x;
+    }
+    const double2 o = to_d2(y[e]);
+    y[e] = from_d2<T>(make_double2(o.x + sign * ar, o.y + sign * ai));
+  }
+}
+
+template <typename T>
+void launch_mlincomb(cplx<T>* Y, long yk, const cplx<T>* X, long xk, long xi, int J, const double2* c, int ldc,
+                     double sign, int nk, long n, const int* act, hipStream_t s) {
+  if (J <= 0 || nk <= 0) return;
+  long nb = (n + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  BW_LAUNCH("k_mlincomb", (long)nk * J, (k_mlincomb<T>), dim3((unsigned)nb, 1, nk), dim3(256), 0, s, Y, yk, X, xk,
+            xi, J, c, ldc, sign, n, act);
+}
+
+template <typename T>
+__global__ void k_scale_copy(const cplx<T>* __restrict__ X, long xk, cplx<T>* __restrict__ Y, long yk,
+                             const double* __restrict__ sc, long n, const int* act) {
+  const int k = blockIdx.y;
+  if (act && !act[k]) return;
+  const double f = sc[k];
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const double2 a = to_d2(X[(size_t)k * xk + e]);
+    Y[(size_t)k * yk + e] = from_d2<T>(make_double2(a.x * f, a.y * f));
+  }
+}
+
+template <typename T>
+void launch_scale_copy(const cplx<T>* X, long xk, cplx<T>* Y, long yk, const double* sc, int nk, long n,
+                       const int* act, hipStream_t s) {
+  if (nk <= 0) return;
+  long nb = (n + 255) / 256;
+  if (nb > 512) nb = 512;
+  hipLaunchKernelGGL((k_scale_copy<T>), dim3((unsigned)nb, nk), dim3(256), 0, s, X, xk, Y, yk, sc, n, act);
+}
+
+template <typename T>
+__global__ void k_set_entries(cplx<T>* U, long vstride, long nvox, int nent, const long* vec, const long* vox,
+                              const double* val) {
+  const int t = threadIdx.x;
+  if (t >= nent * 3) return;
+  const int e = t / 3, c = t - 3 * e;
+  U[(size_t)vec[e] * vstride + (size_t)c * nvox + vox[e]] = from_d2<T>(make_double2(val[t], 0.0));
+}
+
+template <typename T>
+void launch_set_entries(cplx<T>* U, long vstride, long nvox, int nent, const long* vec, const long* vox,
+                        const double* val, hipStream_t s) {
+  BW_REQUIRE(nent * 3 <= 256, BW_EINVAL, "too many entries");
+  hipLaunchKernelGGL((k_set_entries<T>), dim3(1), dim3(256), 0, s, U, vstride, nvox, nent, vec, vox, val);
+}
+
 #define BW_INST_BLOCK(T)                                                                                          \
   template void launch_gram<T>(const cplx<T>*, int, const cplx<T>*, int, long, long, double2*, DevBuf&,            \
                                unsigned*, hipStream_t);                                                                      \
@@ -565,7 +677,15 @@ void launch_small_geig(const double2* Kq, const double2* Mq, int q, double* lam,
                                   hipStream_t);                                                                   \
   template void launch_scale_cols<T>(const cplx<T>*, const double*, cplx<T>*, int, long, long, hipStream_t);      \
   template void launch_deflate<T>(cplx<T>*, cplx<T>*, const cplx<T>*, int, long, long, double2*, hipStream_t);    \
-  template void launch_planewaves<T>(cplx<T>*, int, long, const long*, const double*, hipStream_t);
+  template void launch_planewaves<T>(cplx<T>*, int, long, const long*, const double*, hipStream_t);             \
+  template void launch_mdot<T>(const cplx<T>*, long, long, int, const cplx<T>*, long, int, long, const int*,      \
+                               double2*, int, DevBuf&, hipStream_t);                                                   \
+  template void launch_mlincomb<T>(cplx<T>*, long, const cplx<T>*, long, long, int, const double2*, int, double,   \
+                                   int, long, const int*, hipStream_t);                                           \
+  template void launch_scale_copy<T>(const cplx<T>*, long, cplx<T>*, long, const double*, int, long, const int*,  \
+                                     hipStream_t);                                                                \
+  template void launch_set_entries<T>(cplx<T>*, long, long, int, const long*, const long*, const double*,        \
+                                      hipStream_t);
 
 BW_INST_BLOCK(double)
 BW_INST_BLOCK(float)

@@ -149,6 +149,9 @@ struct bw_rve {
   bw::DevBuf ws_q, ws_q2, ws_pcg, ws_misc, ws_red, ws_red2;
   bw::Workspace<double> ws64;
   bw::Workspace<float> ws32;
+  bw::Workspace<double> wl64;  // Lanczos bases
+  bw::Workspace<float> wl32;
+  bw::DevBuf ws_q3;
   double qcache_k[3] = {0, 0, 0};
   int qcache_nvec = -1;
   int pcg_counters_nvec = 0;
@@ -220,6 +223,9 @@ template <typename T> void zero_voxel(cplx<T>* x, int nvec, long nvox, long vox,
 template <typename T> Workspace<T>& ws(bw_rve* r);
 template <> inline Workspace<double>& ws<double>(bw_rve* r) { return r->ws64; }
 template <> inline Workspace<float>& ws<float>(bw_rve* r) { return r->ws32; }
+template <typename T> Workspace<T>& wl(bw_rve* r);
+template <> inline Workspace<double>& wl<double>(bw_rve* r) { return r->wl64; }
+template <> inline Workspace<float>& wl<float>(bw_rve* r) { return r->wl32; }
 PcgDev pcg_dev(bw_rve* r, int nvec);
 const double* upload_qtable(bw_rve* r, const QTable& t, DevBuf& buf, hipStream_t s);
 double K_scale(const bw_rve* r);

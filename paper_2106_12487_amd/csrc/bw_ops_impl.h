@@ -428,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_row_plain(const cplx<T>* __restrict__ sr
 // (plane, column) with plane = (component, i0); a tile holds LT consecutive
 // lines (within one plane, or whole consecutive planes).
 // ---------------------------------------------------------------------------
-template <typename T, int N1, bool INV>
+template <typename T, int N1, bool INV, int PCG = 0>
 __global__ __launch_bounds__(NT) void k_axis1(cplx<T>* __restrict__ X, int n2, long vec_stride, ColTile ct,
                                               const cplx<T>* __restrict__ tw, const int* __restrict__ active) {
   using V = cplx<T>;
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(NT) void k_axis1(cplx<T>* __restrict__ X, int n2, l
 // OP 0: stiffness contraction on 6 Voigt components (Ctab: G x 21).
 // OP 1: density scaling on 3 components (Ctab: G densities).
 // ---------------------------------------------------------------------------
-template <typename T, int N0, int OP>
+template <typename T, int N0, int OP, int PCG = 0>
 __global__ __launch_bounds__(NT) void k_axis0_op(cplx<T>* __restrict__ X, long n12, long nvox, ColTile ct,
                                                  const uint16_t* __restrict__ gmap, const T* __restrict__ Ctab,
                                                  T scale, const cplx<T>* __restrict__ tw,
@@ -786,24 +786,34 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
   if (g.n1 > 1) {
     with_n(g.n1, [&](auto N1) {
       ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2);
-      BW_LAUNCH(OP == 0 ? (active ? "k_axis1_inv_pcg" : "k_axis1_inv") : "k_axis1_inv_mass", active ? 0 : nvec,
-                (k_axis1<T, decltype(N1)::value, true>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2,
-                         (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
+      if (active)
+        BW_LAUNCH("k_axis1_inv_pcg", 0, (k_axis1<T, decltype(N1)::value, true, 1>), dim3(nvec * ct.tpv), dim3(NT),
+                  0, s, W, g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
+      else
+        BW_LAUNCH(OP == 0 ? "k_axis1_inv" : "k_axis1_inv_mass", nvec, (k_axis1<T, decltype(N1)::value, true>),
+                  dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
     });
   }
   with_n(g.n0, [&](auto N0) {
     ColTile ct = axis0_tile<T>(N0, n12);
     const T* tab = tab_override ? tab_override : (OP == 0 ? ctab<T>(r) : rhotab<T>(r));
-    BW_LAUNCH(OP == 0 ? (active ? "k_axis0_contract_pcg" : "k_axis0_contract") : "k_axis0_mass", active ? 0 : nvec,
-              (k_axis0_op<T, decltype(N0)::value, OP>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, n12,
-                       g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+    if (active)
+      BW_LAUNCH("k_axis0_contract_pcg", 0, (k_axis0_op<T, decltype(N0)::value, OP, 1>), dim3(nvec * ct.tpv),
+                dim3(NT), 0, s, W, n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+    else
+      BW_LAUNCH(OP == 0 ? "k_axis0_contract" : "k_axis0_mass", nvec, (k_axis0_op<T, decltype(N0)::value, OP>),
+                dim3(nvec * ct.tpv), dim3(NT), 0, s, W, n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0),
+                active);
   });
   if (g.n1 > 1) {
     with_n(g.n1, [&](auto N1) {
       ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2);
-      BW_LAUNCH(OP == 0 ? (active ? "k_axis1_fwd_pcg" : "k_axis1_fwd") : "k_axis1_fwd_mass", active ? 0 : nvec,
-                (k_axis1<T, decltype(N1)::value, false>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2,
-                         (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
+      if (active)
+        BW_LAUNCH("k_axis1_fwd_pcg", 0, (k_axis1<T, decltype(N1)::value, false, 1>), dim3(nvec * ct.tpv), dim3(NT),
+                  0, s, W, g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
+      else
+        BW_LAUNCH(OP == 0 ? "k_axis1_fwd" : "k_axis1_fwd_mass", nvec, (k_axis1<T, decltype(N1)::value, false>),
+                  dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
     });
   }
 }
