@@ -86,6 +86,9 @@ typedef struct bw_eig_opts {
                           to the outer residual, never looser than 1e-2 nor
                           tighter than tol_lin); 0: the err1 / err2 rule of the
                           subspace algorithm with TOL_eig                        */
+  int32_t kbatch;      /* Lanczos: wave vectors advanced together (one PCG right-
+                          hand side each per Lanczos step); 0 -> as many as fit
+                          in about 48 GB, at most 64; 1 -> one k at a time       */
 } bw_eig_opts;
 
 /* Statistics of the last solver call (all optional outputs). */

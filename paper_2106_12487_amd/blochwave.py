@@ -35,7 +35,7 @@ class bw_eig_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("block", ctypes.c_int32), ("ncv", ctypes.c_int32),
                 ("maxit_outer", ctypes.c_int32), ("maxit_lin", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("tol_eig", ctypes.c_double),
-                ("tol_lin", ctypes.c_double), ("tol_omega", ctypes.c_double)]
+                ("tol_lin", ctypes.c_double), ("tol_omega", ctypes.c_double), ("kbatch", ctypes.c_int32)]
 
 
 class bw_stats(ctypes.Structure):
@@ -214,14 +214,14 @@ def bw_pcg_solve(rve: Rve, k, b, x, rtol: float, maxit: int = 0, stream=None):
 def bw_lowest_modes(rve: Rve, k_list, nmodes: int, method: int = BW_SUBSPACE, block: int = 0, ncv: int = 0,
                     tol_eig: float = 0.0, tol_lin: float = 0.0, maxit_outer: int = 0, maxit_lin: int = 0,
                     warm_start: bool = True, modes=None, want_err: bool = True, tol_omega: float = 0.0,
-                    stream=None):
+                    kbatch: int = 0, stream=None):
     """omega (nk x nmodes, rad/s), error bounds, status and statistics."""
     k_arr, k_p = _darr(np.asarray(k_list).reshape(-1, 3))
     nk = int(k_arr.shape[0])
     om = np.zeros((nk, nmodes))
     er = np.zeros((nk, nmodes))
     opts = bw_eig_opts(method, block, ncv, maxit_outer, maxit_lin, int(bool(warm_start)), tol_eig, tol_lin,
-                       tol_omega)
+                       tol_omega, kbatch)
     st = bw_stats()
     code = _check(lib().bw_lowest_modes(rve.handle, k_p, nk, int(nmodes), ctypes.byref(opts),
                                         om.ctypes.data_as(_DP), er.ctypes.data_as(_DP) if want_err else None,

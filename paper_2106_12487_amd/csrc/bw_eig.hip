@@ -27,6 +27,7 @@ static bool verbose() {
 struct EigOpts {
   int method, block, ncv, maxit_outer, maxit_lin, warm;
   double tol_eig, tol_lin, tol_omega;
+  int kbatch;
 };
 
 // Relative omega bound from a residual norm in the M^-1 norm: Kato-Temple when
@@ -255,6 +256,59 @@ static void rr64_bounds(bw_rve* r, const double* dq, cplx<double>*& U, int q, in
   for (int p = 0; p < n_want; ++p) bound[p] = omega_bound(std::sqrt(std::max(rn[p].x, 0.0)), lam, p, q);
 }
 
+// FP64 refinement of a block of Ritz vectors (mixed-precision path): FP64
+// Rayleigh-Ritz and residual R = K U - lambda M U, then, while a bound misses
+// the target, an FP32 correction solve K D = R (iterative refinement driven by
+// the FP64 residual; U - D is one step of inverse iteration) and a new FP64
+// Rayleigh-Ritz.  U64 (q vectors, FP64 workspace slot 3) is updated in place.
+template <typename T>
+static void refine64(bw_rve* r, const double* dq, const QTable& qt, long jstar, int q, int n_want,
+                     std::vector<double>& lam, std::vector<double>& bound, double target, int rounds, Counters& cnt,
+                     hipStream_t s) {
+  const long n3 = r->g.nvox * 3;
+  Small sm = small_bufs(r);
+  Workspace<double>& w64 = ws<double>(r);
+  cplx<double>* U64 = (cplx<double>*)w64.v[3].p;
+  rr64_bounds(r, dq, U64, q, n_want, lam, bound, true, nullptr, nullptr, cnt, s);
+  for (int it = 0; it < rounds && n_want > 0; ++it) {
+    const double worst = *std::max_element(bound.begin(), bound.end());
+    if (verbose()) fprintf(stderr, "[bw]   refinement round %d: worst bound %.3e\n", it, worst);
+    if (worst <= target) break;
+    const cplx<double>* R = (const cplx<double>*)w64.v[9].p;  // K U - lambda M U (first n_want)
+    Workspace<T>& w = ws<T>(r);
+    cplx<T>* Rt = w.vec(12, (size_t)n_want * n3);
+    cplx<T>* D = w.vec(13, (size_t)n_want * n3);
+    if (sizeof(T) == 4)
+      launch_convert<double, float>(R, (cplx<float>*)Rt, (size_t)n_want * n3, s);
+    else
+      BW_HIP(hipMemcpyAsync(Rt, R, (size_t)n_want * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
+    BW_HIP(hipMemsetAsync(D, 0, (size_t)n_want * n3 * sizeof(cplx<T>), s));
+    PcgResult pr = pcg_run<T>(r, dq, qt, Rt, D, n_want, sizeof(T) == 4 ? 1e-6 : 1e-10, 2000, true, s, false, false);
+    cnt.pcg_iters += pr.total_iters;
+    cnt.block_iters += pr.block_iters;
+    cnt.kap += pr.k_applies;
+    cplx<double>* D64 = w64.vec(12, (size_t)n_want * n3);
+    if (sizeof(T) == 4)
+      launch_convert<float, double>((const cplx<float>*)D, D64, (size_t)n_want * n3, s);
+    else
+      BW_HIP(hipMemcpyAsync(D64, D, (size_t)n_want * n3 * sizeof(cplx<double>), hipMemcpyDeviceToDevice, s));
+    if (jstar >= 0) {  // keep the block M-orthogonal to the rigid translations
+      cplx<double>* MD = w64.vec(13, (size_t)n_want * n3);
+      cplx<double>* MN = w64.vec(14, (size_t)3 * n3);
+      cplx<double>* N3 = w64.vec(15, (size_t)3 * n3);
+      rigid_MN<double>(r, jstar, N3, MN, sm, cnt, s);
+      apply_M_blk<double>(r, D64, MD, n_want, false, cnt, s);
+      launch_deflate<double>(D64, MD, MN, n_want, r->g.nvox, jstar, sm.coef, s);
+    }
+    std::vector<double> ones(n_want, 1.0);
+    BW_HIP(hipMemcpyAsync(sm.sc, ones.data(), n_want * sizeof(double), hipMemcpyHostToDevice, s));
+    U64 = (cplx<double>*)w64.v[3].p;
+    launch_lincomb<double>(U64, D64, sm.sc, U64, n_want, n3, n3, s);  // U <- U - D
+    BW_HIP(hipStreamSynchronize(s));
+    rr64_bounds(r, dq, U64, q, n_want, lam, bound, true, nullptr, nullptr, cnt, s);
+  }
+}
+
 template <typename T>
 static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigOpts& o, bool& have_start,
                        std::vector<double>& lam_prev, Counters& cnt, hipStream_t s) {
@@ -399,12 +453,13 @@ static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigO
         ++it;
         break;
       }
-      // FP64 Rayleigh-Ritz on the FP32 block and the a-posteriori bounds
+      // FP64 Rayleigh-Ritz on the FP32 block, FP64-residual-driven refinement and the bounds
       std::vector<double> lam64, bnd;
       Workspace<double>& w64 = ws<double>(r);
       cplx<double>* U64 = w64.vec(3, (size_t)q * n3);
       launch_convert<float, double>((const cplx<float>*)U, U64, (size_t)q * n3, s);
-      rr64_bounds(r, dq, U64, q, nw, lam64, bnd, true, nullptr, nullptr, cnt, s);
+      refine64<T>(r, dq, qt, out.jstar, q, nw, lam64, bnd, bound_target, 3, cnt, s);
+      U64 = (cplx<double>*)w64.v[3].p;
       launch_convert<double, float>(U64, (cplx<float>*)U, (size_t)q * n3, s);
       lam_prev = lam64;
       have_KU = false;
@@ -683,7 +738,7 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
         QTable qk = make_qtable(r, k1.data(), qsel);
         const double* dqk = upload_qtable(r, qk, r->ws_q3, s);
         std::vector<double> lam64, bnd;
-        rr64_bounds(r, dqk, U64, qsel, nw, lam64, bnd, true, nullptr, nullptr, cnt, s);
+        refine64<T>(r, dqk, qk, qt.null_index[k], qsel, nw, lam64, bnd, bound_target, 3, cnt, s);
         const double wb = nw > 0 ? *std::max_element(bnd.begin(), bnd.end()) : 0.0;
         if (verbose()) fprintf(stderr, "[bw] lanczos k#%d FP64 bound %.3e\n", kofs + k, wb);
         const bool stalled = wb > 0.5 * best[k];  // the bound stopped improving (precision floor)
@@ -789,6 +844,7 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
       o.tol_eig = opts->tol_eig;
       o.tol_lin = opts->tol_lin;
       o.tol_omega = opts->tol_omega;
+      o.kbatch = opts->kbatch;
     } else {
       o.warm = 1;
     }
@@ -815,6 +871,7 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
       const double vbytes = (double)r->g.nvox * 3 * (r->precision == BW_FP64 ? 16 : 8);
       int kb = (int)std::max(1.0, std::floor(48e9 / (vbytes * (2.0 * (m + 1) + 3))));
       kb = std::min({kb, nk, 64});
+      if (o.kbatch > 0) kb = std::min(kb, o.kbatch);
       for (int k0 = 0; k0 < nk; k0 += kb) {
         const int nb = std::min(kb, nk - k0);
         const int s1 = r->precision == BW_FP64

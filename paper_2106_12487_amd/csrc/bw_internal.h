@@ -98,7 +98,7 @@ struct Geom {
 
 // Cached vector workspaces of one precision.
 template <typename T> struct Workspace {
-  DevBuf v[12];
+  DevBuf v[16];
   DevBuf w;
   cplx<T>* vec(int i, size_t n) { return (cplx<T>*)v[i].get(n * sizeof(cplx<T>)); }
   cplx<T>* work(size_t n) { return (cplx<T>*)w.get(n * sizeof(cplx<T>)); }
