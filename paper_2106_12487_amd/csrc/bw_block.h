@@ -65,5 +65,8 @@ void launch_set_entries(cplx<T>* U, long vstride, long nvox, int nent, const lon
 // lam ascending, Q with Q^H Mq Q = I.  info[0] != 0 if Mq is not positive definite.
 void launch_small_geig(const double2* Kq, const double2* Mq, int q, double* lam, double2* Q, int* info,
                        hipStream_t s);
+// nb independent Hermitian eigenproblems H_b z = lam z (q x q each, stored one
+// after the other), one workgroup each: lam[b*q..], Q[b*q*q..], info[b]
+void launch_small_eig_batched(const double2* H, int q, int nb, double* lam, double2* Q, int* info, hipStream_t s);
 
 }  // namespace bw

@@ -637,9 +637,8 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
 
   std::vector<std::vector<double>> H(nk, std::vector<double>((size_t)m * m, 0.0));
   std::vector<double2> hh(hcount), hh2(hcount);
-  std::vector<double> Hd((size_t)m * m * 2), Id((size_t)m * m * 2, 0.0), thv(m);
+  std::vector<double> thv(m);
   std::vector<double2> Sm((size_t)m * m);
-  for (int i = 0; i < m; ++i) Id[2 * (i * m + i)] = 1.0;
   int j0 = 0;
   int status = BW_OK;
   int cycles = 0;
@@ -694,19 +693,28 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
     }
     ++cycles;
     cnt.outer += 1;
-    // projected eigenproblems, convergence, restart
-    for (int k = 0; k < nk; ++k) {
-      if (!act[k]) continue;
-      for (size_t i = 0; i < (size_t)m * m; ++i) {
-        Hd[2 * i] = H[k][i];
-        Hd[2 * i + 1] = 0.0;
-      }
-      BW_HIP(hipMemcpyAsync(sm.Kq, Hd.data(), m * m * sizeof(double2), hipMemcpyHostToDevice, s));
-      BW_HIP(hipMemcpyAsync(sm.Mq, Id.data(), m * m * sizeof(double2), hipMemcpyHostToDevice, s));
-      launch_small_geig(sm.Kq, sm.Mq, m, sm.lam, sm.Q, sm.info, s);
-      BW_HIP(hipMemcpyAsync(thv.data(), sm.lam, m * sizeof(double), hipMemcpyDeviceToHost, s));
-      BW_HIP(hipMemcpyAsync(Sm.data(), sm.Q, m * m * sizeof(double2), hipMemcpyDeviceToHost, s));
-      BW_HIP(hipStreamSynchronize(s));
+    // projected eigenproblems of all active wave vectors in one launch
+    std::vector<int> idx;
+    for (int k = 0; k < nk; ++k)
+      if (act[k]) idx.push_back(k);
+    const int nb = (int)idx.size();
+    std::vector<double> Hall((size_t)nb * m * m * 2, 0.0), thall((size_t)nb * m);
+    std::vector<double2> Sall((size_t)nb * m * m);
+    for (int b = 0; b < nb; ++b)
+      for (size_t i = 0; i < (size_t)m * m; ++i) Hall[((size_t)b * m * m + i) * 2] = H[idx[b]][i];
+    double2* Hd_dev = (double2*)w.v[9].get(Hall.size() * sizeof(double));
+    double2* Sd_dev = (double2*)w.v[10].get((size_t)nb * m * m * sizeof(double2));
+    double* th_dev = (double*)w.v[11].get((size_t)nb * m * sizeof(double) + (size_t)nb * sizeof(int) + 64);
+    int* inf_dev = (int*)(th_dev + (size_t)nb * m);
+    BW_HIP(hipMemcpyAsync(Hd_dev, Hall.data(), Hall.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_small_eig_batched(Hd_dev, m, nb, th_dev, Sd_dev, inf_dev, s);
+    BW_HIP(hipMemcpyAsync(thall.data(), th_dev, thall.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    BW_HIP(hipMemcpyAsync(Sall.data(), Sd_dev, Sall.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    BW_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < nb; ++b) {
+      const int k = idx[b];
+      std::copy(thall.begin() + (size_t)b * m, thall.begin() + (size_t)(b + 1) * m, thv.begin());
+      std::copy(Sall.begin() + (size_t)b * m * m, Sall.begin() + (size_t)(b + 1) * m * m, Sm.begin());
       const int nw = nwk[k];
       bool conv = true;
       double worst = 0;

@@ -325,8 +325,15 @@ __device__ __forceinline__ double2 cmc(double2 a, double2 b) {  // a * conj(b)
   return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
-__global__ __launch_bounds__(64) void k_small_geig(const double2* __restrict__ Kq, const double2* __restrict__ Mq,
-                                                   int q, double* lam, double2* Qout, int* info) {
+__global__ __launch_bounds__(64) void k_small_geig(const double2* __restrict__ Kq_all,
+                                                   const double2* __restrict__ Mq_all, int q, double* lam_all,
+                                                   double2* Qout_all, int* info_all, int m_identity) {
+  // one workgroup per problem of the batch
+  const double2* Kq = Kq_all + (size_t)blockIdx.x * q * q;
+  const double2* Mq = Mq_all + (size_t)blockIdx.x * q * q;
+  double* lam = lam_all + (size_t)blockIdx.x * q;
+  double2* Qout = Qout_all + (size_t)blockIdx.x * q * q;
+  int* info = info_all + blockIdx.x;
   constexpr int QE = GEIG_QMAX;
   __shared__ double2 A[QE * QE];
   __shared__ double2 Z[QE * QE];
@@ -341,15 +348,19 @@ __global__ __launch_bounds__(64) void k_small_geig(const double2* __restrict__ K
     flag = 0;
     info[0] = 0;
   }
-  for (int i = tid; i < q; i += 64) dsc[i] = 1.0 / sqrt(Mq[i * q + i].x);
+  for (int i = tid; i < q; i += 64) dsc[i] = m_identity ? 1.0 : 1.0 / sqrt(Mq[i * q + i].x);
   __syncthreads();
   for (int idx = tid; idx < q * q; idx += 64) {
     const int i = idx / q, j = idx - i * q;
     const double s = dsc[i] * dsc[j];
     const double2 k1 = Kq[i * q + j], k2 = Kq[j * q + i];
-    const double2 m1 = Mq[i * q + j], m2 = Mq[j * q + i];
     A[idx] = make_double2(0.5 * (k1.x + k2.x) * s, 0.5 * (k1.y - k2.y) * s);  // Hermitian part
-    Lm[idx] = make_double2(0.5 * (m1.x + m2.x) * s, 0.5 * (m1.y - m2.y) * s);
+    if (m_identity) {
+      Lm[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    } else {
+      const double2 m1 = Mq[i * q + j], m2 = Mq[j * q + i];
+      Lm[idx] = make_double2(0.5 * (m1.x + m2.x) * s, 0.5 * (m1.y - m2.y) * s);
+    }
   }
   __syncthreads();
   // Cholesky Lm = L L^H (lower), in place
@@ -550,7 +561,13 @@ __global__ __launch_bounds__(64) void k_small_geig(const double2* __restrict__ K
 void launch_small_geig(const double2* Kq, const double2* Mq, int q, double* lam, double2* Q, int* info,
                        hipStream_t s) {
   BW_REQUIRE(q >= 1 && q <= GEIG_QMAX, BW_EINVAL, "small eigenproblem larger than 48");
-  hipLaunchKernelGGL(k_small_geig, dim3(1), dim3(64), 0, s, Kq, Mq, q, lam, Q, info);
+  hipLaunchKernelGGL(k_small_geig, dim3(1), dim3(64), 0, s, Kq, Mq, q, lam, Q, info, 0);
+}
+
+void launch_small_eig_batched(const double2* H, int q, int nb, double* lam, double2* Q, int* info, hipStream_t s) {
+  BW_REQUIRE(q >= 1 && q <= GEIG_QMAX, BW_EINVAL, "small eigenproblem larger than 48");
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_small_geig, dim3(nb), dim3(64), 0, s, H, H, q, lam, Q, info, 1);
 }
 
 // ---------------------------------------------------------------------------
