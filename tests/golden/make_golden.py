@@ -4,7 +4,7 @@ Calls only the CPU oracle (oracle/) and the seeded input generators; nothing
 here touches the HIP path.  Usage:
 
     python tests/golden/make_golden.py cu16      # 16^3, 8 grains, all 11 k on Gamma-X
-    python tests/golden/make_golden.py cu64      # 64^3, 64 grains, sampled k of the path
+    python tests/golden/make_golden.py cu64      # 64^3, 64 grains, sampled k of the path (Lanczos)
 
 Output: tests/golden/<name>.json with the wave vectors (rad/m), omega (rad/s)
 and the oracle settings.
@@ -32,6 +32,7 @@ def nearest_path_indices(config, labels):
 
 
 def run(name):
+    method = "subspace"
     if name == "cu16":
         cfg, nmodes, block = 1, 6, 12
         idx = list(range(11))
@@ -41,21 +42,22 @@ def run(name):
         idx = nearest_path_indices(2, "GXMR")
         mid = [int(np.argmin(np.linalg.norm(ks - 0.5 * inputs.sc_points(inputs.L_MM)["X"], axis=1)))]
         idx = sorted(set(idx + mid))
+        method = "lanczos"
     else:
         raise SystemExit(f"unknown golden set {name}")
     rve = inputs.workload_rve(cfg, 0)
     ks = inputs.workload_kpoints(cfg)[idx]
-    out = dict(name=name, config=cfg, nmodes=nmodes, block=block, tol_eig=1e-12, tol_lin=1e-12,
+    out = dict(name=name, config=cfg, nmodes=nmodes, block=block, method=method, tol_eig=1e-12, tol_lin=1e-12,
                k_index=idx, k=ks.tolist(), omega=[], seconds=[], pcg_iters=[], outer=[])
     path = os.path.join(HERE, f"{name}.json")
     for i, k in enumerate(ks):
         t = time.time()
         st = []
-        w = solvers.lowest_modes(rve, k[None], nmodes, method="subspace", block=block,
+        w = solvers.lowest_modes(rve, k[None], nmodes, method=method, block=block,
                                  tol_eig=1e-12, tol_lin=1e-12, dense_max=0, warm_start=False, stats=st)
         out["omega"].append(w[0].tolist())
         out["pcg_iters"].append(int(st[0]["pcg_iters"]))
-        out["outer"].append(int(st[0]["outer"]))
+        out["outer"].append(int(st[0].get("outer", st[0].get("restarts", 0))))
         out["seconds"].append(time.time() - t)
         print(f"{name} k[{idx[i]}] {time.time() - t:.1f}s omega[:3]={w[0][:3]}", flush=True)
         with open(path, "w") as f:
