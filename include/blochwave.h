@@ -189,6 +189,88 @@ int bw_timing_filter(const char* kernel_name);
  * Returns the length the full report needs (including the NUL). */
 int64_t bw_timing_report(char* buf, int64_t len);
 
+/* ------------------------------------------------------------------------
+ * Learned preconditioner (an extension of the homogeneous-reference
+ * preconditioner of Sec. 3.3 eqs. matrixP, precond; not part of the paper).
+ *
+ *   z = P^ r + F[ s e^{i phi} N_theta(x) ],
+ *   x = [ e^{-i phi} F^-1(P^ r) / s  (real and imaginary parts of the three
+ *         components: 6 channels),  the 21 scaled Voigt stiffness entries and
+ *         the scaled density of the voxel's grain (22 channels) ]
+ * in real space, with s the RMS of F^-1(P^ r) over voxels and components and
+ * phi = arg(sum of (F^-1 P^ r)^2) / 2.  N_theta is a 3-level 3D U-Net
+ * (16 / 32 / 64 channels, 3x3x3 periodic convolutions, ReLU, 2x2x2 average
+ * pooling, nearest upsampling with skip concatenation, 1x1x1 head), evaluated
+ * with BF16 matrix-core products and FP32 accumulation.  Every grid size must
+ * be a multiple of 4 (BW_EUNSUPPORTED otherwise) and the cell BW_MIXED.
+ *
+ * Parameters: one flat FP32 vector, per layer l = 0..8 the weights
+ * W_l[tap][c_out][c_in] followed by the bias b_l[c_out]; layers
+ * (c_in -> c_out, taps): 32->16 (27), 16->16 (27), 16->32 (27), 32->32 (27),
+ * 32->64 (27), 64->64 (27), 96->32 (27), 48->16 (27), 16->16 (1).  Tap
+ * t = 9 (d0 + 1) + 3 (d1 + 1) + (d2 + 1) reads the periodic neighbour at grid
+ * offset (d0, d1, d2), d in {-1, 0, 1}.  Input channels 28..31 of layer 0 and
+ * output channels 6..15 of layer 8 are padding: their weights are held at 0.
+ * Concatenations put the upsampled coarse channels first, then the skip.
+ * ------------------------------------------------------------------------ */
+typedef struct bw_unet bw_unet;
+
+/* Number of FP32 parameters of the network. */
+int64_t bw_unet_param_count(void);
+
+/* Create a network on the current device: He-normal weights from `seed`, zero
+ * biases and a zero head (the untrained network adds nothing to P^ r). */
+int bw_unet_create(bw_unet** out, uint64_t seed);
+
+/* Release the network and its workspaces. */
+void bw_unet_destroy(bw_unet* net);
+
+/* Copy the FP32 parameters to / from host memory (n = bw_unet_param_count()).
+ * Setting weights zeroes the padding entries, checks that every value is
+ * finite (BW_EINVAL otherwise) and resets the optimizer state. */
+int bw_unet_get_weights(const bw_unet* net, float* w_host, int64_t n);
+int bw_unet_set_weights(bw_unet* net, const float* w_host, int64_t n);
+
+/* The bare network on nb samples of an n[0] x n[1] x n[2] grid:
+ *   x  device float [nb][n0*n1*n2][32] (channels last), y device float
+ *      [nb][n0*n1*n2][16].  Asynchronous on `stream`. */
+int bw_unet_net_forward(bw_unet* net, const int32_t n[3], const float* x, float* y, int32_t nb, void* stream);
+
+/* Gradient of sum(dy . y(x)) with respect to the parameters, written to
+ * grad_host (bw_unet_param_count() floats; padding entries 0).  x and dy are
+ * device buffers laid out as in bw_unet_net_forward.  Synchronizes `stream`. */
+int bw_unet_net_backward(bw_unet* net, const int32_t n[3], const float* x, const float* dy, float* grad_host,
+                         int32_t nb, void* stream);
+
+/* z = learned preconditioner applied to nrhs residuals r of the physical
+ * system K(k) x = r (k_host: nrhs x 3, one wave vector per right-hand side);
+ * r, z device [nrhs][3][n0][n1][n2] float2, not aliased.  The component on
+ * the xi + k = 0 voxel (if any) is zero.  Synchronizes `stream`. */
+int bw_unet_apply(bw_unet* net, bw_rve* rve, const double* k_host, const void* r, void* z, int32_t nrhs,
+                  void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * mean squared error between N_theta(x) and the normalized real-space target
+ * e^{-i phi} F^-1(x* - P^ r) / s, over nrhs pairs (r, x* = K(k)^-1 r) of
+ * device vectors laid out as in bw_unet_apply.  loss_host (optional) receives
+ * the loss before the step.  Synchronizes `stream`. */
+int bw_unet_train_step(bw_unet* net, bw_rve* rve, const double* k_host, const void* r, const void* x_star,
+                       int32_t nrhs, double lr, double* loss_host, void* stream);
+
+/* Solve K(k) x = b by flexible preconditioned CG with the learned
+ * preconditioner (net may be NULL: the plain P^, which reproduces
+ * bw_pcg_solve's iterates up to rounding).  Directions are made K-orthogonal
+ * to the previous one (Polak-Ribiere form, needed for a nonlinear
+ * preconditioner).  Per right-hand side, a learned z with Re <r, z> <= 0 or a
+ * non-finite value is replaced by P^ r and the direction restarted; after
+ * three such events, or when the residual has not dropped by 10% over 10
+ * iterations, the right-hand side continues with P^ only.  Arguments as in
+ * bw_pcg_solve (BW_MIXED cells, float2 vectors); fallbacks_host (optional,
+ * int32[nrhs]) receives the number of fallback events.  Synchronizes `stream`. */
+int bw_pcg_solve_learned(bw_rve* rve, bw_unet* net, const double k_host[3], const void* b, void* x, int32_t nrhs,
+                         double rtol, int32_t maxit, int32_t* iters_host, double* relres_host,
+                         int32_t* fallbacks_host, void* stream);
+
 /* Thread-local message describing the last non-zero status. */
 const char* bw_last_error(void);
 

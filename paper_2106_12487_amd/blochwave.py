@@ -68,6 +68,16 @@ _SIGS = {
     "bw_timing_enable": (_I, [_I]),
     "bw_timing_report": (ctypes.c_int64, [ctypes.c_char_p, ctypes.c_int64]),
     "bw_timing_filter": (_I, [ctypes.c_char_p]),
+    "bw_unet_param_count": (ctypes.c_int64, []),
+    "bw_unet_create": (_I, [ctypes.POINTER(_P), ctypes.c_uint64]),
+    "bw_unet_destroy": (None, [_P]),
+    "bw_unet_get_weights": (_I, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
+    "bw_unet_set_weights": (_I, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
+    "bw_unet_net_forward": (_I, [_P, _IP, _P, _P, _I, _P]),
+    "bw_unet_net_backward": (_I, [_P, _IP, _P, _P, ctypes.POINTER(ctypes.c_float), _I, _P]),
+    "bw_unet_apply": (_I, [_P, _P, _DP, _P, _P, _I, _P]),
+    "bw_unet_train_step": (_I, [_P, _P, _DP, _P, _P, _I, _D, _DP, _P]),
+    "bw_pcg_solve_learned": (_I, [_P, _P, _DP, _P, _P, _I, _D, _I, _IP, _DP, _IP, _P]),
 }
 
 
@@ -228,3 +238,96 @@ def bw_lowest_modes(rve: Rve, k_list, nmodes: int, method: int = BW_SUBSPACE, bl
                                         _dptr(modes) if modes is not None else None, ctypes.byref(st),
                                         _stream(stream)))
     return om, (er if want_err else None), code, st.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# learned preconditioner
+# ---------------------------------------------------------------------------
+def bw_unet_param_count() -> int:
+    return int(lib().bw_unet_param_count())
+
+
+class UNet:
+    """Owning wrapper of a bw_unet handle (the network lives on the current device)."""
+
+    def __init__(self, seed: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().bw_unet_create(ctypes.byref(h), ctypes.c_uint64(int(seed))))
+        self.handle = h
+        self.nparam = bw_unet_param_count()
+
+    def get_weights(self) -> np.ndarray:
+        w = np.zeros(self.nparam, dtype=np.float32)
+        _check(lib().bw_unet_get_weights(self.handle, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), self.nparam))
+        return w
+
+    def set_weights(self, w) -> None:
+        w = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+        _check(lib().bw_unet_set_weights(self.handle, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bw_unet_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _grid(n):
+    return (ctypes.c_int32 * 3)(*[int(v) for v in n])
+
+
+def bw_unet_net_forward(net: UNet, n, x, y, stream=None) -> None:
+    """y (nb, V, 16) = network(x (nb, V, 32)); float32 device tensors."""
+    _check(lib().bw_unet_net_forward(net.handle, _grid(n), _dptr(x), _dptr(y), int(x.shape[0]), _stream(stream)))
+
+
+def bw_unet_net_backward(net: UNet, n, x, dy, stream=None) -> np.ndarray:
+    """Gradient of sum(dy * y(x)) with respect to the flat parameter vector."""
+    g = np.zeros(net.nparam, dtype=np.float32)
+    _check(lib().bw_unet_net_backward(net.handle, _grid(n), _dptr(x), _dptr(dy),
+                                      g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(x.shape[0]),
+                                      _stream(stream)))
+    return g
+
+
+def _klist(k, nrhs):
+    k = np.asarray(k, dtype=np.float64).reshape(-1, 3)
+    if k.shape[0] == 1 and nrhs > 1:
+        k = np.repeat(k, nrhs, axis=0)
+    if k.shape[0] != nrhs:
+        raise ValueError("one wave vector, or one per right-hand side")
+    return _darr(k)
+
+
+def bw_unet_apply(net: UNet, rve: Rve, k, r, z, stream=None) -> None:
+    nrhs = int(r.shape[0])
+    k_arr, k_p = _klist(k, nrhs)
+    _check(lib().bw_unet_apply(net.handle, rve.handle, k_p, _dptr(r), _dptr(z), nrhs, _stream(stream)))
+
+
+def bw_unet_train_step(net: UNet, rve: Rve, k, r, x_star, lr: float, stream=None) -> float:
+    nrhs = int(r.shape[0])
+    k_arr, k_p = _klist(k, nrhs)
+    loss = ctypes.c_double()
+    _check(lib().bw_unet_train_step(net.handle, rve.handle, k_p, _dptr(r), _dptr(x_star), nrhs, float(lr),
+                                    ctypes.byref(loss), _stream(stream)))
+    return loss.value
+
+
+def bw_pcg_solve_learned(rve: Rve, net, k, b, x, rtol: float, maxit: int = 0, stream=None):
+    """Flexible PCG with the learned preconditioner (net None: plain P^);
+    returns (status, iterations, true relative residuals, fallback counts)."""
+    nrhs = int(b.shape[0])
+    k_arr, k_p = _darr(k)
+    it = np.zeros(nrhs, dtype=np.int32)
+    rr = np.zeros(nrhs)
+    fb = np.zeros(nrhs, dtype=np.int32)
+    code = _check(lib().bw_pcg_solve_learned(rve.handle, net.handle if net is not None else None, k_p, _dptr(b),
+                                             _dptr(x), nrhs, float(rtol), int(maxit), it.ctypes.data_as(_IP),
+                                             rr.ctypes.data_as(_DP), fb.ctypes.data_as(_IP), _stream(stream)))
+    return code, it, rr, fb
