@@ -773,6 +773,10 @@ inline int pw_blocks(long nvox) {
   return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
 }
 
+}  // namespace bw
+#include "bw_fft64.h"
+namespace bw {
+
 // ---------------------------------------------------------------------------
 // operator launchers
 // ---------------------------------------------------------------------------
@@ -783,39 +787,57 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
   const Geom& g = r->g;
   constexpr int NC = OP == 0 ? 6 : 3;
   const long n12 = (long)g.n1 * g.n2;
-  if (g.n1 > 1) {
+  const bool reg1 = g.n1 == 64 && g.n2 % C64_LINES == 0;
+  auto axis1 = [&](auto INVc) {
+    constexpr bool INV = decltype(INVc)::value;
+    const char* name = active ? (INV ? "k_axis1_inv_pcg" : "k_axis1_fwd_pcg")
+                              : (OP == 0 ? (INV ? "k_axis1_inv" : "k_axis1_fwd")
+                                         : (INV ? "k_axis1_inv_mass" : "k_axis1_fwd_mass"));
+    const long units = active ? 0 : nvec;
+    if (reg1) {
+      const int tpv = NC * g.n0 * (g.n2 / C64_LINES);
+      if (active)
+        BW_LAUNCH(name, units, (k_axis1_64<T, INV, 1>), dim3(nvec * tpv), dim3(NT), 0, s, W, g.n2,
+                  (long)NC * g.nvox, tpv, twiddles<T>(r, 1), active);
+      else
+        BW_LAUNCH(name, units, (k_axis1_64<T, INV, 0>), dim3(nvec * tpv), dim3(NT), 0, s, W, g.n2,
+                  (long)NC * g.nvox, tpv, twiddles<T>(r, 1), active);
+      return;
+    }
     with_n(g.n1, [&](auto N1) {
       ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2);
       if (active)
-        BW_LAUNCH("k_axis1_inv_pcg", 0, (k_axis1<T, decltype(N1)::value, true, 1>), dim3(nvec * ct.tpv), dim3(NT),
-                  0, s, W, g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
+        BW_LAUNCH(name, units, (k_axis1<T, decltype(N1)::value, INV, 1>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W,
+                  g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
       else
-        BW_LAUNCH(OP == 0 ? "k_axis1_inv" : "k_axis1_inv_mass", nvec, (k_axis1<T, decltype(N1)::value, true>),
-                  dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
+        BW_LAUNCH(name, units, (k_axis1<T, decltype(N1)::value, INV>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W,
+                  g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
     });
-  }
-  with_n(g.n0, [&](auto N0) {
-    ColTile ct = axis0_tile<T>(N0, n12);
-    const T* tab = tab_override ? tab_override : (OP == 0 ? ctab<T>(r) : rhotab<T>(r));
+  };
+  if (g.n1 > 1) axis1(std::true_type{});
+  const T* tab = tab_override ? tab_override : (OP == 0 ? ctab<T>(r) : rhotab<T>(r));
+  const char* name0 = active ? "k_axis0_contract_pcg" : (OP == 0 ? "k_axis0_contract" : "k_axis0_mass");
+  const long units0 = active ? 0 : nvec;
+  if (g.n0 == 64 && n12 % C64_LINES == 0 && (long)NC * g.nvox < (1L << 31)) {
+    const int tpv = (int)(n12 / C64_LINES);
     if (active)
-      BW_LAUNCH("k_axis0_contract_pcg", 0, (k_axis0_op<T, decltype(N0)::value, OP, 1>), dim3(nvec * ct.tpv),
-                dim3(NT), 0, s, W, n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+      BW_LAUNCH(name0, units0, (k_axis0_op64<T, OP, 1>), dim3(nvec * tpv), dim3(NT), 0, s, W, n12, g.nvox, tpv,
+                r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
     else
-      BW_LAUNCH(OP == 0 ? "k_axis0_contract" : "k_axis0_mass", nvec, (k_axis0_op<T, decltype(N0)::value, OP>),
-                dim3(nvec * ct.tpv), dim3(NT), 0, s, W, n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0),
-                active);
-  });
-  if (g.n1 > 1) {
-    with_n(g.n1, [&](auto N1) {
-      ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2);
+      BW_LAUNCH(name0, units0, (k_axis0_op64<T, OP, 0>), dim3(nvec * tpv), dim3(NT), 0, s, W, n12, g.nvox, tpv,
+                r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+  } else {
+    with_n(g.n0, [&](auto N0) {
+      ColTile ct = axis0_tile<T>(N0, n12);
       if (active)
-        BW_LAUNCH("k_axis1_fwd_pcg", 0, (k_axis1<T, decltype(N1)::value, false, 1>), dim3(nvec * ct.tpv), dim3(NT),
-                  0, s, W, g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
+        BW_LAUNCH(name0, units0, (k_axis0_op<T, decltype(N0)::value, OP, 1>), dim3(nvec * ct.tpv), dim3(NT), 0, s,
+                  W, n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
       else
-        BW_LAUNCH(OP == 0 ? "k_axis1_fwd" : "k_axis1_fwd_mass", nvec, (k_axis1<T, decltype(N1)::value, false>),
-                  dim3(nvec * ct.tpv), dim3(NT), 0, s, W, g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
+        BW_LAUNCH(name0, units0, (k_axis0_op<T, decltype(N0)::value, OP>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W,
+                  n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
     });
   }
+  if (g.n1 > 1) axis1(std::false_type{});
 }
 
 template <typename T>
@@ -824,35 +846,55 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   const Geom& g = r->g;
   const int* active = mode == 1 ? pd->active : nullptr;
   PcgDev dummy{};
-  with_n(g.n2, [&](auto N2) {
-    constexpr int n2c = decltype(N2)::value;
-    RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1);
+  const bool reg2 = g.n2 == 64 && ((long)g.n0 * g.n1) % R64_ROWS == 0;
+  const int tpv64 = (int)(((long)g.n0 * g.n1) / R64_ROWS);
+  if (reg2) {
     if (mode == 0)
-      BW_LAUNCH("k_strain_row", nvec, (k_strain_row<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u,
-                (cplx<T>*)nullptr, W,
-                         d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active, (const double*)nullptr,
-                         c0v<T>(r));
+      BW_LAUNCH("k_strain_row", nvec, (k_strain_row64<T, 0>), dim3(nvec * tpv64), dim3(NT), 0, s, u,
+                (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, tpv64, twiddles<T>(r, 2), active,
+                (const double*)nullptr, c0v<T>(r));
     else
-      BW_LAUNCH("k_strain_row_pcg", 0, (k_strain_row<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, pp, W,
-                d_qtab, g.n0,
-                         g.n1, g.nvox, rt, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
-  });
+      BW_LAUNCH("k_strain_row_pcg", 0, (k_strain_row64<T, 1>), dim3(nvec * tpv64), dim3(NT), 0, s, u, pp, W,
+                d_qtab, g.n0, g.n1, g.nvox, tpv64, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
+  } else {
+    with_n(g.n2, [&](auto N2) {
+      constexpr int n2c = decltype(N2)::value;
+      RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1);
+      if (mode == 0)
+        BW_LAUNCH("k_strain_row", nvec, (k_strain_row<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u,
+                  (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active,
+                  (const double*)nullptr, c0v<T>(r));
+      else
+        BW_LAUNCH("k_strain_row_pcg", 0, (k_strain_row<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, pp, W,
+                  d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
+    });
+  }
   launch_middle<T, 0>(r, W, nvec, (T)(1.0 / (double)g.nvox), active, s);
-  with_n(g.n2, [&](auto N2) {
-    constexpr int n2c = decltype(N2)::value;
-    RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1);
+  int nblk = 0;
+  if (reg2) {
+    nblk = tpv64;
     if (mode == 0)
-      BW_LAUNCH("k_row_div", nvec, (k_row_div<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab,
-                g.n0, g.n1,
-                         g.nvox, rt, twiddles<T>(r, 2), active, (const cplx<T>*)nullptr, dummy, (T)scale);
+      BW_LAUNCH("k_row_div", nvec, (k_row_div64<T, 0>), dim3(nvec * tpv64), dim3(NT), 0, s, W, y, d_qtab, g.n0,
+                g.n1, g.nvox, tpv64, twiddles<T>(r, 2), active, (const cplx<T>*)nullptr, dummy, (T)scale);
     else
-      BW_LAUNCH("k_row_div_pcg", 0, (k_row_div<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab,
-                g.n0, g.n1,
-                         g.nvox, rt, twiddles<T>(r, 2), active, (const cplx<T>*)pp, *pd, (T)scale);
-    if (mode == 1)
-      hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_ALPHA, rt.tpv, *pd, (const int*)nullptr,
-                         (double*)nullptr, (double*)nullptr);
-  });
+      BW_LAUNCH("k_row_div_pcg", 0, (k_row_div64<T, 1>), dim3(nvec * tpv64), dim3(NT), 0, s, W, y, d_qtab, g.n0,
+                g.n1, g.nvox, tpv64, twiddles<T>(r, 2), active, (const cplx<T>*)pp, *pd, (T)scale);
+  } else {
+    with_n(g.n2, [&](auto N2) {
+      constexpr int n2c = decltype(N2)::value;
+      RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1);
+      nblk = rt.tpv;
+      if (mode == 0)
+        BW_LAUNCH("k_row_div", nvec, (k_row_div<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab,
+                  g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active, (const cplx<T>*)nullptr, dummy, (T)scale);
+      else
+        BW_LAUNCH("k_row_div_pcg", 0, (k_row_div<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab,
+                  g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active, (const cplx<T>*)pp, *pd, (T)scale);
+    });
+  }
+  if (mode == 1)
+    hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_ALPHA, nblk, *pd, (const int*)nullptr,
+                       (double*)nullptr, (double*)nullptr);
 }
 
 template <typename T>

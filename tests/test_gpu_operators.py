@@ -44,6 +44,9 @@ CASES = [
     ((40, 6, 48), 7, [0.25, 0.25, 0.25]),
     ((64, 1, 1), 2, [0.3, 0.0, 0.0]),
     ((8, 32, 4), 3, [-0.7, 0.2, 0.9]),
+    # length-64 axes take the register-resident transforms
+    ((64, 4, 64), 9, [0.2, -0.4, 0.35]),
+    ((8, 64, 32), 5, [0.1, 0.6, -0.3]),
 ]
 
 
@@ -98,6 +101,28 @@ def test_pcg_matches_dense_solution(lib, prec):
         xref = np.linalg.solve(Kd, b[v].ravel()).reshape(b[v].shape)
         assert np.linalg.norm(xd[v].cpu().numpy() - xref) <= (1e-7 if prec == 0 else 1e-3) * np.linalg.norm(xref)
     # same iteration count as the oracle's PCG (same algorithm, same preconditioner)
+    if prec == 0:
+        _, it_o, _ = solvers.pcg(ops, b[0], tol)
+        assert abs(int(it[0]) - it_o) <= 1
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n", [(64, 4, 64), (8, 64, 32)])
+def test_pcg_on_length64_axes(lib, n, prec):
+    print(f"\n[case] pcg n={n} prec={prec}", flush=True)
+    torch = _dev()
+    rve = inputs.polycrystal(n, (L, L, L), 7, 95, 0)
+    k = np.array([0.45, -0.2, 0.1]) * np.pi / L
+    ops = Operators(rve, k)
+    b = _rand((3, 3) + n, 6)
+    R = lib.Rve.from_inputs(rve, prec)
+    xd = torch.zeros_like(_to_dev(b, prec))
+    tol = 1e-10 if prec == 0 else 1e-5
+    code, it, rr = lib.bw_pcg_solve(R, k, _to_dev(b, prec), xd, tol, 2000)
+    assert code == 0 and np.all(rr <= tol)
+    x = xd.cpu().numpy()
+    res = np.linalg.norm((ops.apply_K(x) - b).reshape(3, -1), axis=1) / np.linalg.norm(b.reshape(3, -1), axis=1)
+    assert np.all(res <= (2 * tol if prec == 0 else 3e-5)), res
     if prec == 0:
         _, it_o, _ = solvers.pcg(ops, b[0], tol)
         assert abs(int(it[0]) - it_o) <= 1
