@@ -53,6 +53,8 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--method", type=int, default=1, help="0 = subspace iteration, 1 = batched Lanczos")
     ap.add_argument("--skip-subspace", action="store_true", help="do not run the subspace-iteration context arm")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with plain 1 GiB device copies (reference kernel for memory-counter runs)")
     return ap.parse_args()
 
 
@@ -111,10 +113,47 @@ def roofline(rep, nvox, word_bytes):
     per_launch = bytes_total / max(v["launches"], 1)
     avg_s = v["ms"] / max(v["launches"], 1) / 1e3
     achieved = per_launch / avg_s / 1e9
+    traffic = measured_traffic(name)
     return dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None,
+                frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
                 bytes_per_launch=int(per_launch), avg_launch_us=round(avg_s * 1e6, 2),
                 launches=v["launches"], bytes_per_voxel_vector=words * word_bytes + extra)
+
+
+KERNEL_SOURCES = ("paper_2106_12487_amd/csrc/bw_ops_impl.h", "paper_2106_12487_amd/csrc/bw_fft64.h",
+                  "paper_2106_12487_amd/csrc/bw_fft.h", "paper_2106_12487_amd/csrc/bw_internal.h")
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter runs
+    (profiles/traffic_<kernel>_cu64.json), or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_cu64.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("sources_sha256_16") != kernel_sources_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def copy_calibration(bw):
+    import torch
+    n = 1 << 30
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        bw.bw_diag_copy(src, dst)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: 3 x {n} bytes", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(rve_in, ks, budget_s):
@@ -205,6 +244,8 @@ def main():
                                                      "unit": "k-points/s", "max_error_bound": sub["max_bound"]}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(rve_in, ks, a.cpu_seconds)
+    if a.copy_calibration:
+        copy_calibration(bw)
     print(json.dumps(out), flush=True)
 
 

@@ -68,6 +68,7 @@ _SIGS = {
     "bw_timing_enable": (_I, [_I]),
     "bw_timing_report": (ctypes.c_int64, [ctypes.c_char_p, ctypes.c_int64]),
     "bw_timing_filter": (_I, [ctypes.c_char_p]),
+    "bw_diag_copy": (_I, [_P, _P, ctypes.c_int64, _P]),
     "bw_unet_param_count": (ctypes.c_int64, []),
     "bw_unet_create": (_I, [ctypes.POINTER(_P), ctypes.c_uint64]),
     "bw_unet_destroy": (None, [_P]),
@@ -122,6 +123,14 @@ def bw_timing_report() -> dict:
     buf = ctypes.create_string_buffer(int(need) + 16)
     lib().bw_timing_report(buf, len(buf))
     return json.loads(buf.value.decode())
+
+
+def bw_diag_copy(src, dst, stream=None) -> None:
+    """Plain device copy of src into dst (same byte size), the counter-calibration kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst sizes differ")
+    _check(lib().bw_diag_copy(_dptr(src), _dptr(dst), nbytes, _stream(stream)))
 
 
 def _check(code: int) -> int:

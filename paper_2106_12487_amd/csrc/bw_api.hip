@@ -336,6 +336,30 @@ extern "C" int bw_timing_filter(const char* kernel_name) {
   return BW_OK;
 }
 
+namespace bw {
+// plain streaming copy (16-byte words), the calibration kernel for memory counters
+__global__ void k_diag_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, long n) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+}  // namespace bw
+
+extern "C" int bw_diag_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+  BW_GUARD_BEGIN
+  BW_REQUIRE(src && dst, BW_EINVAL, "null argument");
+  BW_REQUIRE(bytes >= 0 && bytes % 16 == 0, BW_EINVAL, "bytes must be a non-negative multiple of 16");
+  BW_REQUIRE(((uintptr_t)src | (uintptr_t)dst) % 16 == 0, BW_EINVAL, "buffers must be 16-byte aligned");
+  const long n = bytes / 16;
+  if (n == 0) return BW_OK;
+  long blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  BW_LAUNCH("k_diag_copy", 0, k_diag_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+            (const uint4*)src, (uint4*)dst, n);
+  BW_HIP(hipGetLastError());
+  return BW_OK;
+  BW_GUARD_END
+}
+
 extern "C" int64_t bw_timing_report(char* buf, int64_t len) {
   std::lock_guard<std::mutex> lk(g_tmu);
   drain_locked();
