@@ -53,6 +53,7 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--method", type=int, default=1, help="0 = subspace iteration, 1 = batched Lanczos")
     ap.add_argument("--skip-subspace", action="store_true", help="do not run the subspace-iteration context arm")
+    ap.add_argument("--skip-operator-arm", action="store_true", help="do not time bw_apply_K at 64^3 and 128^3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with plain 1 GiB device copies (reference kernel for memory-counter runs)")
     return ap.parse_args()
@@ -120,7 +121,7 @@ def roofline(rep, nvox, word_bytes):
                 launches=v["launches"], bytes_per_voxel_vector=words * word_bytes + extra)
 
 
-KERNEL_SOURCES = ("paper_2106_12487_amd/csrc/bw_ops_impl.h", "paper_2106_12487_amd/csrc/bw_fft64.h",
+KERNEL_SOURCES = ("paper_2106_12487_amd/csrc/bw_ops_impl.h", "paper_2106_12487_amd/csrc/bw_fftreg.h",
                   "paper_2106_12487_amd/csrc/bw_fft.h", "paper_2106_12487_amd/csrc/bw_internal.h")
 
 
@@ -143,6 +144,34 @@ def measured_traffic(kernel: str):
     if t.get("sources_sha256_16") != kernel_sources_hash():
         return None
     return t.get("traffic_bytes_per_launch")
+
+
+APPLY_K_WORDS = 54   # complex words per voxel and vector of one K apply (5 passes: 9 + 12 + 12 + 12 + 9)
+
+
+def operator_arm(bw, rve_in, nvec=8, reps=10):
+    """bw_apply_K throughput on a mixed cell: vector applies/s and algorithmic GB/s."""
+    import numpy as np
+    import torch
+    R = bw.Rve.from_inputs(rve_in, bw.BW_MIXED)
+    rng = np.random.default_rng(3)
+    u = torch.from_numpy(rng.standard_normal((nvec, 3) + tuple(rve_in.n)).astype(np.complex64)).to("cuda")
+    y = torch.empty_like(u)
+    k = (0.3 * np.pi / rve_in.L[0], 0.1 * np.pi / rve_in.L[1], 0.0)
+    for _ in range(2):
+        bw.bw_apply_K(R, k, u, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bw.bw_apply_K(R, k, u, y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    nvox = int(np.prod(rve_in.n))
+    R.close()
+    gbs = nvec * nvox * APPLY_K_WORDS * 8 / dt / 1e9
+    return {"grid": list(rve_in.n), "vectors": nvec, "ms_per_apply": round(dt * 1e3, 3),
+            "vector_applies_per_s": round(nvec / dt, 1), "algorithmic_GBps": round(gbs, 1),
+            "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
 
 
 def copy_calibration(bw):
@@ -188,7 +217,7 @@ def cpu_baseline(rve_in, ks, budget_s):
     return dict(value=1.0 / (sec_per_it * its_per_k), unit="k-points/s", cores=cores, kind="oracle",
                 sample=(f"{its} oracle PCG iterations (1 RHS, 64^3, k index 1) in {dt:.1f} s = "
                         f"{sec_per_it:.3f} s/iteration, times {its_per_k:.0f} PCG iterations per k-point "
-                        f"of the oracle's subspace iteration from its {src}; extrapolated"))
+                        f"of the oracle's shift-invert Lanczos from its {src}; extrapolated"))
 
 
 def main():
@@ -242,6 +271,10 @@ def main():
             sub = run_arm(bw, rve_in, ks, bw.BW_MIXED, 1, 0, 1e-6, 1e-6, method=0)
             out["arms"]["mixed_subspace_block16"] = {"value": round(len(ks) / sub["seconds"], 4),
                                                      "unit": "k-points/s", "max_error_bound": sub["max_bound"]}
+    if not a.skip_operator_arm:
+        out.setdefault("arms", {})["apply_K_mixed"] = [operator_arm(bw, rve_in),
+                                                      operator_arm(bw, inputs.workload_rve(4, 0))]
+        print(f"[bench] apply_K arm: {out['arms']['apply_K_mixed']}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(rve_in, ks, a.cpu_seconds)
     if a.copy_calibration:

@@ -1,0 +1,377 @@
+// Register-resident FFTs of power-of-two length N = 16 .. 256 for the passes
+// of the K operator: 8 points per thread, N / 8 threads per line, Stockham
+// radix passes in registers (radix 8 first, then 8, 4 or 2) with one LDS
+// exchange between consecutive passes.
+//
+// Layouts.  Thread j of a line holds 8 points.  "Layout A" is the natural
+// load order x[j + m N/8] (m < 8); a transform that starts from layout A
+// (decimation in time, `fft_dit`) ends with the outputs in "layout B", the
+// Stockham write positions of its last pass.  The same pass network run
+// backwards with the same twiddles (decimation in frequency, `fft_dif`) takes
+// layout B to layout A; since the DFT matrix is symmetric it computes the same
+// transform.  Kernels load in layout A, store wherever the transform leaves
+// the data, and the axis-0 pass (inverse transform, pointwise contraction,
+// forward transform) returns to layout A without any extra exchange.
+//
+// LDS traffic per transform: one write and one read of the tile per pass
+// after the first, against a load stage, one read-write per pass and a
+// read-back for the generic LDS FFT.  Consecutive exchanges alternate between
+// two buffers, so each needs a single barrier.
+#pragma once
+// Included by bw_ops_impl.h after the generic kernels and before the launchers.
+
+namespace bw {
+
+template <int N> struct RegFFT {
+  static_assert(N == 16 || N == 32 || N == 64 || N == 128 || N == 256, "register FFT length");
+  static constexpr int T = N / 8;          // threads per line
+  static constexpr int LINES = NT / T;     // lines per 256-thread block
+  static constexpr int P = (N <= 64) ? 2 : 3;
+  static constexpr int radix(int p) {
+    return p == 0 ? 8 : (N == 16 ? 2 : N == 32 ? 4 : N == 64 ? 8 : p == 1 ? 8 : (N == 128 ? 2 : 4));
+  }
+  static constexpr int ns(int p) { return p == 0 ? 1 : (p == 1 ? 8 : 64); }
+  // butterfly b, element r of pass p
+  __device__ static constexpr int rpos(int p, int b, int r) { return b + r * (N / radix(p)); }
+  __device__ static constexpr int wpos(int p, int b, int r) {
+    return (b / ns(p)) * ns(p) * radix(p) + (b % ns(p)) + r * ns(p);
+  }
+  __device__ static constexpr int texp(int p, int b, int r) {
+    return ns(p) == 1 ? 0 : r * (b % ns(p)) * (N / (ns(p) * radix(p)));
+  }
+  // register m of thread j in pass p: butterfly and element
+  __device__ static constexpr int bfly(int p, int j, int m) { return j * (8 / radix(p)) + m / radix(p); }
+  __device__ static constexpr int elem(int p, int m) { return m % radix(p); }
+  __device__ static constexpr int posA(int j, int m) { return j + m * T; }
+  __device__ static constexpr int posB(int j, int m) {
+    return wpos(P - 1, bfly(P - 1, j, m), elem(P - 1, m));
+  }
+  static constexpr int BUF = LINES * (N + N / 8);  // elements per exchange buffer (row pitch with skew)
+  static constexpr int BUFC = LINES * N;           // column tiles (no skew)
+  static constexpr int NBUF = P > 2 ? 2 : 1;       // a single transform with one exchange needs one buffer
+};
+
+// Twiddles of passes 1 .. P-1 for thread j: w[p - 1][m] = tw[texp].
+template <typename T, int N>
+__device__ __forceinline__ void load_twr(cplx<T> (&w)[RegFFT<N>::P - 1][8], const cplx<T>* __restrict__ tw, int j) {
+  using F = RegFFT<N>;
+#pragma unroll
+  for (int p = 1; p < F::P; ++p)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) w[p - 1][m] = tw[F::texp(p, F::bfly(p, j, m), F::elem(p, m))];
+}
+
+template <int R, bool INV, typename V> __device__ __forceinline__ void dft_groups(V (&v)[8]) {
+#pragma unroll
+  for (int t = 0; t < 8 / R; ++t) SmallDFT<R, INV, V>::run(&v[t * R]);
+}
+
+template <int N, int p, bool INV, typename V> __device__ __forceinline__ void dft_pass(V (&v)[8]) {
+  constexpr int R = RegFFT<N>::radix(p);
+  dft_groups<R, INV>(v);
+}
+
+// Decimation in time: v holds layout A on entry, layout B on exit.
+template <typename T, int N, bool INV, class Slot>
+__device__ __forceinline__ void fft_dit(cplx<T> (&v)[8], cplx<T>* buf0, cplx<T>* buf1, int& parity, const Slot& slot,
+                                        int j, const cplx<T> (&w)[RegFFT<N>::P - 1][8]) {
+  using F = RegFFT<N>;
+  using V = cplx<T>;
+  dft_pass<N, 0, INV>(v);
+#pragma unroll
+  for (int p = 1; p < F::P; ++p) {
+    V* buf = (parity++ & 1) ? buf1 : buf0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) buf[slot(F::wpos(p - 1, F::bfly(p - 1, j, m), F::elem(p - 1, m)))] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const V x = buf[slot(F::rpos(p, F::bfly(p, j, m), F::elem(p, m)))];
+      v[m] = INV ? cmulc(x, w[p - 1][m]) : cmul(x, w[p - 1][m]);
+    }
+    if (p == 1) dft_pass<N, 1, INV>(v);
+    if (p == 2) dft_pass<N, (F::P > 2 ? 2 : 1), INV>(v);
+  }
+}
+
+// Decimation in frequency: v holds layout B on entry, layout A on exit.
+template <typename T, int N, bool INV, class Slot>
+__device__ __forceinline__ void fft_dif(cplx<T> (&v)[8], cplx<T>* buf0, cplx<T>* buf1, int& parity, const Slot& slot,
+                                        int j, const cplx<T> (&w)[RegFFT<N>::P - 1][8]) {
+  using F = RegFFT<N>;
+  using V = cplx<T>;
+#pragma unroll
+  for (int p = F::P - 1; p >= 1; --p) {
+    if (p == 2) dft_pass<N, (F::P > 2 ? 2 : 1), INV>(v);
+    if (p == 1) dft_pass<N, 1, INV>(v);
+    V* buf = (parity++ & 1) ? buf1 : buf0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const V y = INV ? cmulc(v[m], w[p - 1][m]) : cmul(v[m], w[p - 1][m]);
+      buf[slot(F::rpos(p, F::bfly(p, j, m), F::elem(p, m)))] = y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = buf[slot(F::wpos(p - 1, F::bfly(p - 1, j, m), F::elem(p - 1, m)))];
+  }
+  dft_pass<N, 0, INV>(v);
+}
+
+// Row tiles (axis 2, contiguous): lane = T * row + j; pitch N + N/8 with a skew
+// of one slot per 8 points.  Column tiles (axes 0 and 1): lane = line + LINES * j.
+template <int N> struct RowSlotR {
+  int base;
+  __device__ __forceinline__ int operator()(int n) const { return base + n + (n >> 3); }
+};
+template <int N> struct ColSlotR {
+  int line;
+  __device__ __forceinline__ int operator()(int n) const { return n * RegFFT<N>::LINES + line; }
+};
+
+// ---------------------------------------------------------------------------
+// K, first pass (same contract as k_strain_row; tpv = n0 n1 / LINES)
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_strain_row_r(const cplx<T>* __restrict__ U, cplx<T>* __restrict__ Pp,
+                                                     cplx<T>* __restrict__ W, const double* __restrict__ qtab,
+                                                     int n0, int n1, long nvox, int tpv,
+                                                     const cplx<T>* __restrict__ tw, const int* __restrict__ active,
+                                                     const double* __restrict__ beta, C21v<T> C0) {
+  using V = cplx<T>;
+  using F = RegFFT<N>;
+  __shared__ V lds[2][F::BUF];
+  const int v = blockIdx.x / tpv;
+  const int tile = blockIdx.x - v * tpv;
+  if (active && !active[v]) return;
+  const int tid = threadIdx.x;
+  const int j = tid % F::T, line = tid / F::T;
+  const int row = tile * F::LINES + line;
+  const int i0 = row / n1, i1 = row - i0 * n1;
+  const double* q = qtab + (size_t)v * (n0 + n1 + N);
+  const T qa = (T)q[i0], qb = (T)q[n0 + i1];
+  T qc[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) qc[m] = (T)q[n0 + n1 + F::posA(j, m)];
+  V w[F::P - 1][8];
+  load_twr<T, N>(w, tw, j);
+  const size_t rbase = (size_t)row * N;
+  V u[3][8];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) u[c][m] = U[((size_t)v * 3 + c) * nvox + rbase + F::posA(j, m)];
+  if (MODE == 1) {
+    const T bt = (T)beta[v];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      V in[3] = {u[0][m], u[1][m], u[2][m]}, z[3];
+      precond3<T, V>(C0, qa, qb, qc[m], in, z);
+      const size_t o = rbase + F::posA(j, m);
+      if (bt != T(0)) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) z[c] = caxpy(z[c], bt, Pp[((size_t)v * 3 + c) * nvox + o]);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Pp[((size_t)v * 3 + c) * nvox + o] = z[c];
+        u[c][m] = z[c];
+      }
+    }
+  }
+  const RowSlotR<N> slot{line * (N + N / 8)};
+  int parity = 0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    V e[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      switch (c) {
+        case 0: e[m] = cscale(u[0][m], qa); break;
+        case 1: e[m] = cscale(u[1][m], qb); break;
+        case 2: e[m] = cscale(u[2][m], qc[m]); break;
+        case 3: e[m] = cadd(cscale(u[1][m], qc[m]), cscale(u[2][m], qb)); break;
+        case 4: e[m] = cadd(cscale(u[0][m], qc[m]), cscale(u[2][m], qa)); break;
+        default: e[m] = cadd(cscale(u[0][m], qb), cscale(u[1][m], qa)); break;
+      }
+    }
+    fft_dit<T, N, true>(e, lds[0], lds[1], parity, slot, j, w);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) W[((size_t)v * 6 + c) * nvox + rbase + F::posB(j, m)] = e[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K, last pass (same contract as k_row_div; partials per tile)
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_row_div_r(const cplx<T>* __restrict__ W, cplx<T>* __restrict__ Y,
+                                                  const double* __restrict__ qtab, int n0, int n1, long nvox,
+                                                  int tpv, const cplx<T>* __restrict__ tw,
+                                                  const int* __restrict__ active, const cplx<T>* __restrict__ Pp,
+                                                  PcgDev pd, T oscale) {
+  using V = cplx<T>;
+  using F = RegFFT<N>;
+  __shared__ V lds[2][F::BUF];
+  __shared__ double sh[NT / 64];
+  const int v = blockIdx.x / tpv;
+  const int tile = blockIdx.x - v * tpv;
+  if (active && !active[v]) return;
+  const int tid = threadIdx.x;
+  const int j = tid % F::T, line = tid / F::T;
+  const int row = tile * F::LINES + line;
+  const int i0 = row / n1, i1 = row - i0 * n1;
+  const double* q = qtab + (size_t)v * (n0 + n1 + N);
+  const T qa = (T)q[i0], qb = (T)q[n0 + i1];
+  T qc[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) qc[m] = (T)q[n0 + n1 + F::posB(j, m)];
+  V w[F::P - 1][8];
+  load_twr<T, N>(w, tw, j);
+  const size_t rbase = (size_t)row * N;
+  const RowSlotR<N> slot{line * (N + N / 8)};
+  int parity = 0;
+  V acc[3][8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) acc[0][m] = acc[1][m] = acc[2][m] = V{0, 0};
+  V nxt[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) nxt[m] = W[((size_t)v * 6) * nvox + rbase + F::posA(j, m)];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    V e[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) e[m] = nxt[m];
+    if (c < 5) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) nxt[m] = W[((size_t)v * 6 + c + 1) * nvox + rbase + F::posA(j, m)];
+    }
+    fft_dit<T, N, false>(e, lds[0], lds[1], parity, slot, j, w);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      switch (c) {
+        case 0: acc[0][m] = caxpy(acc[0][m], qa, e[m]); break;
+        case 1: acc[1][m] = caxpy(acc[1][m], qb, e[m]); break;
+        case 2: acc[2][m] = caxpy(acc[2][m], qc[m], e[m]); break;
+        case 3: acc[1][m] = caxpy(acc[1][m], qc[m], e[m]); acc[2][m] = caxpy(acc[2][m], qb, e[m]); break;
+        case 4: acc[0][m] = caxpy(acc[0][m], qc[m], e[m]); acc[2][m] = caxpy(acc[2][m], qa, e[m]); break;
+        default: acc[0][m] = caxpy(acc[0][m], qb, e[m]); acc[1][m] = caxpy(acc[1][m], qa, e[m]); break;
+      }
+    }
+  }
+  double part = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const size_t o = ((size_t)v * 3 + c) * nvox + rbase + F::posB(j, m);
+      const V ov = cscale(acc[c][m], oscale);
+      Y[o] = ov;
+      if (MODE == 1) {
+        const V pv = Pp[o];
+        part += (double)pv.x * (double)ov.x + (double)pv.y * (double)ov.y;
+      }
+    }
+  if (MODE == 1) {
+    const double vals[1] = {part};
+    store_partials<1>(vals, pd.partial, v, tile, pd.max_blocks, sh);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FFT along axis 1 (stride n2, n2 % LINES == 0), in place; lines are (plane,
+// column) with plane = (component, i0).  tpv = planes * n2 / LINES.
+// ---------------------------------------------------------------------------
+template <typename T, int N, bool INV, int PCG = 0>
+__global__ __launch_bounds__(NT) void k_axis1_r(cplx<T>* __restrict__ X, int n2, long vec_stride, int tpv,
+                                                const cplx<T>* __restrict__ tw, const int* __restrict__ active) {
+  using V = cplx<T>;
+  using F = RegFFT<N>;
+  __shared__ V lds[F::NBUF][F::BUFC];
+  const int v = blockIdx.x / tpv;
+  if (active && !active[v]) return;
+  const int tile = blockIdx.x - v * tpv;
+  const int tid = threadIdx.x;
+  const int line = tid % F::LINES, j = tid / F::LINES;
+  const int tpp = n2 / F::LINES;
+  const int plane = tile / tpp;
+  const int col = (tile - plane * tpp) * F::LINES + line;
+  V* base = X + (size_t)v * vec_stride + (size_t)plane * N * n2 + col;
+  V w[F::P - 1][8];
+  load_twr<T, N>(w, tw, j);
+  V e[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) e[m] = base[(size_t)F::posA(j, m) * n2];
+  int parity = 0;
+  fft_dit<T, N, INV>(e, lds[0], lds[F::NBUF - 1], parity, ColSlotR<N>{line}, j, w);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) base[(size_t)F::posB(j, m) * n2] = e[m];
+}
+
+// ---------------------------------------------------------------------------
+// Axis 0 (same contract as k_axis0_op; n12 % LINES == 0, NC nvox < 2^31):
+// inverse FFT (layout A -> B), stiffness contraction (OP 0) or density
+// scaling (OP 1) at the layout-B points, forward FFT back to layout A.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int OP, int PCG = 0>
+__global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, long n12, long nvox, int tpv,
+                                                      const uint16_t* __restrict__ gmap, const T* __restrict__ Ctab,
+                                                      T scale, const cplx<T>* __restrict__ tw,
+                                                      const int* __restrict__ active) {
+  using V = cplx<T>;
+  using F = RegFFT<N>;
+  constexpr int NC = OP == 0 ? 6 : 3;
+  __shared__ V lds[2][F::BUFC];
+  const int v = blockIdx.x / tpv;
+  if (active && !active[v]) return;
+  const int tile = blockIdx.x - v * tpv;
+  const int tid = threadIdx.x;
+  const int line = tid % F::LINES, j = tid / F::LINES;
+  const int pos = tile * F::LINES + line;
+  V w[F::P - 1][8];
+  load_twr<T, N>(w, tw, j);
+  // 32-bit offsets within the vector (NC * nvox < 2^31, checked by the host)
+  cplx<T>* Xv = X + (size_t)v * NC * nvox;
+  const int s12 = (int)n12, cs = (int)nvox;
+  V x[NC][8];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[c][m] = Xv[c * cs + pos + F::posA(j, m) * s12];
+  const ColSlotR<N> slot{line};
+  int parity = 0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) fft_dit<T, N, true>(x[c], lds[0], lds[1], parity, slot, j, w);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int g = gmap[pos + F::posB(j, m) * s12];
+    if (OP == 0) {
+      T cg[21];
+#pragma unroll
+      for (int i = 0; i < 21; ++i) cg[i] = Ctab[g * 21 + i];
+      V e[6], sg[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) e[c] = x[c][m];
+      contract6<T, V>(cg, e, sg, scale);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) x[c][m] = sg[c];
+    } else {
+      const T rs = Ctab[g] * scale;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) x[c][m] = cscale(x[c][m], rs);
+    }
+    // keep the table loads of one point at a time in flight (register pressure)
+    asm volatile("" ::: "memory");
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    fft_dif<T, N, false>(x[c], lds[0], lds[1], parity, slot, j, w);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) Xv[c * cs + pos + F::posA(j, m) * s12] = x[c][m];
+  }
+}
+
+// which lengths / tilings take the register kernels
+inline bool reg_len(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
+inline int reg_lines(int n) { return NT / (n / 8); }
+
+}  // namespace bw

@@ -774,12 +774,22 @@ inline int pw_blocks(long nvox) {
 }
 
 }  // namespace bw
-#include "bw_fft64.h"
+#include "bw_fftreg.h"
 namespace bw {
 
 // ---------------------------------------------------------------------------
 // operator launchers
 // ---------------------------------------------------------------------------
+template <class F> void with_reg(int n, F&& f) {
+  switch (n) {
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    case 128: f(std::integral_constant<int, 128>{}); break;
+    case 256: f(std::integral_constant<int, 256>{}); break;
+    default: throw Error{BW_EUNSUPPORTED, "no register FFT of length " + std::to_string(n)};
+  }
+}
 // Middle passes shared by K and M: inverse axis 1, axis-0 op, forward axis 1.
 template <typename T, int OP>
 void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* active, hipStream_t s,
@@ -787,7 +797,7 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
   const Geom& g = r->g;
   constexpr int NC = OP == 0 ? 6 : 3;
   const long n12 = (long)g.n1 * g.n2;
-  const bool reg1 = g.n1 == 64 && g.n2 % C64_LINES == 0;
+  const bool reg1 = reg_len(g.n1) && g.n2 % reg_lines(g.n1) == 0;
   auto axis1 = [&](auto INVc) {
     constexpr bool INV = decltype(INVc)::value;
     const char* name = active ? (INV ? "k_axis1_inv_pcg" : "k_axis1_fwd_pcg")
@@ -795,13 +805,16 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
                                          : (INV ? "k_axis1_inv_mass" : "k_axis1_fwd_mass"));
     const long units = active ? 0 : nvec;
     if (reg1) {
-      const int tpv = NC * g.n0 * (g.n2 / C64_LINES);
-      if (active)
-        BW_LAUNCH(name, units, (k_axis1_64<T, INV, 1>), dim3(nvec * tpv), dim3(NT), 0, s, W, g.n2,
-                  (long)NC * g.nvox, tpv, twiddles<T>(r, 1), active);
-      else
-        BW_LAUNCH(name, units, (k_axis1_64<T, INV, 0>), dim3(nvec * tpv), dim3(NT), 0, s, W, g.n2,
-                  (long)NC * g.nvox, tpv, twiddles<T>(r, 1), active);
+      with_reg(g.n1, [&](auto N1) {
+        constexpr int n1c = decltype(N1)::value;
+        const int tpv = NC * g.n0 * (g.n2 / reg_lines(n1c));
+        if (active)
+          BW_LAUNCH(name, units, (k_axis1_r<T, n1c, INV, 1>), dim3(nvec * tpv), dim3(NT), 0, s, W, g.n2,
+                    (long)NC * g.nvox, tpv, twiddles<T>(r, 1), active);
+        else
+          BW_LAUNCH(name, units, (k_axis1_r<T, n1c, INV, 0>), dim3(nvec * tpv), dim3(NT), 0, s, W, g.n2,
+                    (long)NC * g.nvox, tpv, twiddles<T>(r, 1), active);
+      });
       return;
     }
     with_n(g.n1, [&](auto N1) {
@@ -818,14 +831,17 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
   const T* tab = tab_override ? tab_override : (OP == 0 ? ctab<T>(r) : rhotab<T>(r));
   const char* name0 = active ? "k_axis0_contract_pcg" : (OP == 0 ? "k_axis0_contract" : "k_axis0_mass");
   const long units0 = active ? 0 : nvec;
-  if (g.n0 == 64 && n12 % C64_LINES == 0 && (long)NC * g.nvox < (1L << 31)) {
-    const int tpv = (int)(n12 / C64_LINES);
-    if (active)
-      BW_LAUNCH(name0, units0, (k_axis0_op64<T, OP, 1>), dim3(nvec * tpv), dim3(NT), 0, s, W, n12, g.nvox, tpv,
-                r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
-    else
-      BW_LAUNCH(name0, units0, (k_axis0_op64<T, OP, 0>), dim3(nvec * tpv), dim3(NT), 0, s, W, n12, g.nvox, tpv,
-                r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+  if (reg_len(g.n0) && n12 % reg_lines(g.n0) == 0 && (long)NC * g.nvox < (1L << 31)) {
+    with_reg(g.n0, [&](auto N0) {
+      constexpr int n0c = decltype(N0)::value;
+      const int tpv = (int)(n12 / reg_lines(n0c));
+      if (active)
+        BW_LAUNCH(name0, units0, (k_axis0_op_r<T, n0c, OP, 1>), dim3(nvec * tpv), dim3(NT), 0, s, W, n12, g.nvox,
+                  tpv, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+      else
+        BW_LAUNCH(name0, units0, (k_axis0_op_r<T, n0c, OP, 0>), dim3(nvec * tpv), dim3(NT), 0, s, W, n12, g.nvox,
+                  tpv, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+    });
   } else {
     with_n(g.n0, [&](auto N0) {
       ColTile ct = axis0_tile<T>(N0, n12);
@@ -846,16 +862,19 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   const Geom& g = r->g;
   const int* active = mode == 1 ? pd->active : nullptr;
   PcgDev dummy{};
-  const bool reg2 = g.n2 == 64 && ((long)g.n0 * g.n1) % R64_ROWS == 0;
-  const int tpv64 = (int)(((long)g.n0 * g.n1) / R64_ROWS);
+  const bool reg2 = reg_len(g.n2) && ((long)g.n0 * g.n1) % reg_lines(g.n2) == 0;
+  const int tpvr = reg2 ? (int)(((long)g.n0 * g.n1) / reg_lines(g.n2)) : 0;
   if (reg2) {
-    if (mode == 0)
-      BW_LAUNCH("k_strain_row", nvec, (k_strain_row64<T, 0>), dim3(nvec * tpv64), dim3(NT), 0, s, u,
-                (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, tpv64, twiddles<T>(r, 2), active,
-                (const double*)nullptr, c0v<T>(r));
-    else
-      BW_LAUNCH("k_strain_row_pcg", 0, (k_strain_row64<T, 1>), dim3(nvec * tpv64), dim3(NT), 0, s, u, pp, W,
-                d_qtab, g.n0, g.n1, g.nvox, tpv64, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
+    with_reg(g.n2, [&](auto N2) {
+      constexpr int n2c = decltype(N2)::value;
+      if (mode == 0)
+        BW_LAUNCH("k_strain_row", nvec, (k_strain_row_r<T, n2c, 0>), dim3(nvec * tpvr), dim3(NT), 0, s, u,
+                  (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active,
+                  (const double*)nullptr, c0v<T>(r));
+      else
+        BW_LAUNCH("k_strain_row_pcg", 0, (k_strain_row_r<T, n2c, 1>), dim3(nvec * tpvr), dim3(NT), 0, s, u, pp, W,
+                  d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
+    });
   } else {
     with_n(g.n2, [&](auto N2) {
       constexpr int n2c = decltype(N2)::value;
@@ -872,13 +891,16 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   launch_middle<T, 0>(r, W, nvec, (T)(1.0 / (double)g.nvox), active, s);
   int nblk = 0;
   if (reg2) {
-    nblk = tpv64;
-    if (mode == 0)
-      BW_LAUNCH("k_row_div", nvec, (k_row_div64<T, 0>), dim3(nvec * tpv64), dim3(NT), 0, s, W, y, d_qtab, g.n0,
-                g.n1, g.nvox, tpv64, twiddles<T>(r, 2), active, (const cplx<T>*)nullptr, dummy, (T)scale);
-    else
-      BW_LAUNCH("k_row_div_pcg", 0, (k_row_div64<T, 1>), dim3(nvec * tpv64), dim3(NT), 0, s, W, y, d_qtab, g.n0,
-                g.n1, g.nvox, tpv64, twiddles<T>(r, 2), active, (const cplx<T>*)pp, *pd, (T)scale);
+    nblk = tpvr;
+    with_reg(g.n2, [&](auto N2) {
+      constexpr int n2c = decltype(N2)::value;
+      if (mode == 0)
+        BW_LAUNCH("k_row_div", nvec, (k_row_div_r<T, n2c, 0>), dim3(nvec * tpvr), dim3(NT), 0, s, W, y, d_qtab,
+                  g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, (const cplx<T>*)nullptr, dummy, (T)scale);
+      else
+        BW_LAUNCH("k_row_div_pcg", 0, (k_row_div_r<T, n2c, 1>), dim3(nvec * tpvr), dim3(NT), 0, s, W, y, d_qtab,
+                  g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, (const cplx<T>*)pp, *pd, (T)scale);
+    });
   } else {
     with_n(g.n2, [&](auto N2) {
       constexpr int n2c = decltype(N2)::value;

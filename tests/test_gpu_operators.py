@@ -44,9 +44,12 @@ CASES = [
     ((40, 6, 48), 7, [0.25, 0.25, 0.25]),
     ((64, 1, 1), 2, [0.3, 0.0, 0.0]),
     ((8, 32, 4), 3, [-0.7, 0.2, 0.9]),
-    # length-64 axes take the register-resident transforms
+    # power-of-two axes take the register-resident transforms (8 points per thread)
     ((64, 4, 64), 9, [0.2, -0.4, 0.35]),
     ((8, 64, 32), 5, [0.1, 0.6, -0.3]),
+    ((128, 2, 128), 6, [0.45, 0.0, -0.15]),
+    ((4, 256, 32), 4, [-0.3, 0.25, 0.5]),
+    ((32, 16, 16), 5, [0.0, -0.5, 0.5]),
 ]
 
 
@@ -107,8 +110,8 @@ def test_pcg_matches_dense_solution(lib, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("n", [(64, 4, 64), (8, 64, 32)])
-def test_pcg_on_length64_axes(lib, n, prec):
+@pytest.mark.parametrize("n", [(64, 4, 64), (8, 64, 32), (128, 2, 128), (32, 16, 16)])
+def test_pcg_on_register_fft_axes(lib, n, prec):
     print(f"\n[case] pcg n={n} prec={prec}", flush=True)
     torch = _dev()
     rve = inputs.polycrystal(n, (L, L, L), 7, 95, 0)
