@@ -54,6 +54,7 @@ def _args():
     ap.add_argument("--method", type=int, default=1, help="0 = subspace iteration, 1 = batched Lanczos")
     ap.add_argument("--skip-subspace", action="store_true", help="do not run the subspace-iteration context arm")
     ap.add_argument("--skip-operator-arm", action="store_true", help="do not time bw_apply_K at 64^3 and 128^3")
+    ap.add_argument("--skip-uneven", action="store_true", help="do not run the batched uneven-cells arm")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with plain 1 GiB device copies (reference kernel for memory-counter runs)")
     return ap.parse_args()
@@ -174,6 +175,35 @@ def operator_arm(bw, rve_in, nvec=8, reps=10):
             "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
 
 
+def uneven_arm(bw, tol_omega=5e-6):
+    """Batched uneven workload: 8 cells (32^3, 40^3, 48^3, 64^3, two each; Cu or Al
+    grains), 24 wave vectors on Gamma-X-M-Gamma each, 8 modes, mixed, batched
+    Lanczos; the cells one after the other vs all cells in one batched call."""
+    import numpy as np
+    from paper_2106_12487_amd import inputs
+    w = inputs.WORKLOADS[3]
+    cells = [bw.Rve.from_inputs(inputs.workload_rve(3, i), bw.BW_MIXED) for i in range(len(w["grids"]))]
+    ks = [inputs.workload_kpoints(3)] * len(cells)
+    kw = dict(method=1, tol_omega=tol_omega, tol_lin=1e-6)
+    nkt = sum(len(k) for k in ks)
+    bw.bw_lowest_modes_batched(cells, ks, w["nmodes"], **kw)           # warm-up (workspaces)
+    t0 = time.perf_counter()
+    maxb = 0.0
+    for c, k in zip(cells, ks):
+        _, er, _, _ = bw.bw_lowest_modes(c, k, w["nmodes"], **kw)
+        maxb = max(maxb, float(er.max()))
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, ers, _, _ = bw.bw_lowest_modes_batched(cells, ks, w["nmodes"], **kw)
+    t_bat = time.perf_counter() - t0
+    maxb = max(maxb, max(float(e.max()) for e in ers))
+    for c in cells:
+        c.close()
+    return {"workload": w["name"], "grids": w["grids"], "k_points": nkt, "modes": w["nmodes"],
+            "sequential_kpoints_per_s": round(nkt / t_seq, 2), "batched_kpoints_per_s": round(nkt / t_bat, 2),
+            "batched_speedup": round(t_seq / t_bat, 3), "max_error_bound": maxb}
+
+
 def copy_calibration(bw):
     import torch
     n = 1 << 30
@@ -275,6 +305,9 @@ def main():
         out.setdefault("arms", {})["apply_K_mixed"] = [operator_arm(bw, rve_in),
                                                       operator_arm(bw, inputs.workload_rve(4, 0))]
         print(f"[bench] apply_K arm: {out['arms']['apply_K_mixed']}", file=sys.stderr, flush=True)
+    if not a.skip_uneven:
+        out.setdefault("arms", {})["uneven_batched"] = uneven_arm(bw)
+        print(f"[bench] uneven arm: {out['arms']['uneven_batched']}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(rve_in, ks, a.cpu_seconds)
     if a.copy_calibration:

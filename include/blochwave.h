@@ -174,6 +174,23 @@ int bw_lowest_modes(bw_rve* rve, const double* k_list_host, int32_t nk, int32_t 
                     const bw_eig_opts* opts, double* omega_host, double* err_host,
                     void* modes, bw_stats* stats_host, void* stream);
 
+/* Lowest modes of several cells at once (uneven grids allowed; Algorithm
+ * "Full algorithm" per cell): cell i gets nks[i] wave vectors k_lists[i]
+ * (host, nks[i] x 3) and writes omegas[i] / errs[i] (host, nks[i] x nmodes;
+ * errs and modes may be NULL, as may any errs[i] / modes[i]) exactly as a
+ * separate bw_lowest_modes call would.  The cells advance concurrently, each
+ * on a stream of its own created by the library, from host threads of the
+ * library, so the kernels of small cells overlap on the GPU; every cell's
+ * results equal those of its own call (same kernels, deterministic
+ * reductions).  The call first waits for `stream` and returns when all cells
+ * are done.  stats (optional) sums the counters over the cells; its
+ * `seconds` is the wall time of the whole call.  Returns the most severe
+ * status of the cells (an error before BW_ENOTCONV); bw_last_error names the
+ * first failing cell.  Different cells must be different handles; nrve <= 256. */
+int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const double* const* k_lists, const int32_t* nks,
+                            int32_t nmodes, const bw_eig_opts* opts, double* const* omegas, double* const* errs,
+                            void* const* modes, bw_stats* stats, void* stream);
+
 /* Diagnostics: opt-in kernel timing.  bw_timing_enable(1) clears the totals
  * and brackets every subsequent kernel launch of the library with HIP events
  * on the launch stream; bw_timing_enable(0) stops recording.  Adds a few

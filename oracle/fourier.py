@@ -86,6 +86,20 @@ def labels(N: int, L: float, k: float) -> np.ndarray:
     return lo + np.mod(j - lo, N)
 
 
+def snap_wavevector(L, k) -> np.ndarray:
+    """k with every component within 1e-9 (in units of 2 pi / L_a) of a whole
+    reciprocal vector replaced by that vector, so that xi + k = 0 holds exactly
+    on one voxel when k is a reciprocal lattice vector up to rounding."""
+    k = np.array(k, dtype=np.float64)
+    for a in range(3):
+        kappa = k[a] * L[a] / (2.0 * np.pi)
+        g = float(np.rint(kappa))
+        if abs(kappa - g) <= 1e-9:
+            k[a] = 2.0 * np.pi * g / L[a]
+    return k
+
+
 def shifted_wavevector(n, L, k) -> list:
     """Per-axis arrays q_a(j) = 2 pi m_a(j) / L_a + k_a (Sec. 3.2, xi + k)."""
+    k = snap_wavevector(L, k)
     return [2.0 * np.pi * labels(n[a], L[a], k[a]) / L[a] + k[a] for a in range(3)]

@@ -64,6 +64,9 @@ _SIGS = {
     "bw_pcg_solve": (_I, [_P, _DP, _P, _P, _I, _D, _I, _IP, _DP, _P]),
     "bw_lowest_modes": (_I, [_P, _DP, _I, _I, ctypes.POINTER(bw_eig_opts), _DP, _DP, _P,
                              ctypes.POINTER(bw_stats), _P]),
+    "bw_lowest_modes_batched": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_DP), _IP, _I, ctypes.POINTER(bw_eig_opts),
+                                     ctypes.POINTER(_DP), ctypes.POINTER(_DP), ctypes.POINTER(_P),
+                                     ctypes.POINTER(bw_stats), _P]),
     "bw_last_error": (ctypes.c_char_p, []),
     "bw_timing_enable": (_I, [_I]),
     "bw_timing_report": (ctypes.c_int64, [ctypes.c_char_p, ctypes.c_int64]),
@@ -247,6 +250,29 @@ def bw_lowest_modes(rve: Rve, k_list, nmodes: int, method: int = BW_SUBSPACE, bl
                                         _dptr(modes) if modes is not None else None, ctypes.byref(st),
                                         _stream(stream)))
     return om, (er if want_err else None), code, st.as_dict()
+
+
+def bw_lowest_modes_batched(rves, k_lists, nmodes: int, method: int = BW_SUBSPACE, block: int = 0, ncv: int = 0,
+                            tol_eig: float = 0.0, tol_lin: float = 0.0, maxit_outer: int = 0, maxit_lin: int = 0,
+                            warm_start: bool = True, tol_omega: float = 0.0, kbatch: int = 0, modes=None,
+                            stream=None):
+    """Several cells at once: lists of omega and error arrays, status, summed statistics."""
+    n = len(rves)
+    ks = [np.ascontiguousarray(np.asarray(k).reshape(-1, 3), dtype=np.float64) for k in k_lists]
+    oms = [np.zeros((k.shape[0], nmodes)) for k in ks]
+    ers = [np.zeros((k.shape[0], nmodes)) for k in ks]
+    h = (_P * n)(*[r.handle for r in rves])
+    kp = (_DP * n)(*[k.ctypes.data_as(_DP) for k in ks])
+    nk = (ctypes.c_int32 * n)(*[k.shape[0] for k in ks])
+    op = (_DP * n)(*[o.ctypes.data_as(_DP) for o in oms])
+    ep = (_DP * n)(*[e.ctypes.data_as(_DP) for e in ers])
+    mp = (_P * n)(*[(_dptr(m) if m is not None else None) for m in modes]) if modes is not None else None
+    opts = bw_eig_opts(method, block, ncv, maxit_outer, maxit_lin, int(bool(warm_start)), tol_eig, tol_lin,
+                       tol_omega, kbatch)
+    st = bw_stats()
+    code = _check(lib().bw_lowest_modes_batched(h, n, kp, nk, int(nmodes), ctypes.byref(opts), op, ep, mp,
+                                                ctypes.byref(st), _stream(stream)))
+    return oms, ers, code, st.as_dict()
 
 
 # ---------------------------------------------------------------------------

@@ -107,8 +107,15 @@ QTable make_qtable(const bw_rve* r, const double* k_host, int nk) {
     int zero_at[3] = {-1, -1, -1};
     double* dst = t.host.data() + (size_t)v * per;
     for (int a = 0; a < 3; ++a) {
-      const double k = k_host[3 * v + a];
-      const double kappa = k * r->L[a] / (2.0 * M_PI);
+      double k = k_host[3 * v + a];
+      double kappa = k * r->L[a] / (2.0 * M_PI);
+      // within 1e-9 of a whole reciprocal vector: take that vector exactly, so
+      // that xi + k = 0 on one voxel (K singular) is recognized
+      const double g = std::nearbyint(kappa);
+      if (std::fabs(kappa - g) <= 1e-9) {
+        kappa = g;
+        k = 2.0 * M_PI * g / r->L[a];
+      }
       const int lo = window_lo(n[a], kappa);
       for (int j = 0; j < n[a]; ++j) {
         int mm = (j - lo) % n[a];

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <numeric>
+#include <string>
+#include <thread>
 
 #include "bw_block.h"
 #include "bw_internal.h"
@@ -16,12 +18,11 @@
 namespace bw {
 
 static bool verbose() {
-  static int v = -1;
-  if (v < 0) {
+  static const bool v = [] {
     const char* e = getenv("BW_VERBOSE");
-    v = (e && *e && *e != '0') ? 1 : 0;
-  }
-  return v == 1;
+    return e && *e && *e != '0';
+  }();
+  return v;
 }
 
 struct EigOpts {
@@ -903,6 +904,85 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
     }
     if (st == BW_ENOTCONV) set_error("bw_lowest_modes: some k hit maxit_outer; see the error bounds");
     return st;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal: ") + e.what());
+    return BW_EINVAL;
+  }
+}
+
+// Several cells (uneven grids) at once: every cell runs the driver above on a
+// stream of its own, from a host thread of its own, so that the kernels of
+// small cells overlap on the GPU.  Results are those of separate calls (same
+// kernels, same deterministic reductions).
+extern "C" int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const double* const* k_lists,
+                                       const int32_t* nks, int32_t nmodes, const bw_eig_opts* opts,
+                                       double* const* omegas, double* const* errs, void* const* modes,
+                                       bw_stats* stats, void* stream) {
+  try {
+    BW_REQUIRE(rves && k_lists && nks && omegas, BW_EINVAL, "null argument");
+    BW_REQUIRE(nrve >= 0 && nrve <= 256, BW_EINVAL, "nrve out of range (0 .. 256)");
+    for (int i = 0; i < nrve; ++i) BW_REQUIRE(rves[i] && k_lists[i] && omegas[i], BW_EINVAL, "null cell argument");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t cs = (hipStream_t)stream;
+    // work already queued on the caller's stream precedes the batch
+    BW_HIP(hipStreamSynchronize(cs));
+    std::vector<hipStream_t> st(nrve, nullptr);
+    std::vector<int> code(nrve, BW_OK);
+    std::vector<std::string> msg(nrve);
+    std::vector<bw_stats> one(nrve);
+    int cur = 0;
+    BW_HIP(hipGetDevice(&cur));
+    try {
+      for (int i = 0; i < nrve; ++i) {
+        BW_HIP(hipSetDevice(rves[i]->device));
+        BW_HIP(hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking));
+      }
+      BW_HIP(hipSetDevice(cur));
+    } catch (...) {
+      for (auto x : st)
+        if (x) (void)hipStreamDestroy(x);
+      (void)hipSetDevice(cur);
+      throw;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nrve);
+    for (int i = 0; i < nrve; ++i)
+      th.emplace_back([&, i]() {
+        if (hipSetDevice(rves[i]->device) != hipSuccess) {
+          code[i] = BW_EHIP;
+          msg[i] = "hipSetDevice failed";
+          return;
+        }
+        std::memset(&one[i], 0, sizeof(bw_stats));
+        code[i] = bw_lowest_modes(rves[i], k_lists[i], nks[i], nmodes, opts, omegas[i], errs ? errs[i] : nullptr,
+                                  modes ? modes[i] : nullptr, &one[i], st[i]);
+        if (code[i] != BW_OK) msg[i] = bw_last_error();
+      });
+    for (auto& t : th) t.join();
+    for (auto x : st) (void)hipStreamDestroy(x);
+    int status = BW_OK;
+    std::string first;
+    for (int i = 0; i < nrve; ++i) {
+      if (code[i] < 0 && (status >= 0 || code[i] < status)) status = code[i];
+      if (code[i] == BW_ENOTCONV && status == BW_OK) status = BW_ENOTCONV;
+      if (code[i] != BW_OK && first.empty()) first = "cell " + std::to_string(i) + ": " + msg[i];
+    }
+    if (stats) {
+      std::memset(stats, 0, sizeof(bw_stats));
+      for (auto& o : one) {
+        stats->pcg_iterations += o.pcg_iterations;
+        stats->block_iterations += o.block_iterations;
+        stats->outer_iterations += o.outer_iterations;
+        stats->k_applies += o.k_applies;
+        stats->m_applies += o.m_applies;
+      }
+      stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status != BW_OK) set_error(first);
+    return status;
   } catch (const Error& e) {
     set_error(e.msg);
     return e.code;

@@ -272,6 +272,10 @@ def kpath(labels: str, n: int, L: float) -> np.ndarray:
         j = min(int(np.searchsorted(s_v, si, side="right")) - 1, len(seg) - 1)
         t = (si - s_v[j]) / seg[j]
         out[i] = (1 - t) * verts[j] + t * verts[j + 1]
+        # samples on a vertex (up to rounding of the arc length) are the vertex itself
+        near = np.nonzero(np.abs(s_v - si) <= 1e-12 * s_v[-1])[0]
+        if near.size:
+            out[i] = verts[near[0]]
     return out
 
 

@@ -56,16 +56,10 @@ def _subspace_angles(ops, Xo, Xg, lam, rel=1e-6):
     return worst
 
 
-@pytest.mark.parametrize("method", [0, 1])
-@pytest.mark.parametrize("prec", [0, 1])
-def test_lowest_modes_match_dense_oracle_8cube(lib, prec, method):
+def _check_against_dense(lib, rve, ks, prec, method, nm=6):
     torch = _torch()
-    rve = inputs.polycrystal((8, 8, 8), (L, L, L), 6, 95, 0)
-    ks = np.array([[0.0, 0.0, 0.0], [0.23, 0.11, -0.05], [1.0, 0.0, 0.0], [1.0, 1.0, 1.0]]) * np.pi / L
-    nm = 6
-    print(f"\n[case] lowest_modes 8^3 prec={prec} method={method}", flush=True)
     R = lib.Rve.from_inputs(rve, prec)
-    modes = torch.zeros((len(ks), nm, 3, 8, 8, 8), dtype=R.complex_dtype, device="cuda")
+    modes = torch.zeros((len(ks), nm, 3) + tuple(rve.n), dtype=R.complex_dtype, device="cuda")
     w, err, code, st = lib.bw_lowest_modes(R, ks, nm, method=method, block=12,
                                            tol_eig=1e-11 if prec == 0 else 1e-7,
                                            tol_lin=1e-12 if prec == 0 else 1e-6, modes=modes)
@@ -87,6 +81,32 @@ def test_lowest_modes_match_dense_oracle_8cube(lib, prec, method):
         assert ang <= (1e-6 if prec == 0 else 1e-2)
     # subspace: at least one outer iteration per k; Lanczos: restart cycles shared by the batch
     assert st["pcg_iterations"] > 0 and st["outer_iterations"] >= (len(ks) if method == 0 else 1)
+    R.close()
+    return w
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lowest_modes_match_dense_oracle_8cube(lib, prec, method):
+    rve = inputs.polycrystal((8, 8, 8), (L, L, L), 6, 95, 0)
+    ks = np.array([[0.0, 0.0, 0.0], [0.23, 0.11, -0.05], [1.0, 0.0, 0.0], [1.0, 1.0, 1.0]]) * np.pi / L
+    print(f"\n[case] lowest_modes 8^3 prec={prec} method={method}", flush=True)
+    _check_against_dense(lib, rve, ks, prec, method)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_phase_density_and_near_gamma_8cube(lib, prec, method):
+    """Cu / Al grains (density 8960 / 2700, so M is not a multiple of the
+    identity), at Gamma, at Gamma up to rounding (a closed path's end point),
+    at a general k and at M."""
+    rve = inputs.polycrystal((8, 8, 8), (L, L, L), 5, 3, 51, phases=("cu", "al"))
+    assert len(set(rve.rho)) == 2
+    ks = np.array([[0.0, 0.0, 0.0], [-6.98e-13, -6.98e-13, 0.0], [1500.0, 300.0, 0.0],
+                   [np.pi / L, np.pi / L, 0.0]])
+    print(f"\n[case] lowest_modes 8^3 Cu/Al prec={prec} method={method}", flush=True)
+    w = _check_against_dense(lib, rve, ks, prec, method)
+    assert np.all(w[:2, :3] == 0.0)
 
 
 @pytest.mark.parametrize("method", [0, 1])

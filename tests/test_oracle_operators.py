@@ -139,3 +139,20 @@ def test_voigt_upper_bound_on_acoustic_branches():
     P0 = inputs.voigt_to_tensor(ops.C0)
     Pk = np.einsum("ijkl,j,l->ik", P0, k, k) / ops.rho_bar
     assert np.all(w <= np.linalg.eigvalsh(Pk) * (1 + 1e-12))
+
+
+def test_near_reciprocal_lattice_wave_vector_is_snapped():
+    """A wave vector within rounding of a reciprocal lattice vector (e.g. the
+    arc-length interpolated end of a closed path) is that vector: one voxel has
+    xi + k = 0 exactly and K has the three rigid zero modes."""
+    from oracle.fourier import snap_wavevector
+    L = (1e-3, 1e-3, 1e-3)
+    k = np.array([-6.98e-13, 2.0 * np.pi / 1e-3 + 4e-13, 0.0])
+    ks = snap_wavevector(L, k)
+    assert ks[0] == 0.0 and ks[1] == 2.0 * np.pi / 1e-3 and ks[2] == 0.0
+    assert np.array_equal(snap_wavevector(L, [1e-3, 0.0, 0.0]), [1e-3, 0.0, 0.0])   # 1.6e-7 of 2 pi / L: kept
+    rve = inputs.polycrystal((4, 4, 4), L, 3, 96, 3, phases=("cu", "al"))
+    ops = Operators(rve, k)
+    assert int(ops.null_mask.sum()) == 1
+    w = np.linalg.eigvalsh(ops.dense("K"))
+    assert np.sum(np.abs(w) <= 1e-9 * w.max()) == 3
