@@ -152,3 +152,29 @@ def test_subspace_and_lanczos_agree_with_bound_stopping(lib):
     assert e0.max() <= 1e-6 and e1.max() <= 1e-6
     wref = _omega_ref(rve)
     assert np.max(np.abs(w0 - w1) / np.maximum(w0, wref)) <= 4e-6
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cu64_bench_workload_against_stored_oracle(lib, prec):
+    """The bench workload at full size (64^3, 64 grains, 12 modes) at the stored
+    oracle wave vectors (Gamma, on Gamma-X, X, on X-M toward M, R), in the
+    bench's solver setting (batched Lanczos, bound-based stopping)."""
+    path = os.path.join(HERE, "golden", "cu64.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values not generated")
+    g = json.load(open(path))
+    w_o = np.array(g["omega"])
+    ks = np.array(g["k"])[: len(w_o)]
+    rve = inputs.workload_rve(2, 0)
+    print(f"\n[case] cu64 stored oracle prec={prec}, {len(ks)} wave vectors", flush=True)
+    R = lib.Rve.from_inputs(rve, prec)
+    w, err, code, st = lib.bw_lowest_modes(R, ks, g["nmodes"], method=lib.BW_LANCZOS,
+                                           tol_omega=5e-6 if prec == 1 else 1e-10,
+                                           tol_lin=1e-6 if prec == 1 else 1e-10)
+    assert code == 0, lib.bw_last_error()
+    e = _relerr(w, w_o, _omega_ref(rve))
+    print(f"max rel err {e.max():.2e}, max bound {err.max():.2e}, {st['seconds']:.2f} s", flush=True)
+    assert e.max() <= BAR[prec]
+    nz = w_o > 1e-6 * _omega_ref(rve)
+    assert np.all(e[nz] <= err[nz] * 1.5 + 1e-12)
+    R.close()
