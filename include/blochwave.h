@@ -197,6 +197,12 @@ int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const double* con
  * microseconds of event overhead per launch. */
 int bw_timing_enable(int32_t enable);
 
+/* PCG iterations run as captured HIP graphs (one graph per chunk of iterations
+ * between host convergence checks, captured once per cell and buffer set and
+ * replayed) unless disabled here or while kernel timing is enabled.  Default:
+ * enabled.  Results are identical either way (same kernels, same order). */
+int bw_graphs_enable(int32_t enable);
+
 /* Restricts the timing to the kernel of that name (NULL or "" = all kernels). */
 int bw_timing_filter(const char* kernel_name);
 

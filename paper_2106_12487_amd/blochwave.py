@@ -71,6 +71,7 @@ _SIGS = {
     "bw_timing_enable": (_I, [_I]),
     "bw_timing_report": (ctypes.c_int64, [ctypes.c_char_p, ctypes.c_int64]),
     "bw_timing_filter": (_I, [ctypes.c_char_p]),
+    "bw_graphs_enable": (_I, [_I]),
     "bw_diag_copy": (_I, [_P, _P, ctypes.c_int64, _P]),
     "bw_unet_param_count": (ctypes.c_int64, []),
     "bw_unet_create": (_I, [ctypes.POINTER(_P), ctypes.c_uint64]),
@@ -114,6 +115,10 @@ def bw_last_error() -> str:
 
 def bw_timing_enable(enable: bool) -> None:
     lib().bw_timing_enable(int(bool(enable)))
+
+
+def bw_graphs_enable(enable: bool) -> None:
+    lib().bw_graphs_enable(int(bool(enable)))
 
 
 def bw_timing_filter(name) -> None:

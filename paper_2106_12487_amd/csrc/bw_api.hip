@@ -63,6 +63,13 @@ void drain_locked() {
 
 bool timing_enabled() { return g_timing.load(std::memory_order_relaxed); }
 
+namespace {
+std::atomic<bool> g_graphs{true};
+}
+// graphs are replayed only while no kernel timing is requested (timing brackets
+// every launch with events, which a replayed graph cannot do)
+bool graphs_enabled() { return g_graphs.load(std::memory_order_relaxed) && !timing_enabled(); }
+
 KTimer::KTimer(const char* n, hipStream_t st, long u) : name(n), s(st), units(u) {
   if (!timing_enabled()) return;
   std::lock_guard<std::mutex> lk(g_tmu);
@@ -206,10 +213,39 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
     bool any = false;
     for (int v = 0; v < nvec; ++v) any |= act[v] != 0;
     if (any) {
-      for (int c = 0; c < chunk; ++c) {
-        launch_pcg_apply<T>(r, d_qtab, rv, p, Ap, W, nvec, pd, s);
-        launch_pcg_update<T>(r, d_qtab, x, rv, p, Ap, nvec, pd, s);
-        res.block_iters += 1;
+      if (graphs_enabled()) {
+        // one chunk of iterations as a captured graph: identical launches with
+        // identical arguments every time (per-vector scalars live on the device)
+        const std::vector<const void*> key = {(const void*)d_qtab, x, rv, p, Ap, W, pd.rz, pd.partial,
+                                              (const void*)(long)nvec, (const void*)(long)chunk,
+                                              (const void*)(long)sizeof(T)};
+        if (!r->pcg_exec || r->pcg_key != key) {
+          if (r->pcg_exec) (void)hipGraphExecDestroy(r->pcg_exec);
+          if (r->pcg_graph) (void)hipGraphDestroy(r->pcg_graph);
+          r->pcg_exec = nullptr;
+          r->pcg_graph = nullptr;
+          r->pcg_key.clear();
+          if (!r->cap_stream) BW_HIP(hipStreamCreateWithFlags(&r->cap_stream, hipStreamNonBlocking));
+          BW_HIP(hipStreamSynchronize(s));
+          BW_HIP(hipStreamBeginCapture(r->cap_stream, hipStreamCaptureModeThreadLocal));
+          for (int c = 0; c < chunk; ++c) {
+            launch_pcg_apply<T>(r, d_qtab, rv, p, Ap, W, nvec, pd, r->cap_stream);
+            launch_pcg_update<T>(r, d_qtab, x, rv, p, Ap, nvec, pd, r->cap_stream);
+          }
+          hipGraph_t gr = nullptr;
+          BW_HIP(hipStreamEndCapture(r->cap_stream, &gr));
+          r->pcg_graph = gr;
+          BW_HIP(hipGraphInstantiate(&r->pcg_exec, gr, nullptr, nullptr, 0));
+          r->pcg_key = key;
+        }
+        BW_HIP(hipGraphLaunch(r->pcg_exec, s));
+        res.block_iters += chunk;
+      } else {
+        for (int c = 0; c < chunk; ++c) {
+          launch_pcg_apply<T>(r, d_qtab, rv, p, Ap, W, nvec, pd, s);
+          launch_pcg_update<T>(r, d_qtab, x, rv, p, Ap, nvec, pd, s);
+          res.block_iters += 1;
+        }
       }
       BW_HIP(hipMemcpyAsync(act.data(), pd.active, nvec * sizeof(int), hipMemcpyDeviceToHost, s));
       BW_HIP(hipMemcpyAsync(its.data(), pd.iters, nvec * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -334,6 +370,11 @@ extern "C" int bw_timing_enable(int32_t enable) {
   drain_locked();
   g_tot.clear();
   g_timing.store(enable != 0);
+  return BW_OK;
+}
+
+extern "C" int bw_graphs_enable(int32_t enable) {
+  g_graphs.store(enable != 0);
   return BW_OK;
 }
 
@@ -515,6 +556,9 @@ extern "C" int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3]
 
 extern "C" void bw_destroy_rve(bw_rve* r) {
   if (!r) return;
+  if (r->pcg_exec) (void)hipGraphExecDestroy(r->pcg_exec);
+  if (r->pcg_graph) (void)hipGraphDestroy(r->pcg_graph);
+  if (r->cap_stream) (void)hipStreamDestroy(r->cap_stream);
   (void)hipFree(r->d_gmap);
   (void)hipFree(r->d_C64);
   (void)hipFree(r->d_C32);

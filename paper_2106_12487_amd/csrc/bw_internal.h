@@ -43,6 +43,7 @@ struct Error {
 // (name, launches, milliseconds, work units = vectors processed)
 // ---------------------------------------------------------------------------
 bool timing_enabled();
+bool graphs_enabled();
 struct KTimer {
   const char* name;
   hipStream_t s;
@@ -155,6 +156,11 @@ struct bw_rve {
   double qcache_k[3] = {0, 0, 0};
   int qcache_nvec = -1;
   int pcg_counters_nvec = 0;
+  // captured PCG chunk (replayed with hipGraphLaunch while its key matches)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t pcg_graph = nullptr;
+  hipGraphExec_t pcg_exec = nullptr;
+  std::vector<const void*> pcg_key;
 };
 
 namespace bw {

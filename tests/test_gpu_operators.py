@@ -162,3 +162,29 @@ def test_invalid_arguments(lib):
     bad[0, 0] = -1.0
     with pytest.raises(lib.BlochwaveError):
         lib.Rve(rve.n, rve.L, rve.grain_map, bad, rve.rho, 0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pcg_graph_replays_match_eager_launches(lib, prec):
+    """PCG chunks replayed from captured HIP graphs (with host convergence checks
+    and copies between the replays) give the same iterates as eager launches,
+    bit for bit; so do eigen-solves built on them."""
+    torch = _dev()
+    rve = inputs.polycrystal((16, 16, 16), (L, L, L), 8, 94, 0, phases=("cu", "al"))
+    k = np.array([0.3, -0.2, 0.1]) * np.pi / L
+    b = _to_dev(_rand((5, 3, 16, 16, 16), 9), prec)
+    R = lib.Rve.from_inputs(rve, prec)
+    out = {}
+    for graphs in (False, True, True):
+        lib.bw_graphs_enable(graphs)
+        x = torch.zeros_like(b)
+        code, it, rr = lib.bw_pcg_solve(R, k, b, x, 1e-10 if prec == 0 else 1e-6)
+        assert code == 0 and it.min() > 8           # chunks of 8 iterations: several replays
+        w, _, c2, _ = lib.bw_lowest_modes(R, [k, 2 * k], 6, method=1, tol_omega=1e-6)
+        assert c2 == 0
+        out.setdefault(graphs, []).append((x.cpu().numpy(), it, w))
+    lib.bw_graphs_enable(True)
+    x0, it0, w0 = out[False][0]
+    for x1, it1, w1 in out[True]:
+        assert np.array_equal(it0, it1) and np.array_equal(x0, x1) and np.array_equal(w0, w1)
+    R.close()
