@@ -63,9 +63,14 @@ def _args():
 TOL_OMEGA = 5e-6   # a-posteriori bound target on the relative omega error (metric: 1e-5)
 
 
-def run_arm(bw, rve_in, ks, precision, steps, warmup, tol_lin, tol_eig, timing=False, method=1, kbatch=0):
+def run_arm(bw, rve_in, ks, precision, steps, warmup, tol_lin, tol_eig, timing=False, method=1, kbatch=0,
+            tune=True):
     import torch
     R = bw.Rve.from_inputs(rve_in, precision)
+    if tune:   # FFT schedule for this cell at the arm's PCG batch (setup, outside the timed region)
+        sp = bw.bw_autotune(R, min(len(ks), 64) if (method == 1 and kbatch == 0) else (kbatch or 16))
+        print(f"[bench] precision {precision} autotune: schedule {bw.bw_fft_schedule(R)}, speedup {sp:.3f}",
+              file=sys.stderr, flush=True)
     kw = dict(block=16, tol_eig=tol_eig, tol_lin=tol_lin, tol_omega=TOL_OMEGA, method=method, kbatch=kbatch)
     breakdown = None
     for i in range(warmup):
@@ -155,6 +160,7 @@ def operator_arm(bw, rve_in, nvec=8, reps=10):
     import numpy as np
     import torch
     R = bw.Rve.from_inputs(rve_in, bw.BW_MIXED)
+    bw.bw_autotune(R, nvec)
     rng = np.random.default_rng(3)
     u = torch.from_numpy(rng.standard_normal((nvec, 3) + tuple(rve_in.n)).astype(np.complex64)).to("cuda")
     y = torch.empty_like(u)
@@ -184,6 +190,8 @@ def uneven_arm(bw, tol_omega=5e-6):
     w = inputs.WORKLOADS[3]
     cells = [bw.Rve.from_inputs(inputs.workload_rve(3, i), bw.BW_MIXED) for i in range(len(w["grids"]))]
     ks = [inputs.workload_kpoints(3)] * len(cells)
+    for c in cells:
+        bw.bw_autotune(c, len(ks[0]))
     kw = dict(method=1, tol_omega=tol_omega, tol_lin=1e-6)
     nkt = sum(len(k) for k in ks)
     bw.bw_lowest_modes_batched(cells, ks, w["nmodes"], **kw)           # warm-up (workspaces)

@@ -122,6 +122,20 @@ int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3],
 /* Release the cell and every workspace the library allocated for it. */
 void bw_destroy_rve(bw_rve* rve);
 
+/* FFT schedule autotuner: for each axis, times bw_apply_K on nvec vectors
+ * (1 .. 256) with the register-resident kernels (power-of-two lengths 16 ..
+ * 256) and with the generic LDS kernels at the widest tile and at 1/2 and 1/4
+ * of it, and keeps the fastest for this cell (used by every later operator
+ * apply and PCG; results agree to rounding whatever the schedule).
+ * speedup_host (optional) receives time(default schedule) / time(chosen).
+ * Allocates and frees two scratch blocks of nvec vectors.  Synchronizes `stream`. */
+int bw_autotune(bw_rve* rve, int32_t nvec, double* speedup_host, void* stream);
+
+/* Get (set = 0) or set (set != 0) the FFT schedule of a cell per axis 0..2:
+ * reg[a] != 0 uses the register kernels where the length allows, cap[a] > 0
+ * limits the lines per tile of the generic kernels (0 = as many as fit). */
+int bw_fft_schedule(bw_rve* rve, int32_t reg[3], int32_t cap[3], int32_t set);
+
 /* Query grid / precision / volume averages of a cell.  Any output may be NULL. */
 int bw_rve_info(const bw_rve* rve, int32_t n[3], int32_t* precision, double C0_21[21],
                 double* rho_bar);

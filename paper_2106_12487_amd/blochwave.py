@@ -72,6 +72,8 @@ _SIGS = {
     "bw_timing_report": (ctypes.c_int64, [ctypes.c_char_p, ctypes.c_int64]),
     "bw_timing_filter": (_I, [ctypes.c_char_p]),
     "bw_graphs_enable": (_I, [_I]),
+    "bw_autotune": (_I, [_P, _I, _DP, _P]),
+    "bw_fft_schedule": (_I, [_P, _IP, _IP, _I]),
     "bw_diag_copy": (_I, [_P, _P, ctypes.c_int64, _P]),
     "bw_unet_param_count": (ctypes.c_int64, []),
     "bw_unet_create": (_I, [ctypes.POINTER(_P), ctypes.c_uint64]),
@@ -211,6 +213,21 @@ class Rve:
             self.close()
         except Exception:
             pass
+
+
+def bw_autotune(rve: Rve, nvec: int = 8, stream=None) -> float:
+    """Pick the fastest FFT schedule of the cell by timing; returns the speedup over the default."""
+    sp = ctypes.c_double()
+    _check(lib().bw_autotune(rve.handle, int(nvec), ctypes.byref(sp), _stream(stream)))
+    return sp.value
+
+
+def bw_fft_schedule(rve: Rve, reg=None, cap=None):
+    """Get the cell's FFT schedule (reg, cap), or set it when both are given."""
+    r = (ctypes.c_int32 * 3)(*(reg if reg is not None else (0, 0, 0)))
+    c = (ctypes.c_int32 * 3)(*(cap if cap is not None else (0, 0, 0)))
+    _check(lib().bw_fft_schedule(rve.handle, r, c, int(reg is not None and cap is not None)))
+    return list(r), list(c)
 
 
 def bw_apply_K(rve: Rve, k, u, y, stream=None) -> None:

@@ -657,6 +657,80 @@ extern "C" int bw_apply_P(bw_rve* r, const double k[3], const void* u, void* y, 
   BW_GUARD_END
 }
 
+// ---------------------------------------------------------------------------
+// FFT schedule: register kernels on/off and tile caps per axis, chosen by timing
+// ---------------------------------------------------------------------------
+static void drop_graph(bw_rve* r) {
+  if (r->pcg_exec) (void)hipGraphExecDestroy(r->pcg_exec);
+  if (r->pcg_graph) (void)hipGraphDestroy(r->pcg_graph);
+  r->pcg_exec = nullptr;
+  r->pcg_graph = nullptr;
+  r->pcg_key.clear();
+}
+
+template <typename T> static int generic_lines(const bw_rve* r, int axis) {
+  const Geom& g = r->g;
+  if (axis == 2) return row_tile<T>(g.n2, (long)g.n0 * g.n1).NR;
+  if (axis == 1) return axis1_tile<T>(g.n1, g.n2, 6L * g.n0 * g.n2).LT;
+  return axis0_tile<T>(g.n0, (long)g.n1 * g.n2).LT;
+}
+
+template <typename T> static double autotune_impl(bw_rve* r, int nvec, hipStream_t s) {
+  const Geom& g = r->g;
+  DevBuf ub, yb;
+  cplx<T>* u = (cplx<T>*)ub.get((size_t)nvec * 3 * g.nvox * sizeof(cplx<T>));
+  cplx<T>* y = (cplx<T>*)yb.get((size_t)nvec * 3 * g.nvox * sizeof(cplx<T>));
+  BW_HIP(hipMemsetAsync(u, 0, (size_t)nvec * 3 * g.nvox * sizeof(cplx<T>), s));
+  const double k[3] = {0.3 * M_PI / r->L[0], 0.1 * M_PI / r->L[1], 0.05 * M_PI / r->L[2]};
+  const double* q = qtab_for(r, k, nvec, s);
+  cplx<T>* W = ws<T>(r).work((size_t)nvec * 6 * g.nvox);
+  hipEvent_t e0, e1;
+  BW_HIP(hipEventCreate(&e0));
+  BW_HIP(hipEventCreate(&e1));
+  auto time_apply = [&]() {
+    launch_apply_K<T>(r, q, u, y, nvec, 1.0, W, s);
+    BW_HIP(hipEventRecord(e0, s));
+    for (int rep = 0; rep < 3; ++rep) launch_apply_K<T>(r, q, u, y, nvec, 1.0, W, s);
+    BW_HIP(hipEventRecord(e1, s));
+    BW_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    BW_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms / 3.0;
+  };
+  for (int a = 0; a < 3; ++a) {
+    r->tune_reg[a] = 1;
+    r->tune_cap[a] = 0;
+  }
+  const double t_default = time_apply();
+  const int n[3] = {g.n0, g.n1, g.n2};
+  for (int a : {2, 1, 0}) {
+    if (n[a] == 1) continue;
+    std::vector<std::pair<int, int>> cand = {{1, 0}, {0, 0}};
+    const int gl = generic_lines<T>(r, a);
+    for (int c = gl / 2; c >= 1 && c >= gl / 4; c /= 2) cand.push_back({0, c});
+    double best = 1e300;
+    std::pair<int, int> pick = cand[0];
+    for (auto& c : cand) {
+      r->tune_reg[a] = c.first;
+      r->tune_cap[a] = c.second;
+      const double t = time_apply();
+      if (t < best) {
+        best = t;
+        pick = c;
+      }
+    }
+    r->tune_reg[a] = pick.first;
+    r->tune_cap[a] = pick.second;
+  }
+  const double t_best = time_apply();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ub.release();
+  yb.release();
+  drop_graph(r);
+  return t_default / t_best;
+}
+
 template <typename T>
 static int pcg_entry(bw_rve* r, const double* k, const void* b, void* x, int nrhs, double rtol, int maxit,
                      int32_t* iters, double* relres, hipStream_t s) {
@@ -707,5 +781,36 @@ extern "C" int bw_pcg_solve(bw_rve* r, const double k[3], const void* b, void* x
   hipStream_t s = (hipStream_t)stream;
   if (r->precision == BW_FP64) return pcg_entry<double>(r, k, b, x, nrhs, rtol, maxit, iters, relres, s);
   return pcg_entry<float>(r, k, b, x, nrhs, rtol, maxit, iters, relres, s);
+  BW_GUARD_END
+}
+
+extern "C" int bw_autotune(bw_rve* r, int32_t nvec, double* speedup_host, void* stream) {
+  BW_GUARD_BEGIN
+  BW_REQUIRE(r, BW_EINVAL, "null cell");
+  BW_REQUIRE(nvec >= 1 && nvec <= 256, BW_EINVAL, "nvec out of range (1 .. 256)");
+  hipStream_t s = (hipStream_t)stream;
+  const double sp = r->precision == BW_FP64 ? autotune_impl<double>(r, nvec, s) : autotune_impl<float>(r, nvec, s);
+  if (speedup_host) *speedup_host = sp;
+  return BW_OK;
+  BW_GUARD_END
+}
+
+extern "C" int bw_fft_schedule(bw_rve* r, int32_t reg[3], int32_t cap[3], int32_t set) {
+  BW_GUARD_BEGIN
+  BW_REQUIRE(r && reg && cap, BW_EINVAL, "null argument");
+  if (set) {
+    for (int a = 0; a < 3; ++a) BW_REQUIRE(cap[a] >= 0, BW_EINVAL, "tile cap must be >= 0");
+    for (int a = 0; a < 3; ++a) {
+      r->tune_reg[a] = reg[a] ? 1 : 0;
+      r->tune_cap[a] = cap[a];
+    }
+    drop_graph(r);
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      reg[a] = r->tune_reg[a];
+      cap[a] = r->tune_cap[a];
+    }
+  }
+  return BW_OK;
   BW_GUARD_END
 }

@@ -156,6 +156,11 @@ struct bw_rve {
   double qcache_k[3] = {0, 0, 0};
   int qcache_nvec = -1;
   int pcg_counters_nvec = 0;
+  // FFT schedule per axis (0, 1, 2): register kernels where the length allows
+  // (tune_reg) and the cap on lines per tile of the generic LDS kernels (0 =
+  // as many as fit); set by bw_autotune
+  int tune_reg[3] = {1, 1, 1};
+  int tune_cap[3] = {0, 0, 0};
   // captured PCG chunk (replayed with hipGraphLaunch while its key matches)
   hipStream_t cap_stream = nullptr;
   hipGraph_t pcg_graph = nullptr;

@@ -699,26 +699,26 @@ inline int ilog2(int x) {
   return l;
 }
 
-template <typename T> RowTile row_tile(int N2, long rows_per_vec) {
+template <typename T> RowTile row_tile(int N2, long rows_per_vec, int cap = 0) {
   constexpr int TP = TileCfg<T>::TP;
   int NR = 1;
-  while (NR * 2 * N2 <= TP && rows_per_vec % (NR * 2) == 0) NR *= 2;
+  while (NR * 2 * N2 <= TP && rows_per_vec % (NR * 2) == 0 && (cap <= 0 || NR * 2 <= cap)) NR *= 2;
   return RowTile{NR, ilog2(NR), (int)(rows_per_vec / NR)};
 }
 
-template <typename T> ColTile axis1_tile(int N1, int n2, long lines_per_vec) {
+template <typename T> ColTile axis1_tile(int N1, int n2, long lines_per_vec, int cap = 0) {
   constexpr int TP = TileCfg<T>::TP;
   int LT = 1;
   while (LT * 2 * N1 <= TP && LT * 2 <= NT && lines_per_vec % (LT * 2) == 0 &&
-         (n2 % (LT * 2) == 0 || (LT * 2) % n2 == 0))
+         (n2 % (LT * 2) == 0 || (LT * 2) % n2 == 0) && (cap <= 0 || LT * 2 <= cap))
     LT *= 2;
   return ColTile{LT, ilog2(LT), (int)(lines_per_vec / LT)};
 }
 
-template <typename T> ColTile axis0_tile(int N0, long n12) {
+template <typename T> ColTile axis0_tile(int N0, long n12, int cap = 0) {
   constexpr int TP = TileCfg<T>::TP;
   int LT = 1;
-  while (LT * 2 * N0 <= TP && LT * 2 <= NT && n12 % (LT * 2) == 0) LT *= 2;
+  while (LT * 2 * N0 <= TP && LT * 2 <= NT && n12 % (LT * 2) == 0 && (cap <= 0 || LT * 2 <= cap)) LT *= 2;
   return ColTile{LT, ilog2(LT), (int)(n12 / LT)};
 }
 
@@ -797,7 +797,7 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
   const Geom& g = r->g;
   constexpr int NC = OP == 0 ? 6 : 3;
   const long n12 = (long)g.n1 * g.n2;
-  const bool reg1 = reg_len(g.n1) && g.n2 % reg_lines(g.n1) == 0;
+  const bool reg1 = r->tune_reg[1] && reg_len(g.n1) && g.n2 % reg_lines(g.n1) == 0;
   auto axis1 = [&](auto INVc) {
     constexpr bool INV = decltype(INVc)::value;
     const char* name = active ? (INV ? "k_axis1_inv_pcg" : "k_axis1_fwd_pcg")
@@ -818,7 +818,7 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
       return;
     }
     with_n(g.n1, [&](auto N1) {
-      ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2);
+      ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2, r->tune_cap[1]);
       if (active)
         BW_LAUNCH(name, units, (k_axis1<T, decltype(N1)::value, INV, 1>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W,
                   g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
@@ -831,7 +831,7 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
   const T* tab = tab_override ? tab_override : (OP == 0 ? ctab<T>(r) : rhotab<T>(r));
   const char* name0 = active ? "k_axis0_contract_pcg" : (OP == 0 ? "k_axis0_contract" : "k_axis0_mass");
   const long units0 = active ? 0 : nvec;
-  if (reg_len(g.n0) && n12 % reg_lines(g.n0) == 0 && (long)NC * g.nvox < (1L << 31)) {
+  if (r->tune_reg[0] && reg_len(g.n0) && n12 % reg_lines(g.n0) == 0 && (long)NC * g.nvox < (1L << 31)) {
     with_reg(g.n0, [&](auto N0) {
       constexpr int n0c = decltype(N0)::value;
       const int tpv = (int)(n12 / reg_lines(n0c));
@@ -844,7 +844,7 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
     });
   } else {
     with_n(g.n0, [&](auto N0) {
-      ColTile ct = axis0_tile<T>(N0, n12);
+      ColTile ct = axis0_tile<T>(N0, n12, r->tune_cap[0]);
       if (active)
         BW_LAUNCH(name0, units0, (k_axis0_op<T, decltype(N0)::value, OP, 1>), dim3(nvec * ct.tpv), dim3(NT), 0, s,
                   W, n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
@@ -862,7 +862,7 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   const Geom& g = r->g;
   const int* active = mode == 1 ? pd->active : nullptr;
   PcgDev dummy{};
-  const bool reg2 = reg_len(g.n2) && ((long)g.n0 * g.n1) % reg_lines(g.n2) == 0;
+  const bool reg2 = r->tune_reg[2] && reg_len(g.n2) && ((long)g.n0 * g.n1) % reg_lines(g.n2) == 0;
   const int tpvr = reg2 ? (int)(((long)g.n0 * g.n1) / reg_lines(g.n2)) : 0;
   if (reg2) {
     with_reg(g.n2, [&](auto N2) {
@@ -878,7 +878,7 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   } else {
     with_n(g.n2, [&](auto N2) {
       constexpr int n2c = decltype(N2)::value;
-      RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1);
+      RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1, r->tune_cap[2]);
       if (mode == 0)
         BW_LAUNCH("k_strain_row", nvec, (k_strain_row<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u,
                   (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active,
@@ -904,7 +904,7 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   } else {
     with_n(g.n2, [&](auto N2) {
       constexpr int n2c = decltype(N2)::value;
-      RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1);
+      RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1, r->tune_cap[2]);
       nblk = rt.tpv;
       if (mode == 0)
         BW_LAUNCH("k_row_div", nvec, (k_row_div<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab,
@@ -936,7 +936,7 @@ void apply_M_impl(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, doubl
   const long rows = 3L * g.n0 * g.n1;
   with_n(g.n2, [&](auto N2) {
     constexpr int n2c = decltype(N2)::value;
-    RowTile rt = row_tile<T>(n2c, rows);
+    RowTile rt = row_tile<T>(n2c, rows, r->tune_cap[2]);
     BW_LAUNCH("k_row_inv_mass", nvec, (k_row_plain<T, n2c, true>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, W, rt,
               (int)rows,
                        twiddles<T>(r, 2), (const int*)nullptr);
@@ -944,7 +944,7 @@ void apply_M_impl(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, doubl
   launch_middle<T, 1>(r, W, nvec, (T)(scale / (double)g.nvox), nullptr, s, tab);
   with_n(g.n2, [&](auto N2) {
     constexpr int n2c = decltype(N2)::value;
-    RowTile rt = row_tile<T>(n2c, rows);
+    RowTile rt = row_tile<T>(n2c, rows, r->tune_cap[2]);
     BW_LAUNCH("k_row_fwd_mass", nvec, (k_row_plain<T, n2c, false>), dim3(nvec * rt.tpv), dim3(NT), 0, s,
               (const cplx<T>*)W, y, rt,
                        (int)rows, twiddles<T>(r, 2), (const int*)nullptr);

@@ -188,3 +188,33 @@ def test_pcg_graph_replays_match_eager_launches(lib, prec):
     for x1, it1, w1 in out[True]:
         assert np.array_equal(it0, it1) and np.array_equal(x0, x1) and np.array_equal(w0, w1)
     R.close()
+
+
+@pytest.mark.parametrize("n", [(40, 24, 48), (64, 16, 32)])
+def test_fft_schedules_and_autotune_keep_parity(lib, n):
+    """Every FFT schedule (register kernels on/off, generic tile caps) gives the
+    oracle's K to the same bar, and so does the one the autotuner picks."""
+    torch = _dev()
+    rve = inputs.polycrystal(n, (L, L, L), 6, 93, 0)
+    k = np.array([0.2, 0.35, -0.1]) * np.pi / L
+    ops = Operators(rve, k)
+    u = _rand((2, 3) + n, 13)
+    ref = ops.apply_K(u)
+    for prec in (0, 1):
+        R = lib.Rve.from_inputs(rve, prec)
+        ud = _to_dev(u, prec)
+        y = torch.empty_like(ud)
+        for reg, cap in [((1, 1, 1), (0, 0, 0)), ((0, 0, 0), (0, 0, 0)), ((0, 0, 0), (2, 4, 1)),
+                         ((1, 0, 1), (1, 2, 2))]:
+            lib.bw_fft_schedule(R, reg, cap)
+            assert lib.bw_fft_schedule(R) == (list(reg), list(cap))
+            lib.bw_apply_K(R, k, ud, y)
+            torch.cuda.synchronize()
+            assert _rel(y.cpu().numpy(), ref) <= TOL[prec], (reg, cap)
+        sp = lib.bw_autotune(R, 4)
+        print(f"\n[case] autotune n={n} prec={prec}: schedule {lib.bw_fft_schedule(R)}, speedup {sp:.2f}", flush=True)
+        assert sp >= 0.8
+        lib.bw_apply_K(R, k, ud, y)
+        torch.cuda.synchronize()
+        assert _rel(y.cpu().numpy(), ref) <= TOL[prec]
+        R.close()
