@@ -255,7 +255,7 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
         for (int v = 0; v < nvec; ++v) d += its[v] - its_prev[v];
         its_prev = its;
         for (const char* nm : {"k_strain_row_pcg", "k_axis1_inv_pcg", "k_axis0_contract_pcg", "k_axis1_fwd_pcg",
-                               "k_row_div_pcg", "k_pcg_update"})
+                               "k_plane_contract_pcg", "k_row_div_pcg", "k_pcg_update"})
           timing_add_units(nm, d);
       }
       bool cap = false;
@@ -523,6 +523,14 @@ extern "C" int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3]
     BW_HIP(hipMalloc(&r->d_rho64, n_grains * sizeof(double)));
     BW_HIP(hipMalloc(&r->d_rho32, n_grains * sizeof(float)));
     BW_HIP(hipMemcpy(r->d_gmap, grain_map_host, nvox * sizeof(uint16_t), hipMemcpyHostToDevice));
+    if (n[0] == 64 && n[1] == 64) {
+      std::vector<uint16_t> gt(nvox);
+      for (long i0 = 0; i0 < 64; ++i0)
+        for (long i1 = 0; i1 < 64; ++i1)
+          for (long i2 = 0; i2 < n[2]; ++i2) gt[(i2 * 64 + i0) * 64 + i1] = grain_map_host[(i0 * 64 + i1) * n[2] + i2];
+      BW_HIP(hipMalloc(&r->d_gmapT, nvox * sizeof(uint16_t)));
+      BW_HIP(hipMemcpy(r->d_gmapT, gt.data(), nvox * sizeof(uint16_t), hipMemcpyHostToDevice));
+    }
     BW_HIP(hipMemcpy(r->d_C64, r->C21s_host.data(), r->C21s_host.size() * sizeof(double), hipMemcpyHostToDevice));
     BW_HIP(hipMemcpy(r->d_C32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
     BW_HIP(hipMemcpy(r->d_rho64, r->rhos_host.data(), n_grains * sizeof(double), hipMemcpyHostToDevice));
@@ -560,6 +568,7 @@ extern "C" void bw_destroy_rve(bw_rve* r) {
   if (r->pcg_graph) (void)hipGraphDestroy(r->pcg_graph);
   if (r->cap_stream) (void)hipStreamDestroy(r->cap_stream);
   (void)hipFree(r->d_gmap);
+  (void)hipFree(r->d_gmapT);
   (void)hipFree(r->d_C64);
   (void)hipFree(r->d_C32);
   (void)hipFree(r->d_rho64);
@@ -701,7 +710,13 @@ template <typename T> static double autotune_impl(bw_rve* r, int nvec, hipStream
     r->tune_reg[a] = 1;
     r->tune_cap[a] = 0;
   }
+  r->tune_plane = 1;
   const double t_default = time_apply();
+  if (r->d_gmapT && sizeof(T) == 4) {
+    r->tune_plane = 0;
+    const double t_noplane = time_apply();
+    r->tune_plane = t_noplane < t_default ? 0 : 1;
+  }
   const int n[3] = {g.n0, g.n1, g.n2};
   for (int a : {2, 1, 0}) {
     if (n[a] == 1) continue;
@@ -800,6 +815,7 @@ extern "C" int bw_fft_schedule(bw_rve* r, int32_t reg[3], int32_t cap[3], int32_
   BW_REQUIRE(r && reg && cap, BW_EINVAL, "null argument");
   if (set) {
     for (int a = 0; a < 3; ++a) BW_REQUIRE(cap[a] >= 0, BW_EINVAL, "tile cap must be >= 0");
+    r->tune_plane = reg[0] && reg[1] ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
       r->tune_reg[a] = reg[a] ? 1 : 0;
       r->tune_cap[a] = cap[a];

@@ -131,7 +131,9 @@ template <int N> struct ColSlotR {
 // ---------------------------------------------------------------------------
 // K, first pass (same contract as k_strain_row; tpv = n0 n1 / LINES)
 // ---------------------------------------------------------------------------
-template <typename T, int N, int MODE>
+// TR: write the strain to the transposed work layout [vec][c][i2][i0 i1] (the
+// (i0, i1) planes contiguous, for the plane pass) instead of [vec][c][i0 i1][i2].
+template <typename T, int N, int MODE, bool TR = false>
 __global__ __launch_bounds__(NT) void k_strain_row_r(const cplx<T>* __restrict__ U, cplx<T>* __restrict__ Pp,
                                                      cplx<T>* __restrict__ W, const double* __restrict__ qtab,
                                                      int n0, int n1, long nvox, int tpv,
@@ -195,15 +197,22 @@ __global__ __launch_bounds__(NT) void k_strain_row_r(const cplx<T>* __restrict__
       }
     }
     fft_dit<T, N, true>(e, lds[0], lds[1], parity, slot, j, w);
+    if (TR) {
+      const long n01 = nvox / N;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) W[((size_t)v * 6 + c) * nvox + rbase + F::posB(j, m)] = e[m];
+      for (int m = 0; m < 8; ++m) W[(((size_t)v * 6 + c) * N + F::posB(j, m)) * n01 + row] = e[m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) W[((size_t)v * 6 + c) * nvox + rbase + F::posB(j, m)] = e[m];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // K, last pass (same contract as k_row_div; partials per tile)
 // ---------------------------------------------------------------------------
-template <typename T, int N, int MODE>
+// TR: read the stress from the transposed work layout (see k_strain_row_r).
+template <typename T, int N, int MODE, bool TR = false>
 __global__ __launch_bounds__(NT) void k_row_div_r(const cplx<T>* __restrict__ W, cplx<T>* __restrict__ Y,
                                                   const double* __restrict__ qtab, int n0, int n1, long nvox,
                                                   int tpv, const cplx<T>* __restrict__ tw,
@@ -233,9 +242,14 @@ __global__ __launch_bounds__(NT) void k_row_div_r(const cplx<T>* __restrict__ W,
   V acc[3][8];
 #pragma unroll
   for (int m = 0; m < 8; ++m) acc[0][m] = acc[1][m] = acc[2][m] = V{0, 0};
+  const long n01 = nvox / N;
+  auto widx = [&](int c, int m) -> size_t {
+    return TR ? (((size_t)v * 6 + c) * N + F::posA(j, m)) * n01 + row
+              : ((size_t)v * 6 + c) * nvox + rbase + F::posA(j, m);
+  };
   V nxt[8];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) nxt[m] = W[((size_t)v * 6) * nvox + rbase + F::posA(j, m)];
+  for (int m = 0; m < 8; ++m) nxt[m] = W[widx(0, m)];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     V e[8];
@@ -243,7 +257,7 @@ __global__ __launch_bounds__(NT) void k_row_div_r(const cplx<T>* __restrict__ W,
     for (int m = 0; m < 8; ++m) e[m] = nxt[m];
     if (c < 5) {
 #pragma unroll
-      for (int m = 0; m < 8; ++m) nxt[m] = W[((size_t)v * 6 + c + 1) * nvox + rbase + F::posA(j, m)];
+      for (int m = 0; m < 8; ++m) nxt[m] = W[widx(c + 1, m)];
     }
     fft_dit<T, N, false>(e, lds[0], lds[1], parity, slot, j, w);
 #pragma unroll
@@ -367,6 +381,82 @@ __global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, l
     fft_dif<T, N, false>(x[c], lds[0], lds[1], parity, slot, j, w);
 #pragma unroll
     for (int m = 0; m < 8; ++m) Xv[c * cs + pos + F::posA(j, m) * s12] = x[c][m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plane pass for n0 = n1 = 64 on the transposed work layout: one workgroup
+// per (vector, i2) takes the 64 x 64 (i0, i1) plane of all six strain
+// components, inverse 2D FFT (axis 1 then axis 0, register transforms with a
+// transposition through LDS between them), stiffness contraction, forward 2D
+// FFT, and writes the stress back in place: the three middle passes of K in one
+// read and one write of the work array.
+// ---------------------------------------------------------------------------
+constexpr int PLANE_NT = 512;       // 64 lines x 8 threads
+constexpr int PLANE_TPITCH = 65;    // transposition buffer pitch
+template <typename T, int PCG = 0>
+__global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W, int n2, long nvox,
+                                                         const uint16_t* __restrict__ gmapT, const T* __restrict__ Ctab,
+                                                         T scale, const cplx<T>* __restrict__ tw0,
+                                                         const cplx<T>* __restrict__ tw1,
+                                                         const int* __restrict__ active) {
+  using V = cplx<T>;
+  using F = RegFFT<64>;
+  constexpr int NB = 64 * (64 + 8);   // 64 lines at the skewed row pitch; holds the 64 x 65 transposition too
+  __shared__ V lds[2][NB];
+  const int v = blockIdx.x / n2;
+  if (active && !active[v]) return;
+  const int i2 = blockIdx.x - v * n2;
+  const int tid = threadIdx.x;
+  const int line = tid >> 3, j = tid & 7;
+  V w0[1][8], w1[1][8];
+  load_twr<T, 64>(w0, tw0, j);
+  load_twr<T, 64>(w1, tw1, j);
+  V* Wv = W + (size_t)v * 6 * nvox + (size_t)i2 * 4096;
+  const RowSlotR<64> slot{line * (64 + 8)};
+  int parity = 0;
+  V x[6][8];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[c][m] = Wv[(size_t)c * nvox + line * 64 + j + 8 * m];  // (i0 = line, i1 = j + 8m)
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    fft_dit<T, 64, true>(x[c], lds[0], lds[1], parity, slot, j, w1);   // along i1
+    V* buf = (parity++ & 1) ? lds[1] : lds[0];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) buf[line * PLANE_TPITCH + j + 8 * m] = x[c][m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[c][m] = buf[(j + 8 * m) * PLANE_TPITCH + line];   // (i0 = j + 8m, i1 = line)
+    fft_dit<T, 64, true>(x[c], lds[0], lds[1], parity, slot, j, w0);   // along i0
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int g = gmapT[(size_t)i2 * 4096 + (j + 8 * m) * 64 + line];
+    T cg[21];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) cg[i] = Ctab[g * 21 + i];
+    V e[6], sg[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] = x[c][m];
+    contract6<T, V>(cg, e, sg, scale);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) x[c][m] = sg[c];
+    asm volatile("" ::: "memory");
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    fft_dit<T, 64, false>(x[c], lds[0], lds[1], parity, slot, j, w0);  // along i0
+    V* buf = (parity++ & 1) ? lds[1] : lds[0];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) buf[(j + 8 * m) * PLANE_TPITCH + line] = x[c][m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[c][m] = buf[line * PLANE_TPITCH + j + 8 * m];   // (i0 = line, i1 = j + 8m)
+    fft_dit<T, 64, false>(x[c], lds[0], lds[1], parity, slot, j, w1);  // along i1
+#pragma unroll
+    for (int m = 0; m < 8; ++m) Wv[(size_t)c * nvox + line * 64 + j + 8 * m] = x[c][m];
   }
 }
 

@@ -137,6 +137,7 @@ struct bw_rve {
   std::vector<uint16_t> gmap_host;
   // device copies
   uint16_t* d_gmap = nullptr;
+  uint16_t* d_gmapT = nullptr;   // [i2][i0][i1] copy for the plane pass (n0 = n1 = 64 only)
   double* d_C64 = nullptr;
   float* d_C32 = nullptr;
   double* d_rho64 = nullptr;
@@ -161,6 +162,7 @@ struct bw_rve {
   // as many as fit); set by bw_autotune
   int tune_reg[3] = {1, 1, 1};
   int tune_cap[3] = {0, 0, 0};
+  int tune_plane = 1;   // FP32 cells with n0 = n1 = 64: the fused plane pass
   // captured PCG chunk (replayed with hipGraphLaunch while its key matches)
   hipStream_t cap_stream = nullptr;
   hipGraph_t pcg_graph = nullptr;

@@ -864,10 +864,21 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   PcgDev dummy{};
   const bool reg2 = r->tune_reg[2] && reg_len(g.n2) && ((long)g.n0 * g.n1) % reg_lines(g.n2) == 0;
   const int tpvr = reg2 ? (int)(((long)g.n0 * g.n1) / reg_lines(g.n2)) : 0;
+  // fused plane pass (FP32, n0 = n1 = 64): strain and stress in the transposed work layout
+  const bool plane = std::is_same<T, float>::value && reg2 && r->tune_plane && r->d_gmapT && g.n0 == 64 &&
+                     g.n1 == 64 && 6L * g.nvox < (1L << 31);
   if (reg2) {
     with_reg(g.n2, [&](auto N2) {
       constexpr int n2c = decltype(N2)::value;
-      if (mode == 0)
+      if (plane) {
+        if (mode == 0)
+          BW_LAUNCH("k_strain_row", nvec, (k_strain_row_r<T, n2c, 0, true>), dim3(nvec * tpvr), dim3(NT), 0, s, u,
+                    (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active,
+                    (const double*)nullptr, c0v<T>(r));
+        else
+          BW_LAUNCH("k_strain_row_pcg", 0, (k_strain_row_r<T, n2c, 1, true>), dim3(nvec * tpvr), dim3(NT), 0, s, u,
+                    pp, W, d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
+      } else if (mode == 0)
         BW_LAUNCH("k_strain_row", nvec, (k_strain_row_r<T, n2c, 0>), dim3(nvec * tpvr), dim3(NT), 0, s, u,
                   (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active,
                   (const double*)nullptr, c0v<T>(r));
@@ -888,12 +899,33 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
                   d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
     });
   }
-  launch_middle<T, 0>(r, W, nvec, (T)(1.0 / (double)g.nvox), active, s);
+  if (plane) {
+    if (active)
+      BW_LAUNCH("k_plane_contract_pcg", 0, (k_plane64<T, 1>), dim3(nvec * g.n2), dim3(PLANE_NT), 0, s, W, g.n2,
+                g.nvox, r->d_gmapT, ctab<T>(r), (T)(1.0 / (double)g.nvox), twiddles<T>(r, 0), twiddles<T>(r, 1),
+                active);
+    else
+      BW_LAUNCH("k_plane_contract", nvec, (k_plane64<T, 0>), dim3(nvec * g.n2), dim3(PLANE_NT), 0, s, W, g.n2,
+                g.nvox, r->d_gmapT, ctab<T>(r), (T)(1.0 / (double)g.nvox), twiddles<T>(r, 0), twiddles<T>(r, 1),
+                active);
+  } else {
+    launch_middle<T, 0>(r, W, nvec, (T)(1.0 / (double)g.nvox), active, s);
+  }
   int nblk = 0;
   if (reg2) {
     nblk = tpvr;
     with_reg(g.n2, [&](auto N2) {
       constexpr int n2c = decltype(N2)::value;
+      if (plane) {
+        if (mode == 0)
+          BW_LAUNCH("k_row_div", nvec, (k_row_div_r<T, n2c, 0, true>), dim3(nvec * tpvr), dim3(NT), 0, s, W, y,
+                    d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, (const cplx<T>*)nullptr, dummy,
+                    (T)scale);
+        else
+          BW_LAUNCH("k_row_div_pcg", 0, (k_row_div_r<T, n2c, 1, true>), dim3(nvec * tpvr), dim3(NT), 0, s, W, y,
+                    d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, (const cplx<T>*)pp, *pd, (T)scale);
+        return;
+      }
       if (mode == 0)
         BW_LAUNCH("k_row_div", nvec, (k_row_div_r<T, n2c, 0>), dim3(nvec * tpvr), dim3(NT), 0, s, W, y, d_qtab,
                   g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, (const cplx<T>*)nullptr, dummy, (T)scale);

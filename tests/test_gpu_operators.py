@@ -50,6 +50,8 @@ CASES = [
     ((128, 2, 128), 6, [0.45, 0.0, -0.15]),
     ((4, 256, 32), 4, [-0.3, 0.25, 0.5]),
     ((32, 16, 16), 5, [0.0, -0.5, 0.5]),
+    # n0 = n1 = 64: the fused plane pass on the transposed work layout (FP32)
+    ((64, 64, 16), 7, [0.3, 0.45, -0.2]),
 ]
 
 
@@ -110,7 +112,7 @@ def test_pcg_matches_dense_solution(lib, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("n", [(64, 4, 64), (8, 64, 32), (128, 2, 128), (32, 16, 16)])
+@pytest.mark.parametrize("n", [(64, 4, 64), (8, 64, 32), (128, 2, 128), (32, 16, 16), (64, 64, 8)])
 def test_pcg_on_register_fft_axes(lib, n, prec):
     print(f"\n[case] pcg n={n} prec={prec}", flush=True)
     torch = _dev()
@@ -190,7 +192,7 @@ def test_pcg_graph_replays_match_eager_launches(lib, prec):
     R.close()
 
 
-@pytest.mark.parametrize("n", [(40, 24, 48), (64, 16, 32)])
+@pytest.mark.parametrize("n", [(40, 24, 48), (64, 16, 32), (64, 64, 16)])
 def test_fft_schedules_and_autotune_keep_parity(lib, n):
     """Every FFT schedule (register kernels on/off, generic tile caps) gives the
     oracle's K to the same bar, and so does the one the autotuner picks."""
