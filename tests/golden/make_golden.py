@@ -5,6 +5,7 @@ here touches the HIP path.  Usage:
 
     python tests/golden/make_golden.py cu16      # 16^3, 8 grains, all 11 k on Gamma-X
     python tests/golden/make_golden.py cu64      # 64^3, 64 grains, sampled k of the path (Lanczos)
+    python tests/golden/make_golden.py cual32    # 32^3 Cu/Al cell of the uneven workload, 4 k (Lanczos)
 
 Output: tests/golden/<name>.json with the wave vectors (rad/m), omega (rad/s)
 and the oracle settings.
@@ -42,6 +43,10 @@ def run(name):
         idx = nearest_path_indices(2, "GXMR")
         mid = [int(np.argmin(np.linalg.norm(ks - 0.5 * inputs.sc_points(inputs.L_MM)["X"], axis=1)))]
         idx = sorted(set(idx + mid))
+        method = "lanczos"
+    elif name == "cual32":
+        cfg, nmodes, block = 3, 8, 16
+        idx = [0, 5, 11, 17]
         method = "lanczos"
     else:
         raise SystemExit(f"unknown golden set {name}")

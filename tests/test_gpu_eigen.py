@@ -178,3 +178,31 @@ def test_cu64_bench_workload_against_stored_oracle(lib, prec):
     nz = w_o > 1e-6 * _omega_ref(rve)
     assert np.all(e[nz] <= err[nz] * 1.5 + 1e-12)
     R.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cual32_two_phase_cell_against_stored_oracle(lib, prec):
+    """The first cell of the uneven workload (32^3 Cu/Al two-phase polycrystal,
+    densities differ so M is not a multiple of the identity) at four stored
+    oracle wave vectors of the G-X-M-G-R path (Gamma, on G-X, on X-M, on M-G),
+    8 modes, batched Lanczos with bound-based stopping."""
+    path = os.path.join(HERE, "golden", "cual32.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values not generated")
+    g = json.load(open(path))
+    w_o = np.array(g["omega"])
+    ks = np.array(g["k"])
+    rve = inputs.workload_rve(g["config"], 0)
+    assert len(set(np.round(rve.rho, 6))) == 2
+    print(f"\n[case] cual32 stored oracle prec={prec}, {len(ks)} wave vectors", flush=True)
+    R = lib.Rve.from_inputs(rve, prec)
+    w, err, code, st = lib.bw_lowest_modes(R, ks, g["nmodes"], method=lib.BW_LANCZOS,
+                                           tol_omega=5e-6 if prec == 1 else 1e-10,
+                                           tol_lin=1e-6 if prec == 1 else 1e-10)
+    assert code == 0, lib.bw_last_error()
+    e = _relerr(w, w_o, _omega_ref(rve))
+    print(f"max rel err {e.max():.2e}, max bound {err.max():.2e}, {st['seconds']:.2f} s", flush=True)
+    assert e.max() <= BAR[prec]
+    nz = w_o > 1e-6 * _omega_ref(rve)
+    assert np.all(e[nz] <= err[nz] * 1.5 + 1e-12)
+    R.close()
