@@ -58,7 +58,8 @@ __device__ __forceinline__ void load_twr(cplx<T> (&w)[RegFFT<N>::P - 1][8], cons
 #pragma unroll
   for (int p = 1; p < F::P; ++p)
 #pragma unroll
-    for (int m = 0; m < 8; ++m) w[p - 1][m] = tw[F::texp(p, F::bfly(p, j, m), F::elem(p, m))];
+    for (int m = 0; m < 8; ++m)
+      w[p - 1][m] = F::elem(p, m) == 0 ? cplx<T>{1, 0} : tw[F::texp(p, F::bfly(p, j, m), F::elem(p, m))];
 }
 
 template <int R, bool INV, typename V> __device__ __forceinline__ void dft_groups(V (&v)[8]) {
@@ -87,7 +88,8 @@ __device__ __forceinline__ void fft_dit(cplx<T> (&v)[8], cplx<T>* buf0, cplx<T>*
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const V x = buf[slot(F::rpos(p, F::bfly(p, j, m), F::elem(p, m)))];
-      v[m] = INV ? cmulc(x, w[p - 1][m]) : cmul(x, w[p - 1][m]);
+      // element 0 of every butterfly has the twiddle exponent 0
+      v[m] = F::elem(p, m) == 0 ? x : (INV ? cmulc(x, w[p - 1][m]) : cmul(x, w[p - 1][m]));
     }
     if (p == 1) dft_pass<N, 1, INV>(v);
     if (p == 2) dft_pass<N, (F::P > 2 ? 2 : 1), INV>(v);
@@ -107,7 +109,7 @@ __device__ __forceinline__ void fft_dif(cplx<T> (&v)[8], cplx<T>* buf0, cplx<T>*
     V* buf = (parity++ & 1) ? buf1 : buf0;
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const V y = INV ? cmulc(v[m], w[p - 1][m]) : cmul(v[m], w[p - 1][m]);
+      const V y = F::elem(p, m) == 0 ? v[m] : (INV ? cmulc(v[m], w[p - 1][m]) : cmul(v[m], w[p - 1][m]));
       buf[slot(F::rpos(p, F::bfly(p, j, m), F::elem(p, m)))] = y;
     }
     __syncthreads();
@@ -393,25 +395,31 @@ __global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, l
 // read and one write of the work array.
 // ---------------------------------------------------------------------------
 constexpr int PLANE_NT = 512;       // 64 lines x 8 threads
-constexpr int PLANE_TPITCH = 65;    // transposition buffer pitch
+// Transposition slot of (i0, i1): row i0, column i1 XOR a swizzle of i0's low
+// bits.  Lanes of a wave cover 8 lines x 8 points (write: i0 = line; read:
+// i0 = point), and the swizzle spreads both patterns over distinct 8-byte slots
+// modulo 16 within each 16 lanes and modulo 32 within each 32 lanes.
+__device__ __forceinline__ int plane_tslot(int i0, int i1) {
+  const int f = ((i0 & 2) | (i0 & 4) | ((i0 & 1) << 3) | ((i0 & 2) << 3));
+  return i0 * 64 + (i1 ^ f);
+}
+// The two axes have the same length, so one twiddle set serves both.
 template <typename T, int PCG = 0>
 __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W, int n2, long nvox,
                                                          const uint16_t* __restrict__ gmapT, const T* __restrict__ Ctab,
-                                                         T scale, const cplx<T>* __restrict__ tw0,
-                                                         const cplx<T>* __restrict__ tw1,
+                                                         T scale, const cplx<T>* __restrict__ tw,
                                                          const int* __restrict__ active) {
   using V = cplx<T>;
   using F = RegFFT<64>;
-  constexpr int NB = 64 * (64 + 8);   // 64 lines at the skewed row pitch; holds the 64 x 65 transposition too
+  constexpr int NB = 64 * (64 + 8);   // 64 lines at the skewed row pitch; holds the 64 x 64 transposition too
   __shared__ V lds[2][NB];
   const int v = blockIdx.x / n2;
   if (active && !active[v]) return;
   const int i2 = blockIdx.x - v * n2;
   const int tid = threadIdx.x;
   const int line = tid >> 3, j = tid & 7;
-  V w0[1][8], w1[1][8];
-  load_twr<T, 64>(w0, tw0, j);
-  load_twr<T, 64>(w1, tw1, j);
+  V w[1][8];
+  load_twr<T, 64>(w, tw, j);
   V* Wv = W + (size_t)v * 6 * nvox + (size_t)i2 * 4096;
   const RowSlotR<64> slot{line * (64 + 8)};
   int parity = 0;
@@ -422,14 +430,14 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
     for (int m = 0; m < 8; ++m) x[c][m] = Wv[(size_t)c * nvox + line * 64 + j + 8 * m];  // (i0 = line, i1 = j + 8m)
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    fft_dit<T, 64, true>(x[c], lds[0], lds[1], parity, slot, j, w1);   // along i1
+    fft_dit<T, 64, true>(x[c], lds[0], lds[1], parity, slot, j, w);   // along i1
     V* buf = (parity++ & 1) ? lds[1] : lds[0];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) buf[line * PLANE_TPITCH + j + 8 * m] = x[c][m];
+    for (int m = 0; m < 8; ++m) buf[plane_tslot(line, j + 8 * m)] = x[c][m];
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 8; ++m) x[c][m] = buf[(j + 8 * m) * PLANE_TPITCH + line];   // (i0 = j + 8m, i1 = line)
-    fft_dit<T, 64, true>(x[c], lds[0], lds[1], parity, slot, j, w0);   // along i0
+    for (int m = 0; m < 8; ++m) x[c][m] = buf[plane_tslot(j + 8 * m, line)];   // (i0 = j + 8m, i1 = line)
+    fft_dit<T, 64, true>(x[c], lds[0], lds[1], parity, slot, j, w);   // along i0
   }
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
@@ -447,14 +455,14 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    fft_dit<T, 64, false>(x[c], lds[0], lds[1], parity, slot, j, w0);  // along i0
+    fft_dit<T, 64, false>(x[c], lds[0], lds[1], parity, slot, j, w);  // along i0
     V* buf = (parity++ & 1) ? lds[1] : lds[0];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) buf[(j + 8 * m) * PLANE_TPITCH + line] = x[c][m];
+    for (int m = 0; m < 8; ++m) buf[plane_tslot(j + 8 * m, line)] = x[c][m];
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 8; ++m) x[c][m] = buf[line * PLANE_TPITCH + j + 8 * m];   // (i0 = line, i1 = j + 8m)
-    fft_dit<T, 64, false>(x[c], lds[0], lds[1], parity, slot, j, w1);  // along i1
+    for (int m = 0; m < 8; ++m) x[c][m] = buf[plane_tslot(line, j + 8 * m)];   // (i0 = line, i1 = j + 8m)
+    fft_dit<T, 64, false>(x[c], lds[0], lds[1], parity, slot, j, w);  // along i1
 #pragma unroll
     for (int m = 0; m < 8; ++m) Wv[(size_t)c * nvox + line * 64 + j + 8 * m] = x[c][m];
   }
