@@ -65,10 +65,13 @@ bool timing_enabled() { return g_timing.load(std::memory_order_relaxed); }
 
 namespace {
 std::atomic<bool> g_graphs{true};
+thread_local bool t_graphs_off = false;
 }
 // graphs are replayed only while no kernel timing is requested (timing brackets
-// every launch with events, which a replayed graph cannot do)
-bool graphs_enabled() { return g_graphs.load(std::memory_order_relaxed) && !timing_enabled(); }
+// every launch with events, which a replayed graph cannot do), and not on host
+// threads that opted out (see graphs_off_this_thread)
+bool graphs_enabled() { return !t_graphs_off && g_graphs.load(std::memory_order_relaxed) && !timing_enabled(); }
+void graphs_off_this_thread(bool off) { t_graphs_off = off; }
 
 KTimer::KTimer(const char* n, hipStream_t st, long u) : name(n), s(st), units(u) {
   if (!timing_enabled()) return;

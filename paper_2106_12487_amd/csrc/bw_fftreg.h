@@ -72,8 +72,26 @@ template <int N, int p, bool INV, typename V> __device__ __forceinline__ void df
   dft_groups<R, INV>(v);
 }
 
+// Synchronization of one exchange: the workgroup, or only the wavefront when
+// every line of the tile lies inside one wavefront (N / 8 consecutive lanes
+// with lane = (N / 8) line + j).  A wavefront's LDS operations execute in issue
+// order; the wavefront-scope fences keep the compiler from moving accesses
+// across the exchange.  Consecutive exchanges alternate between two buffers, so
+// the writes of one exchange never overtake the reads of the previous one.
+// The plane pass uses the wavefront form; the row passes keep the workgroup
+// form, which measured faster there (the workgroup's stores stay together).
+template <bool WAVE> __device__ __forceinline__ void xsync() {
+  if (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Decimation in time: v holds layout A on entry, layout B on exit.
-template <typename T, int N, bool INV, class Slot>
+template <typename T, int N, bool INV, bool WAVE = false, class Slot>
 __device__ __forceinline__ void fft_dit(cplx<T> (&v)[8], cplx<T>* buf0, cplx<T>* buf1, int& parity, const Slot& slot,
                                         int j, const cplx<T> (&w)[RegFFT<N>::P - 1][8]) {
   using F = RegFFT<N>;
@@ -84,7 +102,7 @@ __device__ __forceinline__ void fft_dit(cplx<T> (&v)[8], cplx<T>* buf0, cplx<T>*
     V* buf = (parity++ & 1) ? buf1 : buf0;
 #pragma unroll
     for (int m = 0; m < 8; ++m) buf[slot(F::wpos(p - 1, F::bfly(p - 1, j, m), F::elem(p - 1, m)))] = v[m];
-    __syncthreads();
+    xsync<WAVE>();
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const V x = buf[slot(F::rpos(p, F::bfly(p, j, m), F::elem(p, m)))];
@@ -97,7 +115,7 @@ __device__ __forceinline__ void fft_dit(cplx<T> (&v)[8], cplx<T>* buf0, cplx<T>*
 }
 
 // Decimation in frequency: v holds layout B on entry, layout A on exit.
-template <typename T, int N, bool INV, class Slot>
+template <typename T, int N, bool INV, bool WAVE = false, class Slot>
 __device__ __forceinline__ void fft_dif(cplx<T> (&v)[8], cplx<T>* buf0, cplx<T>* buf1, int& parity, const Slot& slot,
                                         int j, const cplx<T> (&w)[RegFFT<N>::P - 1][8]) {
   using F = RegFFT<N>;
@@ -112,7 +130,7 @@ __device__ __forceinline__ void fft_dif(cplx<T> (&v)[8], cplx<T>* buf0, cplx<T>*
       const V y = F::elem(p, m) == 0 ? v[m] : (INV ? cmulc(v[m], w[p - 1][m]) : cmul(v[m], w[p - 1][m]));
       buf[slot(F::rpos(p, F::bfly(p, j, m), F::elem(p, m)))] = y;
     }
-    __syncthreads();
+    xsync<WAVE>();
 #pragma unroll
     for (int m = 0; m < 8; ++m) v[m] = buf[slot(F::wpos(p - 1, F::bfly(p - 1, j, m), F::elem(p - 1, m)))];
   }
@@ -130,11 +148,23 @@ template <int N> struct ColSlotR {
   __device__ __forceinline__ int operator()(int n) const { return n * RegFFT<N>::LINES + line; }
 };
 
+// Staging slot of (i2, line) in a row tile's N x LINES block of the
+// transposed work layout: the line index XOR a swizzle of i2, so that both the
+// FFT-side pattern (a wavefront holds 64 / (N/8) lines x N/8 points) and the
+// coalesced pattern (runs of LINES consecutive lines per i2) hit distinct LDS
+// slots for N = 64 (at most 2-way conflicts for 16, 32, 128).
+template <int N> __device__ __forceinline__ int tr_slot(int i2, int ln) {
+  constexpr int L = RegFFT<N>::LINES;
+  return i2 * L + (ln ^ ((((i2 & 7) << 1) | ((i2 & 1) << 4)) & (L - 1)));
+}
+
 // ---------------------------------------------------------------------------
 // K, first pass (same contract as k_strain_row; tpv = n0 n1 / LINES)
 // ---------------------------------------------------------------------------
 // TR: write the strain to the transposed work layout [vec][c][i2][i0 i1] (the
-// (i0, i1) planes contiguous, for the plane pass) instead of [vec][c][i0 i1][i2].
+// (i0, i1) planes contiguous, for the plane pass) instead of [vec][c][i0 i1][i2];
+// the tile is staged through LDS so that every store writes runs of LINES
+// consecutive (i0, i1) positions.
 template <typename T, int N, int MODE, bool TR = false>
 __global__ __launch_bounds__(NT) void k_strain_row_r(const cplx<T>* __restrict__ U, cplx<T>* __restrict__ Pp,
                                                      cplx<T>* __restrict__ W, const double* __restrict__ qtab,
@@ -144,6 +174,7 @@ __global__ __launch_bounds__(NT) void k_strain_row_r(const cplx<T>* __restrict__
   using V = cplx<T>;
   using F = RegFFT<N>;
   __shared__ V lds[2][F::BUF];
+  __shared__ V stage[TR ? N * F::LINES : 1];
   const int v = blockIdx.x / tpv;
   const int tile = blockIdx.x - v * tpv;
   if (active && !active[v]) return;
@@ -200,9 +231,18 @@ __global__ __launch_bounds__(NT) void k_strain_row_r(const cplx<T>* __restrict__
     }
     fft_dit<T, N, true>(e, lds[0], lds[1], parity, slot, j, w);
     if (TR) {
+      // the previous component's reads of `stage` finished before the
+      // workgroup barrier inside this component's transform
       const long n01 = nvox / N;
 #pragma unroll
-      for (int m = 0; m < 8; ++m) W[(((size_t)v * 6 + c) * N + F::posB(j, m)) * n01 + row] = e[m];
+      for (int m = 0; m < 8; ++m) stage[tr_slot<N>(F::posB(j, m), line)] = e[m];
+      __syncthreads();
+      cplx<T>* Wc = W + ((size_t)v * 6 + c) * nvox + (size_t)tile * F::LINES;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int el = s * NT + tid, i2 = el / F::LINES, ln = el % F::LINES;
+        Wc[(size_t)i2 * n01 + ln] = stage[tr_slot<N>(i2, ln)];
+      }
     } else {
 #pragma unroll
       for (int m = 0; m < 8; ++m) W[((size_t)v * 6 + c) * nvox + rbase + F::posB(j, m)] = e[m];
@@ -213,7 +253,8 @@ __global__ __launch_bounds__(NT) void k_strain_row_r(const cplx<T>* __restrict__
 // ---------------------------------------------------------------------------
 // K, last pass (same contract as k_row_div; partials per tile)
 // ---------------------------------------------------------------------------
-// TR: read the stress from the transposed work layout (see k_strain_row_r).
+// TR: read the stress from the transposed work layout (see k_strain_row_r),
+// with coalesced loads staged through LDS.
 template <typename T, int N, int MODE, bool TR = false>
 __global__ __launch_bounds__(NT) void k_row_div_r(const cplx<T>* __restrict__ W, cplx<T>* __restrict__ Y,
                                                   const double* __restrict__ qtab, int n0, int n1, long nvox,
@@ -223,6 +264,7 @@ __global__ __launch_bounds__(NT) void k_row_div_r(const cplx<T>* __restrict__ W,
   using V = cplx<T>;
   using F = RegFFT<N>;
   __shared__ V lds[2][F::BUF];
+  __shared__ V stage[TR ? N * F::LINES : 1];
   __shared__ double sh[NT / 64];
   const int v = blockIdx.x / tpv;
   const int tile = blockIdx.x - v * tpv;
@@ -245,9 +287,13 @@ __global__ __launch_bounds__(NT) void k_row_div_r(const cplx<T>* __restrict__ W,
 #pragma unroll
   for (int m = 0; m < 8; ++m) acc[0][m] = acc[1][m] = acc[2][m] = V{0, 0};
   const long n01 = nvox / N;
+  // TR: element s of this thread is (i2, line) = divmod(s NT + tid, LINES) of the tile
   auto widx = [&](int c, int m) -> size_t {
-    return TR ? (((size_t)v * 6 + c) * N + F::posA(j, m)) * n01 + row
-              : ((size_t)v * 6 + c) * nvox + rbase + F::posA(j, m);
+    if (TR) {
+      const int el = m * NT + tid;
+      return ((size_t)v * 6 + c) * nvox + (size_t)(el / F::LINES) * n01 + (size_t)tile * F::LINES + el % F::LINES;
+    }
+    return ((size_t)v * 6 + c) * nvox + rbase + F::posA(j, m);
   };
   V nxt[8];
 #pragma unroll
@@ -255,8 +301,21 @@ __global__ __launch_bounds__(NT) void k_row_div_r(const cplx<T>* __restrict__ W,
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     V e[8];
+    if (TR) {
+      // the previous component's reads of `stage` finished before the
+      // workgroup barrier inside its transform
 #pragma unroll
-    for (int m = 0; m < 8; ++m) e[m] = nxt[m];
+      for (int m = 0; m < 8; ++m) {
+        const int el = m * NT + tid;
+        stage[tr_slot<N>(el / F::LINES, el % F::LINES)] = nxt[m];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < 8; ++m) e[m] = stage[tr_slot<N>(F::posA(j, m), line)];
+    } else {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) e[m] = nxt[m];
+    }
     if (c < 5) {
 #pragma unroll
       for (int m = 0; m < 8; ++m) nxt[m] = W[widx(c + 1, m)];
@@ -411,8 +470,10 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
                                                          const int* __restrict__ active) {
   using V = cplx<T>;
   using F = RegFFT<64>;
-  constexpr int NB = 64 * (64 + 8);   // 64 lines at the skewed row pitch; holds the 64 x 64 transposition too
+  constexpr int NB = 64 * (64 + 8);   // 64 lines at the skewed row pitch (FFT exchanges, wavefront-local)
   __shared__ V lds[2][NB];
+  __shared__ V tr[2][64 * 64];        // transpositions (workgroup-wide), alternating
+  int tsel = 0;
   const int v = blockIdx.x / n2;
   if (active && !active[v]) return;
   const int i2 = blockIdx.x - v * n2;
@@ -430,14 +491,14 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
     for (int m = 0; m < 8; ++m) x[c][m] = Wv[(size_t)c * nvox + line * 64 + j + 8 * m];  // (i0 = line, i1 = j + 8m)
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    fft_dit<T, 64, true>(x[c], lds[0], lds[1], parity, slot, j, w);   // along i1
-    V* buf = (parity++ & 1) ? lds[1] : lds[0];
+    fft_dit<T, 64, true, true>(x[c], lds[0], lds[1], parity, slot, j, w);   // along i1
+    V* buf = tr[tsel++ & 1];
 #pragma unroll
     for (int m = 0; m < 8; ++m) buf[plane_tslot(line, j + 8 * m)] = x[c][m];
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < 8; ++m) x[c][m] = buf[plane_tslot(j + 8 * m, line)];   // (i0 = j + 8m, i1 = line)
-    fft_dit<T, 64, true>(x[c], lds[0], lds[1], parity, slot, j, w);   // along i0
+    fft_dit<T, 64, true, true>(x[c], lds[0], lds[1], parity, slot, j, w);   // along i0
   }
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
@@ -455,14 +516,14 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    fft_dit<T, 64, false>(x[c], lds[0], lds[1], parity, slot, j, w);  // along i0
-    V* buf = (parity++ & 1) ? lds[1] : lds[0];
+    fft_dit<T, 64, false, true>(x[c], lds[0], lds[1], parity, slot, j, w);  // along i0
+    V* buf = tr[tsel++ & 1];
 #pragma unroll
     for (int m = 0; m < 8; ++m) buf[plane_tslot(j + 8 * m, line)] = x[c][m];
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < 8; ++m) x[c][m] = buf[plane_tslot(line, j + 8 * m)];   // (i0 = line, i1 = j + 8m)
-    fft_dit<T, 64, false>(x[c], lds[0], lds[1], parity, slot, j, w);  // along i1
+    fft_dit<T, 64, false, true>(x[c], lds[0], lds[1], parity, slot, j, w);  // along i1
 #pragma unroll
     for (int m = 0; m < 8; ++m) Wv[(size_t)c * nvox + line * 64 + j + 8 * m] = x[c][m];
   }

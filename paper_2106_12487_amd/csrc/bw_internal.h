@@ -44,6 +44,10 @@ struct Error {
 // ---------------------------------------------------------------------------
 bool timing_enabled();
 bool graphs_enabled();
+// Stream capture on one host thread fails when another thread of the same
+// process allocates, frees or synchronizes meanwhile; drivers that run several
+// cells from concurrent host threads launch eagerly on those threads.
+void graphs_off_this_thread(bool off);
 struct KTimer {
   const char* name;
   hipStream_t s;
