@@ -556,15 +556,37 @@ __global__ __launch_bounds__(NT) void k_axis0_op(cplx<T>* __restrict__ X, long n
 // pointwise kernels over [nvec][3][nvox]; each block owns a chunk of voxels of
 // one vector (grid = nvec * bpv).
 // ---------------------------------------------------------------------------
+// Flat voxel index -> (i0, i1, i2) in 32-bit arithmetic (a cell holds at most
+// 2^30 voxels), with shifts and masks when n1 / n2 are powers of two (s1, s2 >= 0).
 struct VoxIdx {
   int n0, n1, n2;
+  int s1, s2;
   __device__ __forceinline__ void split(long vox, int& i0, int& i1, int& i2) const {
-    const long r = vox / n2;
-    i2 = (int)(vox - r * n2);
-    i0 = (int)(r / n1);
-    i1 = (int)(r - (long)i0 * n1);
+    const unsigned v = (unsigned)vox;
+    unsigned r;
+    if (s2 >= 0) {
+      r = v >> s2;
+      i2 = (int)(v & (unsigned)(n2 - 1));
+    } else {
+      r = v / (unsigned)n2;
+      i2 = (int)(v - r * (unsigned)n2);
+    }
+    if (s1 >= 0) {
+      i0 = (int)(r >> s1);
+      i1 = (int)(r & (unsigned)(n1 - 1));
+    } else {
+      i0 = (int)(r / (unsigned)n1);
+      i1 = (int)(r - (unsigned)i0 * (unsigned)n1);
+    }
   }
 };
+inline int log2_exact(int n) {
+  if (n <= 0 || (n & (n - 1))) return -1;
+  int s = 0;
+  while ((1 << s) < n) ++s;
+  return s;
+}
+inline VoxIdx voxidx(const Geom& g) { return VoxIdx{g.n0, g.n1, g.n2, log2_exact(g.n1), log2_exact(g.n2)}; }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_apply_P(const cplx<T>* __restrict__ U, cplx<T>* __restrict__ Y,
@@ -1000,7 +1022,7 @@ void launch_apply_P(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cpl
                     hipStream_t s) {
   const Geom& g = r->g;
   const int bpv = pw_blocks(g.nvox);
-  hipLaunchKernelGGL((k_apply_P<T>), dim3(nvec * bpv), dim3(NT), 0, s, u, y, d_qtab, VoxIdx{g.n0, g.n1, g.n2},
+  hipLaunchKernelGGL((k_apply_P<T>), dim3(nvec * bpv), dim3(NT), 0, s, u, y, d_qtab, voxidx(g),
                      g.nvox, bpv, c0v<T>(r), (T)scale);
 }
 
@@ -1016,7 +1038,7 @@ void launch_pcg_update(const bw_rve* r, const double* d_qtab, cplx<T>* x, cplx<T
   const Geom& g = r->g;
   const int bpv = pw_blocks(g.nvox);
   BW_LAUNCH("k_pcg_update", 0, (k_pcg_update<T>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
-                     VoxIdx{g.n0, g.n1, g.n2}, g.nvox, bpv, c0v<T>(r), pd);
+                     voxidx(g), g.nvox, bpv, c0v<T>(r), pd);
   hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_BETA, bpv, pd, (const int*)nullptr,
                      (double*)nullptr, (double*)nullptr);
 }
@@ -1055,7 +1077,7 @@ void launch_pcg_restart(const bw_rve* r, const double* d_qtab, const cplx<T>* rv
                         const int* d_mask, hipStream_t s) {
   const Geom& g = r->g;
   const int bpv = pw_blocks(g.nvox);
-  hipLaunchKernelGGL((k_pcg_restart<T>), dim3(nvec * bpv), dim3(NT), 0, s, rv, d_qtab, VoxIdx{g.n0, g.n1, g.n2},
+  hipLaunchKernelGGL((k_pcg_restart<T>), dim3(nvec * bpv), dim3(NT), 0, s, rv, d_qtab, voxidx(g),
                      g.nvox, bpv, c0v<T>(r), pd, d_mask);
   hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_RESTART, bpv, pd, d_mask, (double*)nullptr,
                      (double*)nullptr);
