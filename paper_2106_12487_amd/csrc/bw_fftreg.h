@@ -445,6 +445,41 @@ __global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, l
   }
 }
 
+// Two length-64 transforms at once with wavefront-local exchanges (one buffer
+// each): the butterflies of one overlap the LDS latency of the other.  The
+// fence before the writes keeps them behind the reads of the previous exchange
+// in the same buffers.
+template <typename T, bool INV, class Slot>
+__device__ __forceinline__ void fft64_dit_pair(cplx<T> (&a)[8], cplx<T> (&b)[8], cplx<T>* bufa, cplx<T>* bufb,
+                                               const Slot& slot, int j, const cplx<T> (&w)[1][8]) {
+  using F = RegFFT<64>;
+  using V = cplx<T>;
+  dft_pass<64, 0, INV>(a);
+  dft_pass<64, 0, INV>(b);
+  xsync<true>();
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int o = slot(F::wpos(0, F::bfly(0, j, m), F::elem(0, m)));
+    bufa[o] = a[m];
+    bufb[o] = b[m];
+  }
+  xsync<true>();
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int o = slot(F::rpos(1, F::bfly(1, j, m), F::elem(1, m)));
+    const V xa = bufa[o], xb = bufb[o];
+    if (F::elem(1, m) == 0) {
+      a[m] = xa;
+      b[m] = xb;
+    } else {
+      a[m] = INV ? cmulc(xa, w[0][m]) : cmul(xa, w[0][m]);
+      b[m] = INV ? cmulc(xb, w[0][m]) : cmul(xb, w[0][m]);
+    }
+  }
+  dft_pass<64, 1, INV>(a);
+  dft_pass<64, 1, INV>(b);
+}
+
 // ---------------------------------------------------------------------------
 // Plane pass for n0 = n1 = 64 on the transposed work layout: one workgroup
 // per (vector, i2) takes the 64 x 64 (i0, i1) plane of all six strain
@@ -472,8 +507,7 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
   using F = RegFFT<64>;
   constexpr int NB = 64 * (64 + 8);   // 64 lines at the skewed row pitch (FFT exchanges, wavefront-local)
   __shared__ V lds[2][NB];
-  __shared__ V tr[2][64 * 64];        // transpositions (workgroup-wide), alternating
-  int tsel = 0;
+  __shared__ V tr[2][64 * 64];        // transpositions of a pair of components (workgroup-wide)
   const int v = blockIdx.x / n2;
   if (active && !active[v]) return;
   const int i2 = blockIdx.x - v * n2;
@@ -483,22 +517,27 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
   load_twr<T, 64>(w, tw, j);
   V* Wv = W + (size_t)v * 6 * nvox + (size_t)i2 * 4096;
   const RowSlotR<64> slot{line * (64 + 8)};
-  int parity = 0;
   V x[6][8];
 #pragma unroll
   for (int c = 0; c < 6; ++c)
 #pragma unroll
     for (int m = 0; m < 8; ++m) x[c][m] = Wv[(size_t)c * nvox + line * 64 + j + 8 * m];  // (i0 = line, i1 = j + 8m)
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    fft_dit<T, 64, true, true>(x[c], lds[0], lds[1], parity, slot, j, w);   // along i1
-    V* buf = tr[tsel++ & 1];
+  for (int c = 0; c < 6; c += 2) {
+    fft64_dit_pair<T, true>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i1
+    if (c > 0) __syncthreads();   // every wavefront has read the previous pair's transposition
 #pragma unroll
-    for (int m = 0; m < 8; ++m) buf[plane_tslot(line, j + 8 * m)] = x[c][m];
+    for (int m = 0; m < 8; ++m) {
+      tr[0][plane_tslot(line, j + 8 * m)] = x[c][m];
+      tr[1][plane_tslot(line, j + 8 * m)] = x[c + 1][m];
+    }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 8; ++m) x[c][m] = buf[plane_tslot(j + 8 * m, line)];   // (i0 = j + 8m, i1 = line)
-    fft_dit<T, 64, true, true>(x[c], lds[0], lds[1], parity, slot, j, w);   // along i0
+    for (int m = 0; m < 8; ++m) {                    // (i0 = j + 8m, i1 = line)
+      x[c][m] = tr[0][plane_tslot(j + 8 * m, line)];
+      x[c + 1][m] = tr[1][plane_tslot(j + 8 * m, line)];
+    }
+    fft64_dit_pair<T, true>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i0
   }
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
@@ -515,17 +554,26 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
     asm volatile("" ::: "memory");
   }
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    fft_dit<T, 64, false, true>(x[c], lds[0], lds[1], parity, slot, j, w);  // along i0
-    V* buf = tr[tsel++ & 1];
+  for (int c = 0; c < 6; c += 2) {
+    fft64_dit_pair<T, false>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i0
+    __syncthreads();              // every wavefront has read the previous transposition
 #pragma unroll
-    for (int m = 0; m < 8; ++m) buf[plane_tslot(j + 8 * m, line)] = x[c][m];
+    for (int m = 0; m < 8; ++m) {
+      tr[0][plane_tslot(j + 8 * m, line)] = x[c][m];
+      tr[1][plane_tslot(j + 8 * m, line)] = x[c + 1][m];
+    }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 8; ++m) x[c][m] = buf[plane_tslot(line, j + 8 * m)];   // (i0 = line, i1 = j + 8m)
-    fft_dit<T, 64, false, true>(x[c], lds[0], lds[1], parity, slot, j, w);  // along i1
+    for (int m = 0; m < 8; ++m) {                    // (i0 = line, i1 = j + 8m)
+      x[c][m] = tr[0][plane_tslot(line, j + 8 * m)];
+      x[c + 1][m] = tr[1][plane_tslot(line, j + 8 * m)];
+    }
+    fft64_dit_pair<T, false>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i1
 #pragma unroll
-    for (int m = 0; m < 8; ++m) Wv[(size_t)c * nvox + line * 64 + j + 8 * m] = x[c][m];
+    for (int m = 0; m < 8; ++m) {
+      Wv[(size_t)c * nvox + line * 64 + j + 8 * m] = x[c][m];
+      Wv[(size_t)(c + 1) * nvox + line * 64 + j + 8 * m] = x[c + 1][m];
+    }
   }
 }
 
