@@ -228,6 +228,27 @@ def copy_calibration(bw):
     print(f"[bench] copy calibration: 3 x {n} bytes", file=sys.stderr, flush=True)
 
 
+def copy_bandwidth(bw, reps=20):
+    """Measured device-copy bandwidth (GB/s, read + write) of the library's plain
+    streaming copy on 1 GiB: the practical ceiling of a streaming kernel."""
+    import torch
+    n = 1 << 30
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        bw.bw_diag_copy(src, dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bw.bw_diag_copy(src, dst)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_baseline(rve_in, ks, budget_s):
     """Oracle PCG on the workload (one RHS at the first k != 0) for about budget_s
     seconds, scaled by the oracle's own PCG-iteration count per k-point from its
@@ -296,6 +317,9 @@ def main():
         "solver_stats": mixed["stats"][-1],
     }
     out["roofline"] = roofline(mixed["timing"], nvox, 8)
+    cbw = copy_bandwidth(bw)
+    out["roofline"]["copy_GBps"] = round(cbw, 1)
+    out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / cbw, 4)
     for kname, v in sorted((mixed["breakdown"] or {}).items(), key=lambda kv: -kv[1]["ms"]):
         print(f"[bench] kernel {kname:24s} launches {v['launches']:6d} total {v['ms']:9.1f} ms units {v['units']}",
               file=sys.stderr, flush=True)

@@ -308,10 +308,12 @@ int bw_pcg_solve_learned(bw_rve* rve, bw_unet* net, const double k_host[3], cons
                          double rtol, int32_t maxit, int32_t* iters_host, double* relres_host,
                          int32_t* fallbacks_host, void* stream);
 
-/* Diagnostics: a plain streaming copy of `bytes` (a multiple of 16; 16-byte
- * aligned device buffers, not overlapping) on `stream`, the reference kernel
- * for calibrating memory-traffic counters (its algorithmic traffic is exactly
- * `bytes` read and `bytes` written). */
+/* Diagnostics: a plain streaming copy of `bytes` (a multiple of 16, below
+ * 2^39; 16-byte aligned device buffers, not overlapping) on `stream`, the
+ * reference kernel for calibrating memory-traffic counters (its algorithmic
+ * traffic is exactly `bytes` read and `bytes` written) and for the measured
+ * device-copy bandwidth that kernel roofline fractions are also quoted
+ * against. */
 int bw_diag_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
 /* Thread-local message describing the last non-zero status. */

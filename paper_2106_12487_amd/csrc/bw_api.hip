@@ -388,10 +388,13 @@ extern "C" int bw_timing_filter(const char* kernel_name) {
 }
 
 namespace bw {
-// plain streaming copy (16-byte words), the calibration kernel for memory counters
+// plain streaming copy (16-byte words, one per thread over a full grid: the
+// resident workgroups then stream neighbouring memory, measured faster than a
+// grid-stride loop), the calibration kernel for memory counters and the
+// device-copy bandwidth reference
 __global__ void k_diag_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, long n) {
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
-    dst[e] = src[e];
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = src[e];
 }
 }  // namespace bw
 
@@ -402,8 +405,8 @@ extern "C" int bw_diag_copy(const void* src, void* dst, int64_t bytes, void* str
   BW_REQUIRE(((uintptr_t)src | (uintptr_t)dst) % 16 == 0, BW_EINVAL, "buffers must be 16-byte aligned");
   const long n = bytes / 16;
   if (n == 0) return BW_OK;
-  long blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  const long blocks = (n + 255) / 256;
+  BW_REQUIRE(blocks < (1L << 31), BW_EINVAL, "copy too large");
   BW_LAUNCH("k_diag_copy", 0, k_diag_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
             (const uint4*)src, (uint4*)dst, n);
   BW_HIP(hipGetLastError());
