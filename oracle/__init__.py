@@ -17,6 +17,8 @@ operators  stiffness / mass / inverse-mass operators (Sec. 3.2 eqs. hatA,
 solvers    preconditioned CG (Algorithm "InvA"), subspace iteration (Algorithm
            "subspace"), shift-invert implicitly restarted Lanczos (Sec. 3.3),
            dense generalized eigendecomposition and the Gamma-point deflation
+postproc   group velocity of the branches (Sec. 5.1 eq. c_group) and their
+           long-wave speeds, with the Voigt/Reuss bracket
 
 Every function is FP64 and works in SI units.  Parity status of each function
 is listed in its docstring; none is "parity unpinned" unless it says so.

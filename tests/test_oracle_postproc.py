@@ -1,0 +1,109 @@
+"""Pins of the oracle's group velocity and long-wave speeds (oracle/postproc.py)."""
+import numpy as np
+import pytest
+
+from oracle import postproc, solvers
+from oracle.operators import Operators
+from paper_2106_12487_amd import inputs
+
+L = 1e-3
+
+
+def _dense(rve, k, nm):
+    lam, U = solvers.dense_modes(Operators(rve, k), nm)
+    return np.sqrt(np.maximum(lam, 0.0)), U
+
+
+def _iso_speeds(mat):
+    C = mat["C"]
+    return np.sqrt(C[3, 3] / mat["rho"]), np.sqrt(C[0, 0] / mat["rho"])
+
+
+def test_slopes_homogeneous_isotropic_and_folded_branch():
+    """omega = c |k + G| for a homogeneous isotropic medium: along x at k = 0.3 pi/L the
+    slopes are c_T, c_T, c_L on the G = 0 branches and -c_T on the transverse pair
+    folded from G = -2 pi/L x; along y all five are 0."""
+    al = inputs.AL
+    cT, cL = _iso_speeds(al)
+    rve = inputs.homogeneous((4, 4, 4), (L, L, L), al["C"], al["rho"])
+    k = np.array([0.3 * np.pi / L, 0, 0])
+    w, U = _dense(rve, k, 5)
+    np.testing.assert_allclose(w, [0.3 * np.pi / L * cT] * 2 + [0.3 * np.pi / L * cL] + [1.7 * np.pi / L * cT] * 2,
+                               rtol=1e-12)
+    sx = postproc.branch_slopes(rve, k, [1, 0, 0], U, w)
+    np.testing.assert_allclose(sx, [cT, cT, cL, -cT, -cT], rtol=1e-10)
+    sy = postproc.branch_slopes(rve, k, [0, 1, 0], U, w)
+    assert np.abs(sy).max() <= 1e-10 * cL
+
+
+def test_slopes_match_central_differences_of_dense_eigenvalues():
+    """Sec. 5.1 eq. c_group on a polycrystal at a generic k: slopes against central
+    differences of the exact (dense) eigenvalues at k +- delta d."""
+    rve = inputs.polycrystal((4, 4, 4), (L, L, L), 3, 94, 1)
+    k = np.array([0.37, 0.21, 0.13]) * np.pi / L
+    d = np.array([1.0, 2.0, -0.5]) / np.linalg.norm([1.0, 2.0, -0.5])
+    w, U = _dense(rve, k, 8)
+    assert np.min(np.diff(w) / w[1:]) > 1e-3                       # simple eigenvalues
+    s = postproc.branch_slopes(rve, k, d, U, w)
+    delta = 1e-5 * np.pi / L
+    wp, _ = _dense(rve, k + delta * d, 8)
+    wm, _ = _dense(rve, k - delta * d, 8)
+    fd = (wp - wm) / (2 * delta)
+    scale = np.max(np.abs(fd))
+    assert np.abs(s - fd).max() <= 1e-6 * scale
+    assert np.abs(fd).min() > 1e-3 * scale                          # a discriminating direction
+
+
+def test_slopes_of_rigid_modes_at_gamma_are_zero():
+    rve = inputs.polycrystal((4, 4, 4), (L, L, L), 3, 94, 1)
+    w = solvers.lowest_modes(rve, [np.zeros(3)], 6, method="dense")[0]
+    _, U = _dense(rve, np.zeros(3), 6)
+    s = postproc.branch_slopes(rve, np.zeros(3), [1, 0, 0], U, w)
+    assert np.all(s[:3] == 0.0)
+
+
+@pytest.mark.parametrize("d", [[1, 0, 0], [1, 1, 0]])
+def test_long_wave_speeds_cubic_crystal_closed_form(d):
+    """Homogeneous cubic crystal: Christoffel speeds, [100]: sqrt(C44/rho) (x2), sqrt(C11/rho);
+    [110]: sqrt(C44/rho), sqrt((C11 - C12)/(2 rho)), sqrt((C11 + C12 + 2 C44)/(2 rho))."""
+    ni = inputs.NI
+    C, rho = ni["C"], ni["rho"]
+    rve = inputs.homogeneous((4, 4, 4), (L, L, L), C, rho)
+    c = postproc.long_wave_speeds(rve, d, method="dense")
+    c11, c12, c44 = C[0, 0], C[0, 1], C[3, 3]
+    if d == [1, 0, 0]:
+        ref = np.sqrt([c44 / rho, c44 / rho, c11 / rho])
+    else:
+        ref = np.sqrt(np.sort([c44 / rho, (c11 - c12) / (2 * rho), (c11 + c12 + 2 * c44) / (2 * rho)]))
+    np.testing.assert_allclose(c, ref, rtol=1e-9)
+
+
+def test_long_wave_speeds_laminate_are_reuss_averages():
+    """Epoxy/carbon bilayer (Table 1), waves along the layering normal: the quasi-static
+    stress is uniform along x, so rho_bar c^2 is the harmonic mean of the P-wave modulus
+    (longitudinal) and of the shear modulus (transverse)."""
+    ep, ca = inputs.EPOXY, inputs.CARBON
+    rve = inputs.bilayer(16, L, ep, ca)
+    c = postproc.long_wave_speeds(rve, [1, 0, 0], method="dense")
+    rho = 0.5 * (ep["rho"] + ca["rho"])
+    pw = lambda m: m["C"][0, 0]
+    mu = lambda m: m["C"][3, 3]
+    cL = np.sqrt(1.0 / (0.5 / pw(ep) + 0.5 / pw(ca)) / rho)
+    cT = np.sqrt(1.0 / (0.5 / mu(ep) + 0.5 / mu(ca)) / rho)
+    np.testing.assert_allclose(c, [cT, cT, cL], rtol=1e-6)    # without the extrapolation: 5e-5
+    cV = np.sqrt(0.5 * (mu(ep) + mu(ca)) / rho)                      # the Voigt value is far off
+    assert cV > 2 * cT
+
+
+@pytest.mark.parametrize("d", [[1, 0, 0], [1, 1, 0], [1, 1, 1], [0.3, -0.5, 0.8]])
+def test_long_wave_speeds_polycrystal_within_voigt_reuss(d):
+    rve = inputs.polycrystal((6, 6, 6), (L, L, L), 8, 94, 2)
+    c = postproc.long_wave_speeds(rve, d, method="dense")
+    lo, hi = postproc.voigt_reuss_bracket(rve, d)
+    rho = float(np.mean(rve.rho[rve.grain_map]))
+    e = rho * c ** 2
+    assert np.all(e > lo * (1 + 1e-6)) and np.all(e < hi * (1 - 1e-6)), (lo, e, hi)
+
+
+def test_clusters_groups_equal_frequencies():
+    assert postproc.clusters(np.array([0.0, 0.0, 1.0, 1.0 + 1e-9, 2.0]), 1e-6) == [[0, 1], [2, 3], [4]]
