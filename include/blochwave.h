@@ -183,7 +183,10 @@ int bw_pcg_solve(bw_rve* rve, const double k_host[3], const void* b, void* x, in
  *   stats_host   optional solver statistics
  * At k = 0 (mod reciprocal lattice) the three rigid translations are returned
  * as omega = 0 with constant M-normalized modes and the rest is solved on their
- * M-orthogonal complement.  Synchronizes `stream`. */
+ * M-orthogonal complement.  BW_LANCZOS advances one Krylov vector per wave
+ * vector, so an exactly degenerate eigenvalue (homogeneous cells, symmetric
+ * cells at symmetric k) is found once; BW_SUBSPACE (a block method) resolves
+ * such multiplicities.  Synchronizes `stream`. */
 int bw_lowest_modes(bw_rve* rve, const double* k_list_host, int32_t nk, int32_t nmodes,
                     const bw_eig_opts* opts, double* omega_host, double* err_host,
                     void* modes, bw_stats* stats_host, void* stream);
@@ -307,6 +310,38 @@ int bw_unet_train_step(bw_unet* net, bw_rve* rve, const double* k_host, const vo
 int bw_pcg_solve_learned(bw_rve* rve, bw_unet* net, const double k_host[3], const void* b, void* x, int32_t nrhs,
                          double rtol, int32_t maxit, int32_t* iters_host, double* relres_host,
                          int32_t* fallbacks_host, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Dispersion post-processing (Sec. 5.1)
+ * --------------------------------------------------------------------------- */
+
+/* Slopes d omega / ds of the branches along the direction dir (any nonzero
+ * vector; normalized here) at the wave vector k_host (rad/m): the group
+ * velocity of Sec. 5.1 eq. c_group projected on dir.  modes: device, the
+ * nmodes (1 .. 32) eigenvectors at k_host as written by bw_lowest_modes for this
+ * cell (complex128 for BW_FP64 cells, complex64 for BW_MIXED ones), omega_host
+ * their frequencies (rad/s, ascending, >= 0).  Computed in FP64 from
+ * D = U^H dK/ds U (exact from two K applies, since K is quadratic in k) and
+ * U^H M U: a mode whose omega is separated from its neighbours by more than
+ * cluster_tol (relative) gets D_pp / (2 omega U_p^H M U_p); within a cluster of
+ * equal omega the slopes are the eigenvalues of (D, U^H M U) on the cluster over
+ * 2 omega, ascending (they do not depend on the basis the modes came in).
+ * Modes with omega = 0 (rigid translations at Gamma) get 0.  slopes_host:
+ * float64[nmodes] (m/s).  Synchronizes `stream`.  BW_EINVAL on bad arguments. */
+int bw_group_velocity(bw_rve* rve, const double k_host[3], const double dir[3], int32_t nmodes,
+                      const void* modes, const double* omega_host, double cluster_tol,
+                      double* slopes_host, void* stream);
+
+/* Long-wave speeds of the three acoustic branches along dir (m/s, ascending):
+ * omega / |k| from bw_lowest_modes (subspace iteration, bound-based stopping at
+ * tol_omega; 0 -> 1e-10 for BW_FP64, 1e-8 for BW_MIXED) at k = h dir and
+ * 2h dir with h = h_frac pi / max(L) (h_frac in (0, 0.25]), extrapolated to
+ * k -> 0 as (4 c(h) - c(2h)) / 3 (omega^2 is even and analytic in k).  The
+ * limit is the speed of the equivalent homogeneous medium (Sec. 5.1).  Returns
+ * the status of the eigen-solve (BW_ENOTCONV with c_host filled when a bound
+ * missed tol_omega).  Synchronizes `stream`. */
+int bw_long_wave_speeds(bw_rve* rve, const double dir[3], double h_frac, double tol_omega, double* c_host,
+                        void* stream);
 
 /* Diagnostics: a plain streaming copy of `bytes` (a multiple of 16, below
  * 2^39; 16-byte aligned device buffers, not overlapping) on `stream`, the

@@ -85,6 +85,8 @@ _SIGS = {
     "bw_unet_apply": (_I, [_P, _P, _DP, _P, _P, _I, _P]),
     "bw_unet_train_step": (_I, [_P, _P, _DP, _P, _P, _I, _D, _DP, _P]),
     "bw_pcg_solve_learned": (_I, [_P, _P, _DP, _P, _P, _I, _D, _I, _IP, _DP, _IP, _P]),
+    "bw_group_velocity": (_I, [_P, _DP, _DP, _I, _P, _DP, _D, _DP, _P]),
+    "bw_long_wave_speeds": (_I, [_P, _DP, _D, _D, _DP, _P]),
 }
 
 
@@ -295,6 +297,31 @@ def bw_lowest_modes_batched(rves, k_lists, nmodes: int, method: int = BW_SUBSPAC
     code = _check(lib().bw_lowest_modes_batched(h, n, kp, nk, int(nmodes), ctypes.byref(opts), op, ep, mp,
                                                 ctypes.byref(st), _stream(stream)))
     return oms, ers, code, st.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# dispersion post-processing
+# ---------------------------------------------------------------------------
+def bw_group_velocity(rve: Rve, k, direction, modes, omega, cluster_tol: float = 1e-6, stream=None) -> np.ndarray:
+    """d omega / ds along `direction` for the modes at k (device tensor [nmodes][3][n0][n1][n2]
+    as bw_lowest_modes writes it) with frequencies omega (rad/s, ascending); m/s."""
+    nm = int(modes.shape[0])
+    k_arr, k_p = _darr(np.asarray(k, dtype=np.float64).reshape(3))
+    d_arr, d_p = _darr(np.asarray(direction, dtype=np.float64).reshape(3))
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(nm))
+    out = np.zeros(nm)
+    _check(lib().bw_group_velocity(rve.handle, k_p, d_p, nm, _dptr(modes), om.ctypes.data_as(_DP),
+                                   float(cluster_tol), out.ctypes.data_as(_DP), _stream(stream)))
+    return out
+
+
+def bw_long_wave_speeds(rve: Rve, direction, h_frac: float = 0.02, tol_omega: float = 0.0, stream=None):
+    """(speeds of the three acoustic branches along `direction` for k -> 0 (m/s, ascending), status)."""
+    d_arr, d_p = _darr(np.asarray(direction, dtype=np.float64).reshape(3))
+    out = np.zeros(3)
+    code = _check(lib().bw_long_wave_speeds(rve.handle, d_p, float(h_frac), float(tol_omega),
+                                            out.ctypes.data_as(_DP), _stream(stream)))
+    return out, code
 
 
 # ---------------------------------------------------------------------------

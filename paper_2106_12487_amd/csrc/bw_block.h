@@ -61,6 +61,10 @@ template <typename T>
 void launch_set_entries(cplx<T>* U, long vstride, long nvox, int nent, const long* vec, const long* vox,
                         const double* val, hipStream_t s);
 
+// X_p += amp * (u1 + i u2), u uniform in [-1, 1) from a counter hash of (seed, p, e)
+template <typename T>
+void launch_add_hash(cplx<T>* X, long n, long vstride, int nv, unsigned long long seed, double amp, hipStream_t s);
+
 // small generalized Hermitian eigenproblem Kq z = lam Mq z (q <= GEIG_QMAX):
 // lam ascending, Q with Q^H Mq Q = I.  info[0] != 0 if Mq is not positive definite.
 void launch_small_geig(const double2* Kq, const double2* Mq, int q, double* lam, double2* Q, int* info,

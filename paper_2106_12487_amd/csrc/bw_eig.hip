@@ -625,6 +625,11 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       BW_HIP(hipStreamSynchronize(s));
     }
   }
+  // plus a small deterministic pseudo-random part (norm 1e-3 of the plane wave's),
+  // so that the Krylov space is not confined to the reference plane waves: for a
+  // homogeneous cell they are exact eigenvectors and the iteration would break
+  // down after four steps
+  launch_add_hash<T>(B, n3, n3, nk, 0x2106124870ULL, 1e-3 / std::sqrt((double)n3), s);
   apply_M_blk<T>(r, B, MF, nk, false, cnt, s);
   deflate_batch(B, MF, act);
   launch_dots<T>(B, MF, nk, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);

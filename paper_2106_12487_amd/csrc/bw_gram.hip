@@ -684,6 +684,36 @@ void launch_set_entries(cplx<T>* U, long vstride, long nvox, int nent, const lon
   hipLaunchKernelGGL((k_set_entries<T>), dim3(1), dim3(256), 0, s, U, vstride, nvox, nent, vec, vox, val);
 }
 
+// X_p[e] += amp * (u1 + i u2) with u1, u2 uniform in [-1, 1) from a 64-bit
+// counter hash (splitmix64 finalizer) of (seed, p, e): a deterministic
+// pseudo-random perturbation, identical for every launch configuration.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+template <typename T>
+__global__ void k_add_hash(cplx<T>* X, long n, long vstride, int nv, unsigned long long seed, double amp) {
+  const long total = (long)nv * n;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long p = e / n, i = e - p * n;
+    const unsigned long long h = mix64(seed + 0x9e3779b97f4a7c15ULL * (unsigned long long)(p * n + i + 1));
+    const double u1 = (double)(h >> 40) * (2.0 / 16777216.0) - 1.0;
+    const double u2 = (double)((h >> 16) & 0xffffffULL) * (2.0 / 16777216.0) - 1.0;
+    cplx<T>& x = X[p * vstride + i];
+    x.x = (T)((double)x.x + amp * u1);
+    x.y = (T)((double)x.y + amp * u2);
+  }
+}
+template <typename T>
+void launch_add_hash(cplx<T>* X, long n, long vstride, int nv, unsigned long long seed, double amp, hipStream_t s) {
+  const long total = (long)nv * n;
+  if (total == 0) return;
+  long blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL((k_add_hash<T>), dim3((unsigned)blocks), dim3(256), 0, s, X, n, vstride, nv, seed, amp);
+}
+
 #define BW_INST_BLOCK(T)                                                                                          \
   template void launch_gram<T>(const cplx<T>*, int, const cplx<T>*, int, long, long, double2*, DevBuf&,            \
                                unsigned*, hipStream_t);                                                                      \
@@ -702,7 +732,8 @@ void launch_set_entries(cplx<T>* U, long vstride, long nvox, int nent, const lon
   template void launch_scale_copy<T>(const cplx<T>*, long, cplx<T>*, long, const double*, int, long, const int*,  \
                                      hipStream_t);                                                                \
   template void launch_set_entries<T>(cplx<T>*, long, long, int, const long*, const long*, const double*,        \
-                                      hipStream_t);
+                                      hipStream_t);                                                               \
+  template void launch_add_hash<T>(cplx<T>*, long, long, int, unsigned long long, double, hipStream_t);
 
 BW_INST_BLOCK(double)
 BW_INST_BLOCK(float)
