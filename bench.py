@@ -56,6 +56,8 @@ def _args():
     ap.add_argument("--skip-subspace", action="store_true", help="do not run the subspace-iteration context arm")
     ap.add_argument("--skip-operator-arm", action="store_true", help="do not time bw_apply_K at 64^3 and 128^3")
     ap.add_argument("--skip-uneven", action="store_true", help="do not run the batched uneven-cells arm")
+    ap.add_argument("--skip-post", action="store_true",
+                    help="do not run the group-velocity / long-wave-speed arm")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with plain 1 GiB device copies (reference kernel for memory-counter runs)")
     return ap.parse_args()
@@ -217,6 +219,39 @@ def uneven_arm(bw, tol_omega=5e-6):
             "batched_speedup": round(t_seq / t_bat, 3), "max_error_bound": maxb}
 
 
+def dispersion_post_arm(bw, rve_in, ks, tol_omega=5e-6):
+    """Group velocity (d omega / ds along the path) of the 12 branches at every wave
+    vector of the workload from the mixed path's modes, and the long-wave speeds
+    along [100], [110], [111]."""
+    import numpy as np
+    import torch
+    R = bw.Rve.from_inputs(rve_in, bw.BW_MIXED)
+    bw.bw_autotune(R, min(len(ks), 64))
+    nm = 12
+    modes = torch.zeros((len(ks), nm, 3) + tuple(rve_in.n), dtype=torch.complex64, device="cuda")
+    w, _, code, _ = bw.bw_lowest_modes(R, ks, nm, method=1, tol_omega=tol_omega, tol_lin=1e-6, block=16,
+                                       modes=modes)
+    tang = np.gradient(ks, axis=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    slopes = np.stack([bw.bw_group_velocity(R, ks[i], tang[i] if np.linalg.norm(tang[i]) > 0 else [1, 0, 0],
+                                            modes[i], w[i], cluster_tol=1e-4) for i in range(len(ks))])
+    t_gv = time.perf_counter() - t0
+    del modes
+    lw = {}
+    t0 = time.perf_counter()
+    for name, d in (("100", [1, 0, 0]), ("110", [1, 1, 0]), ("111", [1, 1, 1])):
+        c, _ = bw.bw_long_wave_speeds(R, d)
+        lw[name] = [round(float(v), 2) for v in c]
+    t_lw = time.perf_counter() - t0
+    R.close()
+    torch.cuda.empty_cache()
+    return {"group_velocity_k_points_per_s": round(len(ks) / t_gv, 2), "modes": nm,
+            "acoustic_slopes_at_k1_m_per_s": [round(float(v), 2) for v in slopes[1, :3]],
+            "long_wave_seconds_per_direction": round(t_lw / 3, 3), "long_wave_speeds_m_per_s": lw,
+            "status": int(code)}
+
+
 def copy_calibration(bw):
     import torch
     n = 1 << 30
@@ -345,6 +380,9 @@ def main():
     if not a.skip_uneven:
         out.setdefault("arms", {})["uneven_batched"] = uneven_arm(bw)
         print(f"[bench] uneven arm: {out['arms']['uneven_batched']}", file=sys.stderr, flush=True)
+    if not a.skip_post:
+        out.setdefault("arms", {})["dispersion_post"] = dispersion_post_arm(bw, rve_in, ks)
+        print(f"[bench] dispersion post arm: {out['arms']['dispersion_post']}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(rve_in, ks, a.cpu_seconds)
     if a.copy_calibration:
