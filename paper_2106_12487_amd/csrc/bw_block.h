@@ -57,9 +57,10 @@ void launch_scale_copy(const cplx<T>* X, long xk, cplx<T>* Y, long yk, const dou
                        const int* act, hipStream_t s);
 
 // U[vec[e] * vstride + c * nvox + vox[e]] = val[3 e + c] (real) for e < nent
+// (added to the entry when `add`); the (vec, vox) pairs must be distinct
 template <typename T>
 void launch_set_entries(cplx<T>* U, long vstride, long nvox, int nent, const long* vec, const long* vox,
-                        const double* val, hipStream_t s);
+                        const double* val, hipStream_t s, bool add = false);
 
 // X_p += amp * (u1 + i u2), u uniform in [-1, 1) from a counter hash of (seed, p, e)
 template <typename T>

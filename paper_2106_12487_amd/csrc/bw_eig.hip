@@ -345,6 +345,21 @@ static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigO
     launch_planewaves<T>(U, q, g.nvox, sm.vox, sm.pol, s);
     BW_HIP(hipStreamSynchronize(s));
     lam_prev.clear();
+  } else if (q >= nw + 3) {
+    // warm start: the block's tail (beyond the wanted modes and two more) also gets
+    // the lowest reference plane waves of this k added, so that directions absent
+    // from the previous k's Ritz block enter; for a homogeneous cell the plane waves
+    // are exact eigenvectors, and no iteration would bring a missing one in
+    const int keep = nw + 2, nf = q - keep;
+    std::vector<long> vox, vec(nf);
+    std::vector<double> pol;
+    reference_start(r, qt, nf, vox, pol);
+    for (int i = 0; i < nf; ++i) vec[i] = keep + i;
+    BW_HIP(hipMemcpyAsync(sm.vox, vox.data(), nf * sizeof(long), hipMemcpyHostToDevice, s));
+    BW_HIP(hipMemcpyAsync(sm.vox + 128, vec.data(), nf * sizeof(long), hipMemcpyHostToDevice, s));
+    BW_HIP(hipMemcpyAsync(sm.pol, pol.data(), 3 * nf * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_set_entries<T>(U, n3, g.nvox, nf, sm.vox + 128, sm.vox, sm.pol, s, true);
+    BW_HIP(hipStreamSynchronize(s));
   }
   const bool fp32 = sizeof(T) == 4;
   // FP32 stage: the eigenvalue change must settle to tol (at least 1e-6) and the

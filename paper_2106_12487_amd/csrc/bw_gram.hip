@@ -670,18 +670,23 @@ void launch_scale_copy(const cplx<T>* X, long xk, cplx<T>* Y, long yk, const dou
 
 template <typename T>
 __global__ void k_set_entries(cplx<T>* U, long vstride, long nvox, int nent, const long* vec, const long* vox,
-                              const double* val) {
+                              const double* val, int add) {
   const int t = threadIdx.x;
   if (t >= nent * 3) return;
   const int e = t / 3, c = t - 3 * e;
-  U[(size_t)vec[e] * vstride + (size_t)c * nvox + vox[e]] = from_d2<T>(make_double2(val[t], 0.0));
+  cplx<T>& u = U[(size_t)vec[e] * vstride + (size_t)c * nvox + vox[e]];
+  if (add)
+    u.x = (T)((double)u.x + val[t]);
+  else
+    u = from_d2<T>(make_double2(val[t], 0.0));
 }
 
 template <typename T>
 void launch_set_entries(cplx<T>* U, long vstride, long nvox, int nent, const long* vec, const long* vox,
-                        const double* val, hipStream_t s) {
+                        const double* val, hipStream_t s, bool add) {
   BW_REQUIRE(nent * 3 <= 256, BW_EINVAL, "too many entries");
-  hipLaunchKernelGGL((k_set_entries<T>), dim3(1), dim3(256), 0, s, U, vstride, nvox, nent, vec, vox, val);
+  hipLaunchKernelGGL((k_set_entries<T>), dim3(1), dim3(256), 0, s, U, vstride, nvox, nent, vec, vox, val,
+                     (int)add);
 }
 
 // X_p[e] += amp * (u1 + i u2) with u1, u2 uniform in [-1, 1) from a 64-bit
@@ -732,7 +737,7 @@ void launch_add_hash(cplx<T>* X, long n, long vstride, int nv, unsigned long lon
   template void launch_scale_copy<T>(const cplx<T>*, long, cplx<T>*, long, const double*, int, long, const int*,  \
                                      hipStream_t);                                                                \
   template void launch_set_entries<T>(cplx<T>*, long, long, int, const long*, const long*, const double*,        \
-                                      hipStream_t);                                                               \
+                                      hipStream_t, bool);                                                         \
   template void launch_add_hash<T>(cplx<T>*, long, long, int, unsigned long long, double, hipStream_t);
 
 BW_INST_BLOCK(double)

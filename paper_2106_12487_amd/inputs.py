@@ -251,6 +251,28 @@ def bilayer(N: int, L: float, mat1: dict, mat2: dict) -> RVE:
     return RVE((N, 1, 1), (L, L, L), g, C21, np.array([mat1["rho"], mat2["rho"]]))
 
 
+def fibre_composite(n: int, L: float, section: str, vf: float, matrix: dict = None, fibre: dict = None) -> RVE:
+    """Long-fibre composite (Sec. 4.3): one fibre along z per n x n x 1 cell, centred,
+    square arrangement.  section "circle" (radius L sqrt(vf / pi)) or "square" (side
+    L sqrt(vf), edges along x and y); a voxel is fibre when its centre lies inside.
+    Phase 0 is the matrix (epoxy by default), phase 1 the fibre (carbon)."""
+    matrix = matrix or EPOXY
+    fibre = fibre or CARBON
+    c = (np.arange(n) + 0.5) * (L / n) - 0.5 * L
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    if section == "circle":
+        inside = X ** 2 + Y ** 2 < vf * L * L / np.pi
+    elif section == "square":
+        h = 0.5 * L * math.sqrt(vf)
+        inside = (np.abs(X) < h) & (np.abs(Y) < h)
+    else:
+        raise ValueError(section)
+    g = inside.astype(np.uint16)[:, :, None]
+    C21 = np.stack([voigt_to_c21(matrix["C"]), voigt_to_c21(fibre["C"])])
+    return RVE((n, n, 1), (L, L, L), g, C21, np.array([matrix["rho"], fibre["rho"]]),
+               dict(section=section, vf=vf, vf_voxels=float(inside.mean())))
+
+
 # --------------------------------------------------------------------------
 # wave-vector paths (simple cubic Brillouin zone)
 # --------------------------------------------------------------------------

@@ -6,6 +6,7 @@ here touches the HIP path.  Usage:
     python tests/golden/make_golden.py cu16      # 16^3, 8 grains, all 11 k on Gamma-X
     python tests/golden/make_golden.py cu64      # 64^3, 64 grains, sampled k of the path (Lanczos)
     python tests/golden/make_golden.py cual32    # 32^3 Cu/Al cell of the uneven workload, 4 k (Lanczos)
+    python tests/golden/make_golden.py fibre128  # 128 x 128 x 1 epoxy / 55% circular carbon fibres, 4 k (Lanczos)
 
 Output: tests/golden/<name>.json with the wave vectors (rad/m), omega (rad/s)
 and the oracle settings.
@@ -48,10 +49,20 @@ def run(name):
         cfg, nmodes, block = 3, 8, 16
         idx = [0, 5, 11, 17]
         method = "lanczos"
+    elif name == "fibre128":
+        # Sec. 4.3 workload: 90 k on M-Gamma-X-M; wave vectors off the symmetry points
+        # (no symmetry-forced degeneracy, which a single-vector Lanczos would find once)
+        cfg, nmodes, block = None, 10, 16
+        idx = [18, 50, 60, 75]
+        method = "lanczos"
     else:
         raise SystemExit(f"unknown golden set {name}")
-    rve = inputs.workload_rve(cfg, 0)
-    ks = inputs.workload_kpoints(cfg)[idx]
+    if cfg is None:
+        rve = inputs.fibre_composite(128, inputs.L_MM, "circle", 0.55)
+        ks = inputs.kpath("MGXM", 90, inputs.L_MM)[idx]
+    else:
+        rve = inputs.workload_rve(cfg, 0)
+        ks = inputs.workload_kpoints(cfg)[idx]
     out = dict(name=name, config=cfg, nmodes=nmodes, block=block, method=method, tol_eig=1e-12, tol_lin=1e-12,
                k_index=idx, k=ks.tolist(), omega=[], seconds=[], pcg_iters=[], outer=[])
     path = os.path.join(HERE, f"{name}.json")
