@@ -56,6 +56,7 @@ def _args():
     ap.add_argument("--skip-subspace", action="store_true", help="do not run the subspace-iteration context arm")
     ap.add_argument("--skip-operator-arm", action="store_true", help="do not time bw_apply_K at 64^3 and 128^3")
     ap.add_argument("--skip-uneven", action="store_true", help="do not run the batched uneven-cells arm")
+    ap.add_argument("--skip-fibre", action="store_true", help="do not run the long-fibre composite arm")
     ap.add_argument("--skip-post", action="store_true",
                     help="do not run the group-velocity / long-wave-speed arm")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -252,6 +253,30 @@ def dispersion_post_arm(bw, rve_in, ks, tol_omega=5e-6):
             "status": int(code)}
 
 
+def fibre_arm(bw, tol_omega=5e-6):
+    """Sec. 4.3 workload: epoxy with long carbon fibres (55% circular, 65% square
+    sections) on 128 x 128 x 1, 90 wave vectors on M-Gamma-X-M, 10 modes, mixed path,
+    subspace iteration (block 16; the square cell's symmetry points carry exactly
+    degenerate branches)."""
+    import numpy as np
+    from paper_2106_12487_amd import inputs
+    ks = inputs.kpath("MGXM", 90, inputs.L_MM)
+    out = {}
+    for section, vf in (("circle", 0.55), ("square", 0.65)):
+        R = bw.Rve.from_inputs(inputs.fibre_composite(128, inputs.L_MM, section, vf), bw.BW_MIXED)
+        bw.bw_autotune(R, 16)
+        kw = dict(method=0, block=16, tol_omega=tol_omega, tol_lin=1e-6)
+        bw.bw_lowest_modes(R, ks[:2], 10, **kw)                      # warm-up (workspaces)
+        t0 = time.perf_counter()
+        w, er, code, st = bw.bw_lowest_modes(R, ks, 10, **kw)
+        dt = time.perf_counter() - t0
+        R.close()
+        out[f"{section}_{int(round(vf * 100))}"] = {
+            "k_points_per_s": round(len(ks) / dt, 2), "max_error_bound": float(er.max()), "status": int(code),
+            "gap_5_6": [float(w[:, 4].max()), float(w[:, 5].min())], "pcg_iterations": st["pcg_iterations"]}
+    return {"grid": [128, 128, 1], "k_points": len(ks), "modes": 10, "path": "M-G-X-M", **out}
+
+
 def copy_calibration(bw):
     import torch
     n = 1 << 30
@@ -380,6 +405,9 @@ def main():
     if not a.skip_uneven:
         out.setdefault("arms", {})["uneven_batched"] = uneven_arm(bw)
         print(f"[bench] uneven arm: {out['arms']['uneven_batched']}", file=sys.stderr, flush=True)
+    if not a.skip_fibre:
+        out.setdefault("arms", {})["fibre_composite"] = fibre_arm(bw)
+        print(f"[bench] fibre arm: {out['arms']['fibre_composite']}", file=sys.stderr, flush=True)
     if not a.skip_post:
         out.setdefault("arms", {})["dispersion_post"] = dispersion_post_arm(bw, rve_in, ks)
         print(f"[bench] dispersion post arm: {out['arms']['dispersion_post']}", file=sys.stderr, flush=True)
