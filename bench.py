@@ -277,6 +277,27 @@ def fibre_arm(bw, tol_omega=5e-6):
     return {"grid": [128, 128, 1], "k_points": len(ks), "modes": 10, "path": "M-G-X-M", **out}
 
 
+def texture_arm(bw):
+    """Sec. 5.2 effect of texture: long-wave speeds along x and z of 64^3 / 64-grain Ni
+    polycrystals with random, [111]-fibre and [100]-fibre textures (mixed path), and of the
+    Sec. 5.1 1D Ni bar (256 voxels, 64 grains, Zener 2.45) along the bar."""
+    from paper_2106_12487_amd import inputs
+    L = inputs.L_MM
+    out = {}
+    t0 = time.perf_counter()
+    for tex in ("haar", "fibre111", "fibre100"):
+        R = bw.Rve.from_inputs(inputs.polycrystal((64, 64, 64), (L, L, L), 64, 52, 0, texture=tex, phases=("ni",)),
+                               bw.BW_MIXED)
+        out[tex] = {d: [round(float(v), 2) for v in bw.bw_long_wave_speeds(R, vec)[0]]
+                    for d, vec in (("x", [1, 0, 0]), ("z", [0, 0, 1]))}
+        R.close()
+    R = bw.Rve.from_inputs(inputs.ni_bar(256, 64, 50e-6, 50e-6, 2.45, 0), bw.BW_FP64)
+    out["ni_bar_A2.45"] = [round(float(v), 2) for v in bw.bw_long_wave_speeds(R, [1, 0, 0])[0]]
+    R.close()
+    out["seconds"] = round(time.perf_counter() - t0, 2)
+    return out
+
+
 def copy_calibration(bw):
     import torch
     n = 1 << 30
@@ -409,6 +430,8 @@ def main():
         out.setdefault("arms", {})["fibre_composite"] = fibre_arm(bw)
         print(f"[bench] fibre arm: {out['arms']['fibre_composite']}", file=sys.stderr, flush=True)
     if not a.skip_post:
+        out.setdefault("arms", {})["textures_long_wave_m_per_s"] = texture_arm(bw)
+        print(f"[bench] texture arm: {out['arms']['textures_long_wave_m_per_s']}", file=sys.stderr, flush=True)
         out.setdefault("arms", {})["dispersion_post"] = dispersion_post_arm(bw, rve_in, ks)
         print(f"[bench] dispersion post arm: {out['arms']['dispersion_post']}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:

@@ -155,6 +155,18 @@ def rot_z(psi: float) -> np.ndarray:
     return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
 
 
+def fibre_rotations(axis, psi: np.ndarray) -> np.ndarray:
+    """Fibre texture (Sec. 5.2, effect of texture): the crystal direction `axis` along
+    sample z, spin psi about z.  R = Rz(psi) R0 with R0 the smallest rotation taking
+    axis / |axis| to z (columns of R: crystal axes in the sample frame)."""
+    a = np.asarray(axis, dtype=np.float64) / np.linalg.norm(axis)
+    z = np.array([0.0, 0.0, 1.0])
+    v = np.cross(a, z)
+    s, c = np.linalg.norm(v), float(a @ z)
+    R0 = np.eye(3) if s == 0.0 else rotvec_matrix(v / s * math.atan2(s, c))
+    return np.stack([rot_z(p) @ R0 for p in psi])
+
+
 def c_axis_texture(tilt: np.ndarray, psi: np.ndarray) -> np.ndarray:
     """R = Exp([tx, ty, 0]) Rz(psi): c-axes spread about sample z, free spin about c."""
     return np.stack([rotvec_matrix(np.array([t[0], t[1], 0.0])) @ rot_z(p)
@@ -209,21 +221,25 @@ def polycrystal(n, L, n_grains: int, config: int, index: int, texture: str = "ha
                 phases=("cu",)) -> RVE:
     """Periodic Voronoi polycrystal.
 
-    texture: "haar" (uniform random) or "ti_c_axis" (c-axes N(0, 15 deg) about z).
-    phases:  ("cu",), ("ti",) or ("cu", "al") (each grain Cu or Al with p = 1/2).
+    texture: "haar" (uniform random), "ti_c_axis" (c-axes N(0, 15 deg) about z),
+             "fibre100" / "fibre111" (crystal [100] / [111] along z, uniform spin about z).
+    phases:  ("cu",), ("ti",), ("ni",) or ("cu", "al") (each grain Cu or Al with p = 1/2).
     """
     rng = rng_for(config, index)
     L = tuple(float(v) for v in L)
     seeds = rng.random((n_grains, 3)) * np.asarray(L)
     if texture == "haar":
         R = haar_rotations(rng.random((n_grains, 3)))
+    elif texture in ("fibre100", "fibre111"):
+        psi = rng.random((n_grains, 3))[:, 0] * 2.0 * np.pi
+        R = fibre_rotations([1, 0, 0] if texture == "fibre100" else [1, 1, 1], psi)
     elif texture == "ti_c_axis":
         tilt = rng.normal(0.0, math.radians(15.0), size=(n_grains, 2))
         psi = rng.random(n_grains) * 2.0 * np.pi
         R = c_axis_texture(tilt, psi)
     else:
         raise ValueError(texture)
-    lib = {"cu": CU, "al": AL, "ti": TI}
+    lib = {"cu": CU, "al": AL, "ti": TI, "ni": NI}
     if len(phases) == 1:
         choice = [phases[0]] * n_grains
     else:
@@ -249,6 +265,30 @@ def bilayer(N: int, L: float, mat1: dict, mat2: dict) -> RVE:
     g[x > 0.5 * L, 0, 0] = 1
     C21 = np.stack([voigt_to_c21(mat1["C"]), voigt_to_c21(mat2["C"])])
     return RVE((N, 1, 1), (L, L, L), g, C21, np.array([mat1["rho"], mat2["rho"]]))
+
+
+def ni_bar(n: int, n_grains: int, Dbar: float, sd: float, A: float, index: int, config: int = 51) -> RVE:
+    """1D polycrystal (Sec. 5.1) on an n x 1 x 1 grid: n_grains layers along x with
+    lengths drawn from N(Dbar, sd) (draws below Dbar / 5 are redrawn), rescaled to sum to
+    L = n_grains Dbar; Ni constants with C44 = A (C11 - C12) / 2 (Zener ratio A);
+    Haar-random orientations.  Draw order: lengths, then orientations."""
+    rng = rng_for(config, index)
+    lengths = np.empty(n_grains)
+    for g in range(n_grains):
+        x = rng.normal(Dbar, sd) if sd > 0 else Dbar
+        while x < 0.2 * Dbar:
+            x = rng.normal(Dbar, sd)
+        lengths[g] = x
+    L = n_grains * Dbar
+    edges = np.concatenate([[0.0], np.cumsum(lengths)]) * (L / lengths.sum())
+    R = haar_rotations(rng.random((n_grains, 3)))
+    c11, c12 = NI["C"][0, 0], NI["C"][0, 1]
+    C = cubic_voigt(c11, c12, A * (c11 - c12) / 2)
+    x = (np.arange(n) + 0.5) * (L / n)
+    g = np.clip(np.searchsorted(edges, x, side="right") - 1, 0, n_grains - 1).astype(np.uint16)
+    C21 = np.stack([voigt_to_c21(rotate_voigt(C, R[i])) for i in range(n_grains)])
+    return RVE((n, 1, 1), (L, L, L), g[:, None, None], C21, np.full(n_grains, NI["rho"]),
+               dict(config=config, index=index, A=A, Dbar=Dbar, sd=sd, R=R))
 
 
 def fibre_composite(n: int, L: float, section: str, vf: float, matrix: dict = None, fibre: dict = None) -> RVE:

@@ -107,3 +107,47 @@ def test_long_wave_speeds_polycrystal_within_voigt_reuss(d):
 
 def test_clusters_groups_equal_frequencies():
     assert postproc.clusters(np.array([0.0, 0.0, 1.0, 1.0 + 1e-9, 2.0]), 1e-6) == [[0, 1], [2, 3], [4]]
+
+
+def _christoffel(C6, d):
+    T = inputs.voigt_to_tensor(C6)
+    return np.einsum("ijkl,j,l->ik", T, d, d)
+
+
+def test_long_wave_speeds_fibre100_texture_along_z_exact():
+    """[100] fibre texture (Sec. 5.2, effect of texture): every grain has the cubic axis along
+    z, so a uniform strain e_zz or e_xz / e_yz gives the same stress in every grain (rotations
+    about a cube axis keep C33, C13, C44 and the zero couplings): the uniform field is the
+    exact long-wave solution and c_L = sqrt(C11 / rho), c_T = sqrt(C44 / rho) (twice)."""
+    ni = inputs.NI
+    rve = inputs.polycrystal((6, 6, 6), (L, L, L), 8, 52, 0, texture="fibre100", phases=("ni",))
+    c = postproc.long_wave_speeds(rve, [0, 0, 1], method="dense")
+    ref = np.sqrt(np.array([ni["C"][3, 3], ni["C"][3, 3], ni["C"][0, 0]]) / ni["rho"])
+    np.testing.assert_allclose(c, ref, rtol=1e-7)
+    cx = postproc.long_wave_speeds(rve, [1, 0, 0], method="dense")          # not trivial across z
+    assert np.abs(cx - ref).max() > 1e-3 * ref.max()
+
+
+def test_long_wave_speeds_fibre111_texture_longitudinal_exact():
+    """[111] fibre texture: rotations about a 3-fold axis keep C'3333 = (C11 + 2 C12 + 4 C44) / 3
+    and C'13, and C'3323 = C'3313 = 0, so uniform e_zz is exact for the longitudinal wave."""
+    ni = inputs.NI
+    C = ni["C"]
+    rve = inputs.polycrystal((6, 6, 6), (L, L, L), 8, 52, 1, texture="fibre111", phases=("ni",))
+    c = postproc.long_wave_speeds(rve, [0, 0, 1], method="dense")
+    cl = np.sqrt((C[0, 0] + 2 * C[0, 1] + 4 * C[3, 3]) / 3 / ni["rho"])
+    np.testing.assert_allclose(c[2], cl, rtol=1e-7)
+
+
+def test_long_wave_speeds_ni_bar_is_matrix_harmonic_mean():
+    """1D polycrystal (Sec. 5.1) as layers normal to x: the traction on the layer planes is
+    uniform in the long-wave limit, so rho c^2 are the eigenvalues of the matrix harmonic mean
+    of the layers' Christoffel matrices along x (voxel average)."""
+    rve = inputs.ni_bar(32, 8, 50e-6, 50e-6, 2.45, 0)
+    c = postproc.long_wave_speeds(rve, [1, 0, 0], method="dense")
+    C6 = np.stack([inputs.c21_to_voigt(x) for x in rve.C21])[rve.grain_map.ravel()]
+    G = np.linalg.inv(np.mean([np.linalg.inv(_christoffel(Ci, np.array([1.0, 0, 0]))) for Ci in C6], axis=0))
+    ref = np.sqrt(np.sort(np.linalg.eigvalsh(G)) / inputs.NI["rho"])
+    np.testing.assert_allclose(c, ref, rtol=1e-6)
+    Gv = np.mean([_christoffel(Ci, np.array([1.0, 0, 0])) for Ci in C6], axis=0)   # Voigt: off
+    assert np.abs(np.sqrt(np.sort(np.linalg.eigvalsh(Gv)) / inputs.NI["rho"]) - ref).max() > 1e-3 * ref.max()
