@@ -238,7 +238,16 @@ def dispersion_post_arm(bw, rve_in, ks, tol_omega=5e-6):
     slopes = np.stack([bw.bw_group_velocity(R, ks[i], tang[i] if np.linalg.norm(tang[i]) > 0 else [1, 0, 0],
                                             modes[i], w[i], cluster_tol=1e-4) for i in range(len(ks))])
     t_gv = time.perf_counter() - t0
-    del modes
+    # real-space displacement + strain maps of the 12 modes at every wave vector
+    u = torch.empty_like(modes[0])
+    eps = torch.empty((nm, 6) + tuple(rve_in.n), dtype=modes.dtype, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(len(ks)):
+        bw.bw_mode_fields(R, ks[i], modes[i], u, eps)
+    torch.cuda.synchronize()
+    t_mf = time.perf_counter() - t0
+    del modes, u, eps
     lw = {}
     t0 = time.perf_counter()
     for name, d in (("100", [1, 0, 0]), ("110", [1, 1, 0]), ("111", [1, 1, 1])):
@@ -248,6 +257,7 @@ def dispersion_post_arm(bw, rve_in, ks, tol_omega=5e-6):
     R.close()
     torch.cuda.empty_cache()
     return {"group_velocity_k_points_per_s": round(len(ks) / t_gv, 2), "modes": nm,
+            "mode_fields_k_points_per_s": round(len(ks) / t_mf, 2),
             "acoustic_slopes_at_k1_m_per_s": [round(float(v), 2) for v in slopes[1, :3]],
             "long_wave_seconds_per_direction": round(t_lw / 3, 3), "long_wave_speeds_m_per_s": lw,
             "status": int(code)}

@@ -343,6 +343,20 @@ int bw_group_velocity(bw_rve* rve, const double k_host[3], const double dir[3], 
 int bw_long_wave_speeds(bw_rve* rve, const double dir[3], double h_frac, double tol_omega, double* c_host,
                         void* stream);
 
+/* Real-space fields of modes at k (Sec. 5.2, eigenvectors, eq. rotate_eigenvector):
+ * u = e^{-i phi} F^-1(U^) with the inverse DFT normalized by 1/N and
+ * phi = arg(sum_x u . u) / 2 (the phase that brings the field closest to real;
+ * for a field of common phase it is that phase, up to pi; 0 when the sum
+ * vanishes), and the strain eps = e^{-i phi} F^-1[i B(xi + k) U^] (Voigt order
+ * 11, 22, 33, 23, 13, 12, engineering shear; the strain of the Bloch wave
+ * u(x) e^{i k.x} divided by e^{i k.x}).  Grid point i sits at x = i L / n.
+ * modes: device [nmodes][3][n0][n1][n2] complex in the cell's precision (as
+ * bw_lowest_modes writes them); u_out: device, same shape; eps_out: optional
+ * device [nmodes][6][n0][n1][n2]; phase_host: optional float64[nmodes].  No
+ * argument may alias another.  Synchronizes `stream`. */
+int bw_mode_fields(bw_rve* rve, const double k_host[3], int32_t nmodes, const void* modes, void* u_out,
+                   void* eps_out, double* phase_host, void* stream);
+
 /* Diagnostics: a plain streaming copy of `bytes` (a multiple of 16, below
  * 2^39; 16-byte aligned device buffers, not overlapping) on `stream`, the
  * reference kernel for calibrating memory-traffic counters (its algorithmic

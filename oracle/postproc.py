@@ -19,6 +19,11 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
                    omega / |k| = c + O(k^2) and (4 c(h) - c(2h)) / 3 = c + O(h^4);
                    the long-wave limit is the speed of the equivalent homogeneous
                    medium (Sec. 5.1, the limit of d omega / dk for k -> 0).
+* mode_fields      real-space fields of modes (Sec. 5.2, eigenvectors, eq.
+                   rotate_eigenvector): u = e^{-i phi} F^-1 U^ with phi = arg(sum u.u)/2
+                   (the phase that brings the field closest to real; the paper's common
+                   phase when there is one), and the strain of the Bloch wave divided by
+                   e^{i k.x}: e^{-i phi} F^-1[i B(xi + k) U^].
 * voigt_reuss_bracket  Christoffel eigenvalues of the Voigt (mean stiffness) and
                    Reuss (inverse mean compliance) averages, which bound rho_bar c^2
                    of the long-wave limit from above and below.
@@ -27,7 +32,10 @@ Pins (tests/test_oracle_postproc.py): homogeneous isotropic and cubic closed
 forms, including a folded branch omega = c |k + G|; central differences of
 exact (dense) eigenvalues; the laminate's exact quasi-static moduli along its
 normal (the Reuss averages of the P-wave and shear moduli); the Voigt/Reuss
-bracket for a polycrystal.
+bracket for a polycrystal; exact long-wave speeds along the axis of fibre
+textures; the 1D polycrystal's matrix harmonic mean; for mode_fields, a real
+field rotated by a known phase and the analytic strain of a trigonometric
+displacement.
 """
 from __future__ import annotations
 
@@ -131,3 +139,14 @@ def voigt_reuss_bracket(rve, d):
         T = voigt_to_tensor(C6)
         return np.sort(np.linalg.eigvalsh(np.einsum("ijkl,j,l->ik", T, d, d)))
     return christoffel(CR), christoffel(CV)
+
+
+def mode_fields(rve, k, U):
+    """(u, eps, phi) of the modes U (nmodes, 3, N0, N1, N2): displacement and Voigt strain
+    (engineering shear) in real space, rotated by e^{-i phi}."""
+    ops = Operators(rve, k)
+    u = ifft3(U)
+    phi = 0.5 * np.angle(np.sum(u * u, axis=(-4, -3, -2, -1)))
+    rot = np.exp(-1j * phi)[..., None, None, None, None]
+    eps = ifft3(1j * ops.strain(U))
+    return u * rot, eps * rot, phi

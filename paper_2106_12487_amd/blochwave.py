@@ -87,6 +87,7 @@ _SIGS = {
     "bw_pcg_solve_learned": (_I, [_P, _P, _DP, _P, _P, _I, _D, _I, _IP, _DP, _IP, _P]),
     "bw_group_velocity": (_I, [_P, _DP, _DP, _I, _P, _DP, _D, _DP, _P]),
     "bw_long_wave_speeds": (_I, [_P, _DP, _D, _D, _DP, _P]),
+    "bw_mode_fields": (_I, [_P, _DP, _I, _P, _P, _P, _DP, _P]),
 }
 
 
@@ -322,6 +323,17 @@ def bw_long_wave_speeds(rve: Rve, direction, h_frac: float = 0.02, tol_omega: fl
     code = _check(lib().bw_long_wave_speeds(rve.handle, d_p, float(h_frac), float(tol_omega),
                                             out.ctypes.data_as(_DP), _stream(stream)))
     return out, code
+
+
+def bw_mode_fields(rve: Rve, k, modes, u_out, eps_out=None, stream=None) -> np.ndarray:
+    """Real-space displacement (and strain) fields of the modes at k; returns the phases."""
+    nm = int(modes.shape[0])
+    k_arr, k_p = _darr(np.asarray(k, dtype=np.float64).reshape(3))
+    ph = np.zeros(nm)
+    _check(lib().bw_mode_fields(rve.handle, k_p, nm, _dptr(modes), _dptr(u_out),
+                                _dptr(eps_out) if eps_out is not None else None, ph.ctypes.data_as(_DP),
+                                _stream(stream)))
+    return ph
 
 
 # ---------------------------------------------------------------------------

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "bw_block.h"
+#include "bw_ops_impl.h"
 
 using namespace bw;
 
@@ -201,6 +202,188 @@ extern "C" int bw_long_wave_speeds(bw_rve* r, const double dir[3], double h_frac
     std::sort(om + 3, om + 6);
     for (int i = 0; i < 3; ++i) c_host[i] = (4.0 * om[i] / h - om[3 + i] / (2.0 * h)) / 3.0;
     return code;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal: ") + e.what());
+    return BW_EINVAL;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Real-space mode fields (Sec. 5.2, eigenvectors, eq. rotate_eigenvector):
+// U(x) = e^{-i phi} F^-1(U^) with phi = arg(sum_x U . U) / 2, the phase that makes
+// the field as close to real as it can be (for a field of common phase, that
+// phase, up to pi); strain eps(x) = e^{-i phi} F^-1[i B(xi + k) U^] (Voigt,
+// engineering shear), the strain of the Bloch wave U(x) e^{i k.x} divided by its
+// phase factor e^{i k.x}.
+// ---------------------------------------------------------------------------
+namespace {
+
+// unnormalized inverse 3D FFT of nv fields of nc components, in place
+template <typename T> void ifft3_nc(const bw_rve* r, cplx<T>* X, int nv, int nc, hipStream_t s) {
+  const Geom& g = r->g;
+  const long rows = (long)nc * g.n0 * g.n1;
+  with_n(g.n2, [&](auto N2) {
+    constexpr int n2c = decltype(N2)::value;
+    RowTile rt = row_tile<T>(n2c, rows);
+    hipLaunchKernelGGL((k_row_plain<T, n2c, true>), dim3(nv * rt.tpv), dim3(NT), 0, s, (const cplx<T>*)X, X, rt,
+                       (int)rows, twiddles<T>(r, 2), (const int*)nullptr);
+  });
+  if (g.n1 > 1)
+    with_n(g.n1, [&](auto N1) {
+      ColTile ct = axis1_tile<T>(N1, g.n2, (long)nc * g.n0 * g.n2);
+      hipLaunchKernelGGL((k_axis1<T, decltype(N1)::value, true>), dim3(nv * ct.tpv), dim3(NT), 0, s, X, g.n2,
+                         (long)nc * g.nvox, ct, twiddles<T>(r, 1), (const int*)nullptr);
+    });
+  if (g.n0 > 1) {
+    const int n12 = g.n1 * g.n2;
+    with_n(g.n0, [&](auto N0) {
+      ColTile ct = axis1_tile<T>(N0, n12, (long)nc * n12);
+      hipLaunchKernelGGL((k_axis1<T, decltype(N0)::value, true>), dim3(nv * ct.tpv), dim3(NT), 0, s, X, n12,
+                         (long)nc * g.nvox, ct, twiddles<T>(r, 0), (const int*)nullptr);
+    });
+  }
+}
+
+// E = i B(q) U per Fourier voxel; q = qscale * table (the table of one wave vector)
+template <typename T>
+__global__ void k_strain_hat(const cplx<T>* __restrict__ U, const double* __restrict__ qtab, cplx<T>* __restrict__ E,
+                             int n0, int n1, int n2, long nvox, int nv, double qscale) {
+  const long total = (long)nv * nvox;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long v = e / nvox, x = e - v * nvox;
+    const int i2 = (int)(x % n2), i1 = (int)((x / n2) % n1), i0 = (int)(x / ((long)n1 * n2));
+    const double qa = qscale * qtab[i0], qb = qscale * qtab[n0 + i1], qc = qscale * qtab[n0 + n1 + i2];
+    double ur[3], ui[3];
+    for (int c = 0; c < 3; ++c) {
+      const cplx<T> u = U[((size_t)v * 3 + c) * nvox + x];
+      ur[c] = (double)u.x;
+      ui[c] = (double)u.y;
+    }
+    // Voigt strain [q1 U1, q2 U2, q3 U3, q3 U2 + q2 U3, q3 U1 + q1 U3, q2 U1 + q1 U2], times i
+    const double sr[6] = {qa * ur[0], qb * ur[1], qc * ur[2], qc * ur[1] + qb * ur[2], qc * ur[0] + qa * ur[2],
+                          qb * ur[0] + qa * ur[1]};
+    const double si[6] = {qa * ui[0], qb * ui[1], qc * ui[2], qc * ui[1] + qb * ui[2], qc * ui[0] + qa * ui[2],
+                          qb * ui[0] + qa * ui[1]};
+    for (int c = 0; c < 6; ++c) {
+      cplx<T> o;
+      o.x = (T)(-si[c]);
+      o.y = (T)sr[c];
+      E[((size_t)v * 6 + c) * nvox + x] = o;
+    }
+  }
+}
+
+// per-block partial sums of (Re, Im) of sum U . U over nc components, bpv blocks per field
+template <typename T>
+__global__ void k_square_sum(const cplx<T>* __restrict__ X, long n, int bpv, double* __restrict__ part) {
+  __shared__ double sh[2][256];
+  const int v = blockIdx.x / bpv, b = blockIdx.x - v * bpv;
+  double re = 0, im = 0;
+  for (long e = (long)b * blockDim.x + threadIdx.x; e < n; e += (long)bpv * blockDim.x) {
+    const cplx<T> u = X[(size_t)v * n + e];
+    re += (double)u.x * u.x - (double)u.y * u.y;
+    im += 2.0 * (double)u.x * u.y;
+  }
+  sh[0][threadIdx.x] = re;
+  sh[1][threadIdx.x] = im;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * ((size_t)v * bpv + b)] = sh[0][0];
+    part[2 * ((size_t)v * bpv + b) + 1] = sh[1][0];
+  }
+}
+
+// X_v *= c_v (complex, device) over n elements per field
+template <typename T>
+__global__ void k_scale_fields(cplx<T>* X, long n, int nv, const double2* __restrict__ c) {
+  const long total = (long)nv * n;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const double2 f = c[e / n];
+    const cplx<T> u = X[e];
+    cplx<T> o;
+    o.x = (T)(f.x * (double)u.x - f.y * (double)u.y);
+    o.y = (T)(f.x * (double)u.y + f.y * (double)u.x);
+    X[e] = o;
+  }
+}
+
+unsigned grid_of(long total) {
+  long b = (total + 255) / 256;
+  return (unsigned)(b > 65536 ? 65536 : (b < 1 ? 1 : b));
+}
+
+template <typename T>
+void mode_fields(bw_rve* r, const double* k, int nm, const cplx<T>* Uh, cplx<T>* u, cplx<T>* eps, double* phase,
+                 hipStream_t s) {
+  const Geom& g = r->g;
+  const long n3 = 3 * g.nvox;
+  BW_HIP(hipMemcpyAsync(u, Uh, (size_t)nm * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
+  ifft3_nc<T>(r, u, nm, 3, s);
+  const int bpv = 64;
+  double* part = (double*)r->ws_misc.get((size_t)nm * bpv * 2 * sizeof(double) + (size_t)nm * sizeof(double2));
+  double2* coef = (double2*)(part + (size_t)nm * bpv * 2);
+  hipLaunchKernelGGL((k_square_sum<T>), dim3((unsigned)(nm * bpv)), dim3(256), 0, s, (const cplx<T>*)u, n3, bpv,
+                     part);
+  std::vector<double> ph((size_t)nm * bpv * 2);
+  BW_HIP(hipMemcpyAsync(ph.data(), part, ph.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  BW_HIP(hipStreamSynchronize(s));
+  std::vector<double2> cf(nm);
+  for (int v = 0; v < nm; ++v) {
+    double re = 0, im = 0;
+    for (int b = 0; b < bpv; ++b) {
+      re += ph[2 * ((size_t)v * bpv + b)];
+      im += ph[2 * ((size_t)v * bpv + b) + 1];
+    }
+    const double phi = 0.5 * std::atan2(im, re);
+    if (phase) phase[v] = phi;
+    // e^{-i phi} / N (the inverse transform above is unnormalized)
+    cf[v] = double2{std::cos(phi) / (double)g.nvox, -std::sin(phi) / (double)g.nvox};
+  }
+  BW_HIP(hipMemcpyAsync(coef, cf.data(), nm * sizeof(double2), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL((k_scale_fields<T>), dim3(grid_of((long)nm * n3)), dim3(256), 0, s, u, n3, nm,
+                     (const double2*)coef);
+  if (eps) {
+    QTable qt = make_qtable(r, k, 1);
+    const double* dq = upload_qtable(r, qt, r->ws_q3, s);
+    hipLaunchKernelGGL((k_strain_hat<T>), dim3(grid_of((long)nm * g.nvox)), dim3(256), 0, s, Uh, dq, eps, g.n0, g.n1,
+                       g.n2, g.nvox, nm, 1.0 / r->ell);
+    ifft3_nc<T>(r, eps, nm, 6, s);
+    hipLaunchKernelGGL((k_scale_fields<T>), dim3(grid_of((long)nm * 6 * g.nvox)), dim3(256), 0, s, eps,
+                       6 * g.nvox, nm, (const double2*)coef);
+  }
+  BW_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+extern "C" int bw_mode_fields(bw_rve* r, const double k[3], int32_t nmodes, const void* modes, void* u_out,
+                              void* eps_out, double* phase_host, void* stream) {
+  try {
+    BW_REQUIRE(r && k && modes && u_out, BW_EINVAL, "null argument");
+    BW_REQUIRE(nmodes >= 0, BW_EINVAL, "nmodes < 0");
+    BW_REQUIRE(modes != u_out && (!eps_out || (eps_out != modes && eps_out != u_out)), BW_EINVAL,
+               "modes, u_out and eps_out must not alias");
+    for (int a = 0; a < 3; ++a) BW_REQUIRE(std::isfinite(k[a]), BW_EINVAL, "non-finite wave vector");
+    if (nmodes == 0) return BW_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (r->precision == BW_FP64)
+      mode_fields<double>(r, k, nmodes, (const cplx<double>*)modes, (cplx<double>*)u_out, (cplx<double>*)eps_out,
+                          phase_host, s);
+    else
+      mode_fields<float>(r, k, nmodes, (const cplx<float>*)modes, (cplx<float>*)u_out, (cplx<float>*)eps_out,
+                         phase_host, s);
+    BW_HIP(hipGetLastError());
+    return BW_OK;
   } catch (const Error& e) {
     set_error(e.msg);
     return e.code;

@@ -155,3 +155,47 @@ def test_postproc_argument_errors(lib):
     with pytest.raises(lib.BlochwaveError):
         lib.bw_long_wave_speeds(R, [0, 0, 0])
     R.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mode_fields_match_oracle(lib, prec):
+    """Real-space displacement and strain (Sec. 5.2 eq. rotate_eigenvector) of seeded random
+    Fourier fields on an 8 x 6 x 4 polycrystal against the oracle (same input coefficients);
+    the phase rule picks phi up to pi, so fields are compared up to a common sign."""
+    torch = _torch()
+    rve = inputs.polycrystal((8, 6, 4), (L, L, L), 5, 94, 4)
+    k = np.array([0.37, -0.21, 0.13]) * np.pi / L
+    rng = np.random.default_rng(17)
+    Uh = rng.standard_normal((3, 3, 8, 6, 4)) + 1j * rng.standard_normal((3, 3, 8, 6, 4))
+    uo, eo, po = postproc.mode_fields(rve, k, Uh)
+    R = lib.Rve.from_inputs(rve, prec)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    Ud = torch.from_numpy(Uh).to(dt).to("cuda").contiguous()
+    u = torch.empty_like(Ud)
+    e = torch.empty((3, 6, 8, 6, 4), dtype=dt, device="cuda")
+    ph = lib.bw_mode_fields(R, k, Ud, u, e)
+    u, e = u.cpu().numpy(), e.cpu().numpy()
+    tol = 1e-12 if prec == 0 else 2e-6
+    for p in range(3):
+        sgn = np.sign(np.real(np.vdot(uo[p], u[p])))
+        assert np.abs(u[p] - sgn * uo[p]).max() <= tol * np.abs(uo[p]).max()
+        assert np.abs(e[p] - sgn * eo[p]).max() <= tol * np.abs(eo[p]).max()
+        assert abs(np.angle(np.exp(2j * (ph[p] - po[p])))) <= 1e3 * tol
+    R.close()
+
+
+def test_mode_fields_acoustic_mode_is_nearly_real(lib):
+    """The lowest mode of the 64^3 Cu cell at a small k along x (long wave): after the phase
+    rotation the displacement is real up to the heterogeneity-induced fluctuation."""
+    torch = _torch()
+    rve = inputs.workload_rve(2, 0)
+    k = inputs.workload_kpoints(2)[1]
+    R = lib.Rve.from_inputs(rve, lib.BW_MIXED)
+    w, U = _modes(lib, R, rve, k, 3, 1)
+    u = torch.empty_like(U)
+    lib.bw_mode_fields(R, k, U, u)
+    un = u.cpu().numpy()
+    re, im = np.linalg.norm(un.real), np.linalg.norm(un.imag)
+    print(f"\n[case] 64^3 acoustic modes |Im u| / |Re u| = {im / re:.3e}", flush=True)
+    assert im <= 0.05 * re
+    R.close()

@@ -151,3 +151,38 @@ def test_long_wave_speeds_ni_bar_is_matrix_harmonic_mean():
     np.testing.assert_allclose(c, ref, rtol=1e-6)
     Gv = np.mean([_christoffel(Ci, np.array([1.0, 0, 0])) for Ci in C6], axis=0)   # Voigt: off
     assert np.abs(np.sqrt(np.sort(np.linalg.eigvalsh(Gv)) / inputs.NI["rho"]) - ref).max() > 1e-3 * ref.max()
+
+
+def test_mode_fields_recover_a_rotated_real_field():
+    rng = np.random.default_rng(5)
+    rve = inputs.polycrystal((6, 4, 5), (L, L, L), 3, 94, 1)
+    w = rng.standard_normal((2, 3, 6, 4, 5))
+    alpha = np.array([0.7, -1.1])
+    from oracle.fourier import fft3
+    U = fft3(w) * np.exp(1j * alpha)[:, None, None, None, None]
+    u, _, phi = postproc.mode_fields(rve, [0.1 / L, 0, 0], U)
+    for p in range(2):
+        sgn = np.sign(np.real(u[p]).ravel() @ w[p].ravel())
+        assert np.abs(u[p] - sgn * w[p]).max() <= 1e-12 * np.abs(w[p]).max()
+        assert abs(np.angle(np.exp(2j * (phi[p] - alpha[p])))) <= 1e-12     # phi = alpha mod pi
+
+
+def test_mode_fields_strain_of_trigonometric_displacement():
+    """w = (sin 2pi x/L, 0.5 cos 2pi y/L, 0) on grid points x = i L/n: the strain of the
+    Bloch wave w e^{ik.x} divided by e^{ik.x} is sym grad w + i sym(k (x) w)."""
+    n = (8, 8, 4)
+    rve = inputs.polycrystal(n, (L, L, L), 3, 94, 1)
+    k = np.array([0.3, 0.1, 0.0]) * np.pi / L
+    x = np.arange(n[0])[:, None, None] * L / n[0] + 0 * np.zeros(n)
+    y = np.arange(n[1])[None, :, None] * L / n[1] + 0 * np.zeros(n)
+    g = 2 * np.pi / L
+    w = np.stack([np.sin(g * x), 0.5 * np.cos(g * y), np.zeros(n)])
+    from oracle.fourier import fft3
+    u, eps, phi = postproc.mode_fields(rve, k, fft3(w)[None])
+    assert abs(phi[0]) <= 1e-12
+    e11 = g * np.cos(g * x) + 1j * k[0] * w[0]
+    e22 = -0.5 * g * np.sin(g * y) + 1j * k[1] * w[1]
+    e12 = 1j * (k[1] * w[0] + k[0] * w[1])
+    e13 = 1j * k[2] * w[0]
+    for got, ref in ((eps[0, 0], e11), (eps[0, 1], e22), (eps[0, 5], e12), (eps[0, 4], e13), (eps[0, 2], 0 * x)):
+        assert np.abs(got - ref).max() <= 1e-12 * g
