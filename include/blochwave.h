@@ -334,9 +334,10 @@ int bw_group_velocity(bw_rve* rve, const double k_host[3], const double dir[3], 
 
 /* Long-wave speeds of the three acoustic branches along dir (m/s, ascending):
  * omega / |k| from bw_lowest_modes (subspace iteration, bound-based stopping at
- * tol_omega; 0 -> 1e-10 for BW_FP64, 1e-8 for BW_MIXED) at k = h dir and
- * 2h dir with h = h_frac pi / max(L) (h_frac in (0, 0.25]), extrapolated to
- * k -> 0 as (4 c(h) - c(2h)) / 3 (omega^2 is even and analytic in k).  The
+ * tol_omega; 0 -> 1e-10 for BW_FP64, 1e-8 for BW_MIXED) at k = +-h dir and
+ * +-2h dir with h = h_frac pi / max(L) (h_frac in (0, 0.25]), c(h) the mean
+ * of omega / |k| over +-k (even in k also on even grids, whose frequency set
+ * is not symmetric), extrapolated to k -> 0 as (4 c(h) - c(2h)) / 3.  The
  * limit is the speed of the equivalent homogeneous medium (Sec. 5.1).  Returns
  * the status of the eigen-solve (BW_ENOTCONV with c_host filled when a bound
  * missed tol_omega).  Synchronizes `stream`. */

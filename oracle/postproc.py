@@ -14,9 +14,10 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
                    perturbation); within a cluster of equal omega the slopes are
                    the eigenvalues of the pencil (U^H dK U, U^H M U) on the
                    cluster, each divided by 2 omega.
-* long_wave_speeds the three acoustic branches' omega / |k| at k = h d and 2h d
-                   extrapolated to k -> 0.  omega^2 is even and analytic in k, so
-                   omega / |k| = c + O(k^2) and (4 c(h) - c(2h)) / 3 = c + O(h^4);
+* long_wave_speeds the three acoustic branches' omega / |k| at k = +-h d and +-2h d
+                   extrapolated to k -> 0.  The mean over +-k of omega^2 is even and
+                   analytic in k, so it gives c + O(k^2) and (4 c(h) - c(2h)) / 3 =
+                   c + O(h^4);
                    the long-wave limit is the speed of the equivalent homogeneous
                    medium (Sec. 5.1, the limit of d omega / dk for k -> 0).
 * mode_fields      real-space fields of modes (Sec. 5.2, eigenvectors, eq.
@@ -24,6 +25,14 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
                    (the phase that brings the field closest to real; the paper's common
                    phase when there is one), and the strain of the Bloch wave divided by
                    e^{i k.x}: e^{-i phi} F^-1[i B(xi + k) U^].
+* effective_stiffness  static homogenization on the same discretization (the
+                   long-wave limit of the Bloch problem): for each of the six unit
+                   macro strains E, the periodic displacement solves
+                   K(0) U^ = i B(xi)^H F[C(x) E] (equilibrium of C (E + eps(u)), the
+                   factors i of the gradient kept: eps(u) = F^-1[i B(xi) U^]) by PCG
+                   (Algorithm "InvA"), and the column of C_eff is the volume mean of
+                   C(x) (E + eps(u)).  rho_bar c^2 of the long-wave speeds are then the
+                   Christoffel eigenvalues of C_eff.
 * voigt_reuss_bracket  Christoffel eigenvalues of the Voigt (mean stiffness) and
                    Reuss (inverse mean compliance) averages, which bound rho_bar c^2
                    of the long-wave limit from above and below.
@@ -35,7 +44,9 @@ normal (the Reuss averages of the P-wave and shear moduli); the Voigt/Reuss
 bracket for a polycrystal; exact long-wave speeds along the axis of fibre
 textures; the 1D polycrystal's matrix harmonic mean; for mode_fields, a real
 field rotated by a known phase and the analytic strain of a trigonometric
-displacement.
+displacement; for effective_stiffness, a homogeneous medium, Backus averages of
+a laminate, Voigt/Reuss bounds as quadratic forms and the Christoffel
+eigenvalues against the long-wave speeds of the eigen-solver.
 """
 from __future__ import annotations
 
@@ -46,7 +57,7 @@ from paper_2106_12487_amd.inputs import voigt_to_tensor
 
 from .fourier import fft3, ifft3
 from .operators import Operators
-from .solvers import lowest_modes
+from .solvers import lowest_modes, pcg
 
 
 def _strain_const(d, U):
@@ -118,12 +129,15 @@ def branch_slopes(rve, k, d, U, omega, cluster_tol=1e-6):
 
 def long_wave_speeds(rve, d, h_frac=0.02, **kw):
     """The three acoustic long-wave speeds (ascending) along the unit direction d;
-    h = h_frac pi / max(L).  Keyword arguments go to solvers.lowest_modes."""
+    h = h_frac pi / max(L).  omega / |k| is averaged over k and -k: on an even grid the
+    frequency set is not symmetric (the Nyquist label -N/2 has no +N/2), so omega(k) and
+    omega(-k) differ at O(|k|) and only their mean is even in k.  Keyword arguments go to
+    solvers.lowest_modes."""
     d = np.asarray(d, dtype=np.float64) / np.linalg.norm(d)
     h = h_frac * np.pi / max(rve.L)
-    w = lowest_modes(rve, [h * d, 2 * h * d], 3, **kw)
-    c1 = np.sort(w[0]) / h
-    c2 = np.sort(w[1]) / (2 * h)
+    w = lowest_modes(rve, [h * d, -h * d, 2 * h * d, -2 * h * d], 3, **kw)
+    c1 = (np.sort(w[0]) + np.sort(w[1])) / (2 * h)
+    c2 = (np.sort(w[2]) + np.sort(w[3])) / (4 * h)
     return (4 * c1 - c2) / 3
 
 
@@ -150,3 +164,24 @@ def mode_fields(rve, k, U):
     rot = np.exp(-1j * phi)[..., None, None, None, None]
     eps = ifft3(1j * ops.strain(U))
     return u * rot, eps * rot, phi
+
+
+def effective_stiffness(rve, tol=1e-12):
+    """6 x 6 Voigt effective stiffness (engineering shear) by static homogenization."""
+    ops = Operators(rve, np.zeros(3))
+    n = ops.n
+    Cf = ops.C_field                                               # (N0, N1, N2, 6, 6)
+    Ceff = np.zeros((6, 6))
+    for j in range(6):
+        E = np.zeros(6)
+        E[j] = 1.0
+        s0 = np.moveaxis(Cf @ E, -1, 0).astype(np.complex128)      # (6, N0, N1, N2), C(x) E
+        b = 1j * ops.divergence(fft3(s0))
+        u, _, _ = pcg(ops, b, tol)
+        eps = ifft3(1j * ops.strain(u))                            # (6, N0, N1, N2)
+        # on an even grid the fluctuation is not real (the Nyquist label -N/2 has no +N/2);
+        # the physical tensor is the real part of the mean stress
+        tot = np.moveaxis(eps.real, 0, -1) + E
+        sig = np.einsum("xyzab,xyzb->xyza", Cf, tot)
+        Ceff[:, j] = sig.reshape(-1, 6).mean(axis=0)
+    return 0.5 * (Ceff + Ceff.T)

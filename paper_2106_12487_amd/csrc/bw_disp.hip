@@ -184,10 +184,14 @@ extern "C" int bw_long_wave_speeds(bw_rve* r, const double dir[3], double h_frac
     unit_direction(dir, d);
     const double Lmax = std::max({r->L[0], r->L[1], r->L[2]});
     const double h = h_frac * M_PI / Lmax;
-    double ks[6];
+    // k = h d, -h d, 2h d, -2h d: the mean of omega over +-k is even in k (on an even
+    // grid the frequency set alone is not, the Nyquist label -N/2 having no +N/2)
+    double ks[12];
     for (int a = 0; a < 3; ++a) {
       ks[a] = h * d[a];
-      ks[3 + a] = 2 * h * d[a];
+      ks[3 + a] = -h * d[a];
+      ks[6 + a] = 2 * h * d[a];
+      ks[9 + a] = -2 * h * d[a];
     }
     bw_eig_opts o;
     std::memset(&o, 0, sizeof(o));
@@ -195,12 +199,14 @@ extern "C" int bw_long_wave_speeds(bw_rve* r, const double dir[3], double h_frac
     o.warm_start = 1;
     o.tol_omega = tol_omega > 0 ? tol_omega : (r->precision == BW_FP64 ? 1e-10 : 1e-8);
     o.tol_lin = r->precision == BW_FP64 ? std::min(1e-10, 0.1 * o.tol_omega) : 1e-6;
-    double om[6];
-    const int code = bw_lowest_modes(r, ks, 2, 3, &o, om, nullptr, nullptr, nullptr, stream);
+    double om[12];
+    const int code = bw_lowest_modes(r, ks, 4, 3, &o, om, nullptr, nullptr, nullptr, stream);
     if (code < 0) return code;
-    std::sort(om, om + 3);
-    std::sort(om + 3, om + 6);
-    for (int i = 0; i < 3; ++i) c_host[i] = (4.0 * om[i] / h - om[3 + i] / (2.0 * h)) / 3.0;
+    for (int j = 0; j < 4; ++j) std::sort(om + 3 * j, om + 3 * j + 3);
+    for (int i = 0; i < 3; ++i) {
+      const double c1 = (om[i] + om[3 + i]) / (2.0 * h), c2 = (om[6 + i] + om[9 + i]) / (4.0 * h);
+      c_host[i] = (4.0 * c1 - c2) / 3.0;
+    }
     return code;
   } catch (const Error& e) {
     set_error(e.msg);

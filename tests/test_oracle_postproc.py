@@ -186,3 +186,50 @@ def test_mode_fields_strain_of_trigonometric_displacement():
     e13 = 1j * k[2] * w[0]
     for got, ref in ((eps[0, 0], e11), (eps[0, 1], e22), (eps[0, 5], e12), (eps[0, 4], e13), (eps[0, 2], 0 * x)):
         assert np.abs(got - ref).max() <= 1e-12 * g
+
+
+def test_effective_stiffness_homogeneous_is_C():
+    ni = inputs.NI
+    rve = inputs.homogeneous((4, 4, 4), (L, L, L), inputs.rotate_voigt(ni["C"], inputs.haar_rotations(
+        np.array([[0.3, 0.6, 0.1]]))[0]), ni["rho"])
+    C = inputs.c21_to_voigt(rve.C21[0])
+    np.testing.assert_allclose(postproc.effective_stiffness(rve), C, atol=1e-9 * np.abs(C).max())
+
+
+def test_effective_stiffness_laminate_backus():
+    """Epoxy/carbon layers normal to x (equal thickness): Backus averages.
+    C11 = 1/<1/M>, C12 = C13 = <lam/M>/<1/M>, C22 = C33 = <M - lam^2/M> + <lam/M>^2/<1/M>,
+    C23 = <lam - lam^2/M> + <lam/M>^2/<1/M>, C44 = <mu>, C55 = C66 = 1/<1/mu>."""
+    ep, ca = inputs.EPOXY, inputs.CARBON
+    rve = inputs.bilayer(8, L, ep, ca)
+    Ce = postproc.effective_stiffness(rve)
+    M = np.array([ep["C"][0, 0], ca["C"][0, 0]])
+    lam = np.array([ep["C"][0, 1], ca["C"][0, 1]])
+    mu = np.array([ep["C"][3, 3], ca["C"][3, 3]])
+    a = lambda v: float(np.mean(v))
+    ref = {(0, 0): 1 / a(1 / M), (0, 1): a(lam / M) / a(1 / M), (0, 2): a(lam / M) / a(1 / M),
+           (1, 1): a(M - lam ** 2 / M) + a(lam / M) ** 2 / a(1 / M),
+           (2, 2): a(M - lam ** 2 / M) + a(lam / M) ** 2 / a(1 / M),
+           (1, 2): a(lam - lam ** 2 / M) + a(lam / M) ** 2 / a(1 / M),
+           (3, 3): a(mu), (4, 4): 1 / a(1 / mu), (5, 5): 1 / a(1 / mu)}
+    for (i, j), v in ref.items():
+        assert abs(Ce[i, j] - v) <= 1e-9 * v, (i, j, Ce[i, j], v)
+
+
+def test_effective_stiffness_within_voigt_reuss_and_matches_long_wave_speeds():
+    """The long-wave limit of the Bloch problem is the static homogenization of the same
+    discretization: rho_bar c^2 are the Christoffel eigenvalues of C_eff.  On an odd grid
+    (a symmetric frequency set, real fields) the two agree to the extrapolation error."""
+    rve = inputs.polycrystal((5, 5, 5), (L, L, L), 6, 94, 2)
+    Ce = postproc.effective_stiffness(rve)
+    ops = Operators(rve, np.zeros(3))
+    C = ops.C_field.reshape(-1, 6, 6)
+    CV, CR = C.mean(axis=0), np.linalg.inv(np.linalg.inv(C).mean(axis=0))
+    assert np.linalg.eigvalsh(CV - Ce).min() > -1e-9 * np.abs(CV).max()
+    assert np.linalg.eigvalsh(Ce - CR).min() > -1e-9 * np.abs(CV).max()
+    rho = float(np.mean(rve.rho[rve.grain_map]))
+    for d in ([1, 0, 0], [1, 1, 0], [0.3, -0.5, 0.8]):
+        dn = np.array(d, dtype=float) / np.linalg.norm(d)
+        c = postproc.long_wave_speeds(rve, d, method="dense")
+        ref = np.sqrt(np.sort(np.linalg.eigvalsh(_christoffel(Ce, dn))) / rho)
+        np.testing.assert_allclose(c, ref, rtol=3e-8)
