@@ -489,6 +489,7 @@ extern "C" int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3]
     r->G = n_grains;
     r->precision = precision;
     BW_HIP(hipGetDevice(&r->device));
+    BW_HIP(hipDeviceGetAttribute(&r->ncu, hipDeviceAttributeMultiprocessorCount, r->device));
     // volume averages (Sec. 3.3: C0 = volume-averaged stiffness)
     double rs = 0;
     for (int i = 0; i < 21; ++i) r->C0_si[i] = 0;

@@ -449,9 +449,10 @@ __global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, l
 // each): the butterflies of one overlap the LDS latency of the other.  The
 // fence before the writes keeps them behind the reads of the previous exchange
 // in the same buffers.
-template <typename T, bool INV, class Slot>
-__device__ __forceinline__ void fft64_dit_pair(cplx<T> (&a)[8], cplx<T> (&b)[8], cplx<T>* bufa, cplx<T>* bufb,
-                                               const Slot& slot, int j, const cplx<T> (&w)[1][8]) {
+// twf(m): twiddle of register m in pass 1.
+template <typename T, bool INV, class Slot, class TwF>
+__device__ __forceinline__ void fft64_pair(cplx<T> (&a)[8], cplx<T> (&b)[8], cplx<T>* bufa, cplx<T>* bufb,
+                                           const Slot& slot, int j, const TwF& twf) {
   using F = RegFFT<64>;
   using V = cplx<T>;
   dft_pass<64, 0, INV>(a);
@@ -472,21 +473,34 @@ __device__ __forceinline__ void fft64_dit_pair(cplx<T> (&a)[8], cplx<T> (&b)[8],
       a[m] = xa;
       b[m] = xb;
     } else {
-      a[m] = INV ? cmulc(xa, w[0][m]) : cmul(xa, w[0][m]);
-      b[m] = INV ? cmulc(xb, w[0][m]) : cmul(xb, w[0][m]);
+      const V t = twf(m);
+      a[m] = INV ? cmulc(xa, t) : cmul(xa, t);
+      b[m] = INV ? cmulc(xb, t) : cmul(xb, t);
     }
   }
   dft_pass<64, 1, INV>(a);
   dft_pass<64, 1, INV>(b);
 }
+template <typename T, bool INV, class Slot>
+__device__ __forceinline__ void fft64_dit_pair(cplx<T> (&a)[8], cplx<T> (&b)[8], cplx<T>* bufa, cplx<T>* bufb,
+                                               const Slot& slot, int j, const cplx<T> (&w)[1][8]) {
+  fft64_pair<T, INV>(a, b, bufa, bufb, slot, j, [&](int m) { return w[0][m]; });
+}
 
 // ---------------------------------------------------------------------------
-// Plane pass for n0 = n1 = 64 on the transposed work layout: one workgroup
-// per (vector, i2) takes the 64 x 64 (i0, i1) plane of all six strain
-// components, inverse 2D FFT (axis 1 then axis 0, register transforms with a
-// transposition through LDS between them), stiffness contraction, forward 2D
-// FFT, and writes the stress back in place: the three middle passes of K in one
-// read and one write of the work array.
+// Plane pass for n0 = n1 = 64 on the transposed work layout: a workgroup takes
+// the 64 x 64 (i0, i1) planes of all six strain components, one (vector, i2)
+// plane after another: inverse 2D FFT (axis 1 then axis 0, register transforms
+// with a transposition through LDS between them), stiffness contraction,
+// forward 2D FFT, and the stress written back in place: the three middle
+// passes of K in one read and one write of the work array.
+//
+// One workgroup per CU holds a plane in registers (two planes would not fit the
+// register file).  The workgroups are persistent: plane p = blockIdx.x,
+// blockIdx.x + gridDim.x, ... (planes of inactive vectors skipped), and as soon
+// as a component pair of plane p is stored, the same registers receive that
+// pair of the next plane, so the loads of the next plane overlap the
+// transforms of this one.
 // ---------------------------------------------------------------------------
 constexpr int PLANE_NT = 512;       // 64 lines x 8 threads
 // Transposition slot of (i0, i1): row i0, column i1 XOR a swizzle of i0's low
@@ -498,82 +512,126 @@ __device__ __forceinline__ int plane_tslot(int i0, int i1) {
   return i0 * 64 + (i1 ^ f);
 }
 // The two axes have the same length, so one twiddle set serves both.
-template <typename T, int PCG = 0>
-__global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W, int n2, long nvox,
+// CL: the stiffness table (G <= PLANE_CL_MAX grains) is staged in LDS; the
+// grain indices of a plane are loaded when its transforms start, so neither
+// load is waited for in the contraction.
+constexpr int PLANE_CL_MAX = 256;
+template <typename T, int PCG = 0, bool CL = false>
+__global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W, int n2, int nplanes, long nvox,
                                                          const uint16_t* __restrict__ gmapT, const T* __restrict__ Ctab,
-                                                         T scale, const cplx<T>* __restrict__ tw,
+                                                         int ngrains, T scale, const cplx<T>* __restrict__ tw,
                                                          const int* __restrict__ active) {
   using V = cplx<T>;
-  using F = RegFFT<64>;
   constexpr int NB = 64 * (64 + 8);   // 64 lines at the skewed row pitch (FFT exchanges, wavefront-local)
   __shared__ V lds[2][NB];
   __shared__ V tr[2][64 * 64];        // transpositions of a pair of components (workgroup-wide)
-  const int v = blockIdx.x / n2;
-  if (active && !active[v]) return;
-  const int i2 = blockIdx.x - v * n2;
+  __shared__ T cl[CL ? PLANE_CL_MAX * 21 : 1];
+  // the next plane of this workgroup at or after q whose vector is active (uniform)
+  const auto next_plane = [&](int q) {
+    while (q < nplanes && active && !active[q / n2]) q += gridDim.x;
+    return q;
+  };
+  int p = next_plane(blockIdx.x);
+  if (p >= nplanes) return;
   const int tid = threadIdx.x;
-  const int line = tid >> 3, j = tid & 7;
+  if (CL)   // with the scale folded in; visible after the first barrier
+    for (int i = tid; i < ngrains * 21; i += PLANE_NT) cl[i] = Ctab[i] * scale;
+  const T* __restrict__ Cg = CL ? cl : Ctab;
   V w[1][8];
-  load_twr<T, 64>(w, tw, j);
-  V* Wv = W + (size_t)v * 6 * nvox + (size_t)i2 * 4096;
-  const RowSlotR<64> slot{line * (64 + 8)};
+  load_twr<T, 64>(w, tw, tid & 7);
+  const auto plane_ptr = [&](int q) {
+    const int v = q / n2;
+    return W + (size_t)v * 6 * nvox + (size_t)(q - v * n2) * 4096;
+  };
   V x[6][8];
+  {
+    const int line = tid >> 3, j = tid & 7;
+    const V* Wv = plane_ptr(p);
 #pragma unroll
-  for (int c = 0; c < 6; ++c)
+    for (int c = 0; c < 6; ++c)
 #pragma unroll
-    for (int m = 0; m < 8; ++m) x[c][m] = Wv[(size_t)c * nvox + line * 64 + j + 8 * m];  // (i0 = line, i1 = j + 8m)
-#pragma unroll
-  for (int c = 0; c < 6; c += 2) {
-    fft64_dit_pair<T, true>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i1
-    if (c > 0) __syncthreads();   // every wavefront has read the previous pair's transposition
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      tr[0][plane_tslot(line, j + 8 * m)] = x[c][m];
-      tr[1][plane_tslot(line, j + 8 * m)] = x[c + 1][m];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {                    // (i0 = j + 8m, i1 = line)
-      x[c][m] = tr[0][plane_tslot(j + 8 * m, line)];
-      x[c + 1][m] = tr[1][plane_tslot(j + 8 * m, line)];
-    }
-    fft64_dit_pair<T, true>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i0
+      for (int m = 0; m < 8; ++m) x[c][m] = Wv[(size_t)c * nvox + line * 64 + j + 8 * m];  // (i0 = line, i1 = j + 8m)
   }
+  for (;;) {
+    // the lane's position, opaque to the compiler: every address below is
+    // recomputed per plane instead of being hoisted out of the loop, which would
+    // hold some hundred registers for the whole loop
+    int line = tid >> 3, j = tid & 7;
+    asm volatile("" : "+v"(line), "+v"(j));
+    const RowSlotR<64> slot{line * (64 + 8)};
+    const int pn = next_plane(p + gridDim.x);
+    const int i2 = p % n2;
+    V* Wv = plane_ptr(p);
+    int gm[8];                    // grain of point (i0 = j + 8m, i1 = line)
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const int g = gmapT[(size_t)i2 * 4096 + (j + 8 * m) * 64 + line];
-    T cg[21];
+    for (int m = 0; m < 8; ++m) gm[m] = gmapT[(size_t)i2 * 4096 + (j + 8 * m) * 64 + line];
 #pragma unroll
-    for (int i = 0; i < 21; ++i) cg[i] = Ctab[g * 21 + i];
-    V e[6], sg[6];
+    for (int c = 0; c < 6; c += 2) {
+      fft64_dit_pair<T, true>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i1
+      __syncthreads();            // every wavefront has read the previous transposition
 #pragma unroll
-    for (int c = 0; c < 6; ++c) e[c] = x[c][m];
-    contract6<T, V>(cg, e, sg, scale);
+      for (int m = 0; m < 8; ++m) {
+        tr[0][plane_tslot(line, j + 8 * m)] = x[c][m];
+        tr[1][plane_tslot(line, j + 8 * m)] = x[c + 1][m];
+      }
+      __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 6; ++c) x[c][m] = sg[c];
-    asm volatile("" ::: "memory");
-  }
-#pragma unroll
-  for (int c = 0; c < 6; c += 2) {
-    fft64_dit_pair<T, false>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i0
-    __syncthreads();              // every wavefront has read the previous transposition
+      for (int m = 0; m < 8; ++m) {                    // (i0 = j + 8m, i1 = line)
+        x[c][m] = tr[0][plane_tslot(j + 8 * m, line)];
+        x[c + 1][m] = tr[1][plane_tslot(j + 8 * m, line)];
+      }
+      fft64_dit_pair<T, true>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i0
+    }
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      tr[0][plane_tslot(j + 8 * m, line)] = x[c][m];
-      tr[1][plane_tslot(j + 8 * m, line)] = x[c + 1][m];
-    }
-    __syncthreads();
+      T cg[21];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {                    // (i0 = line, i1 = j + 8m)
-      x[c][m] = tr[0][plane_tslot(line, j + 8 * m)];
-      x[c + 1][m] = tr[1][plane_tslot(line, j + 8 * m)];
-    }
-    fft64_dit_pair<T, false>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i1
+      for (int i = 0; i < 21; ++i) cg[i] = Cg[gm[m] * 21 + i];
+      V e[6], sg[6];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      Wv[(size_t)c * nvox + line * 64 + j + 8 * m] = x[c][m];
-      Wv[(size_t)(c + 1) * nvox + line * 64 + j + 8 * m] = x[c + 1][m];
+      for (int c = 0; c < 6; ++c) e[c] = x[c][m];
+      contract6<T, V>(cg, e, sg, CL ? T(1) : scale);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) x[c][m] = sg[c];
+      // one point's stiffness at a time: the scheduler would otherwise issue the
+      // loads of all eight points at once and spill them
+      __builtin_amdgcn_sched_barrier(0);
     }
+    // inverse 2D FFT and store, pair by pair, each pair followed by the loads of
+    // that pair of the next plane into the same registers.  After the last plane
+    // the loads read plane 0 (a valid address shared by all workgroups, so they
+    // hit in L2) and the values are not used: a load that is always issued keeps
+    // the stored and the loaded values from being live at once.
+    const V* Wn = plane_ptr(pn < nplanes ? pn : 0);
+#pragma unroll
+    for (int c = 0; c < 6; c += 2) {
+      fft64_dit_pair<T, false>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i0
+      __syncthreads();            // every wavefront has read the previous transposition
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        tr[0][plane_tslot(j + 8 * m, line)] = x[c][m];
+        tr[1][plane_tslot(j + 8 * m, line)] = x[c + 1][m];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {                    // (i0 = line, i1 = j + 8m)
+        x[c][m] = tr[0][plane_tslot(line, j + 8 * m)];
+        x[c + 1][m] = tr[1][plane_tslot(line, j + 8 * m)];
+      }
+      fft64_dit_pair<T, false>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i1
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        Wv[(size_t)c * nvox + line * 64 + j + 8 * m] = x[c][m];
+        Wv[(size_t)(c + 1) * nvox + line * 64 + j + 8 * m] = x[c + 1][m];
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        x[c][m] = Wn[(size_t)c * nvox + line * 64 + j + 8 * m];
+        x[c + 1][m] = Wn[(size_t)(c + 1) * nvox + line * 64 + j + 8 * m];
+      }
+    }
+    if (pn >= nplanes) break;
+    p = pn;
   }
 }
 

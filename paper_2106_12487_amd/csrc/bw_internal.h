@@ -131,6 +131,7 @@ struct bw_rve {
   int G;
   int precision;
   int device;
+  int ncu = 0;      // compute units of the device (persistent launches)
   // nondimensionalization: C' = C / Cref, q' = q * ell, rho' = rho / rho_bar
   double Cref, ell, rho_bar;
   double rho_min_s;  // smallest scaled density (bounds the M^-1 norm)

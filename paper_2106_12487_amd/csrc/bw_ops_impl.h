@@ -923,12 +923,26 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   }
   if (plane) {
     if constexpr (std::is_same<T, float>::value) {   // the plane kernel exists for FP32 only
-      if (active)
-        BW_LAUNCH("k_plane_contract_pcg", 0, (k_plane64<T, 1>), dim3(nvec * g.n2), dim3(PLANE_NT), 0, s, W, g.n2,
-                  g.nvox, r->d_gmapT, ctab<T>(r), (T)(1.0 / (double)g.nvox), twiddles<T>(r, 0), active);
-      else
-        BW_LAUNCH("k_plane_contract", nvec, (k_plane64<T, 0>), dim3(nvec * g.n2), dim3(PLANE_NT), 0, s, W, g.n2,
-                  g.nvox, r->d_gmapT, ctab<T>(r), (T)(1.0 / (double)g.nvox), twiddles<T>(r, 0), active);
+      // persistent: one workgroup per CU (the kernel's LDS and registers admit one)
+      const int nplanes = nvec * g.n2;
+      const int grid = std::min(nplanes, std::max(r->ncu, 1));
+      const T sc = (T)(1.0 / (double)g.nvox);
+      const bool cl = r->G <= PLANE_CL_MAX;
+      if (active) {
+        if (cl)
+          BW_LAUNCH("k_plane_contract_pcg", 0, (k_plane64<T, 1, true>), dim3(grid), dim3(PLANE_NT), 0, s, W, g.n2,
+                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active);
+        else
+          BW_LAUNCH("k_plane_contract_pcg", 0, (k_plane64<T, 1, false>), dim3(grid), dim3(PLANE_NT), 0, s, W, g.n2,
+                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active);
+      } else {
+        if (cl)
+          BW_LAUNCH("k_plane_contract", nvec, (k_plane64<T, 0, true>), dim3(grid), dim3(PLANE_NT), 0, s, W, g.n2,
+                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active);
+        else
+          BW_LAUNCH("k_plane_contract", nvec, (k_plane64<T, 0, false>), dim3(grid), dim3(PLANE_NT), 0, s, W, g.n2,
+                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active);
+      }
     }
   } else {
     launch_middle<T, 0>(r, W, nvec, (T)(1.0 / (double)g.nvox), active, s);

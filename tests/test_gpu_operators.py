@@ -133,6 +133,51 @@ def test_pcg_on_register_fft_axes(lib, n, prec):
         assert abs(int(it[0]) - it_o) <= 1
 
 
+@pytest.mark.parametrize("grains,nz,nv", [(300, 4, 3), (12, 48, 6)])
+def test_plane_pass_grain_table_and_persistent_loop(lib, grains, nz, nv):
+    """n0 = n1 = 64 (FP32 plane pass): more grains than the stiffness table staged in
+    LDS holds (the table is read from global memory), and more planes than the device
+    has compute units (each workgroup takes several planes, loading the next while it
+    transforms the current one)."""
+    n = (64, 64, nz)
+    print(f"\n[case] plane pass n={n} grains={grains} nvec={nv}", flush=True)
+    rve = inputs.polycrystal(n, (L, L, L), grains, 91, 0)
+    k = np.array([0.35, -0.25, 0.15]) * np.pi / L
+    ops = Operators(rve, k)
+    R = lib.Rve.from_inputs(rve, 1)
+    u = _rand((nv, 3) + n, 12)
+    ud = _to_dev(u, 1)
+    y = _dev().empty_like(ud)
+    lib.bw_apply_K(R, k, ud, y)
+    _dev().cuda.synchronize()
+    assert _rel(y.cpu().numpy(), ops.apply_K(u)) <= TOL[1]
+    R.close()
+
+
+def test_pcg_batch_over_persistent_planes_matches_single_solves(lib):
+    """A PCG batch of 10 vectors on 64 x 64 x 32 (320 planes per plane pass, so workgroups
+    loop over planes and skip those of converged vectors) gives each vector the iterates
+    of its own single-vector solve."""
+    torch = _dev()
+    n = (64, 64, 32)
+    rve = inputs.polycrystal(n, (L, L, L), 9, 90, 0)
+    k = np.array([0.4, 0.1, -0.3]) * np.pi / L
+    b = _rand((10, 3) + n, 13)
+    b[3:] *= np.linspace(0.5, 2.0, 7)[:, None, None, None, None]
+    R = lib.Rve.from_inputs(rve, 1)
+    bd = _to_dev(b, 1)
+    xd = torch.zeros_like(bd)
+    code, it, rr = lib.bw_pcg_solve(R, k, bd, xd, 1e-6, 500)
+    assert code == 0 and np.all(rr <= 1e-6)
+    print(f"\n[case] pcg batch 64x64x32 iterations {it}", flush=True)
+    for v in range(10):
+        x1 = torch.zeros_like(bd[v:v + 1])
+        c1, it1, _ = lib.bw_pcg_solve(R, k, bd[v:v + 1].contiguous(), x1, 1e-6, 500)
+        assert c1 == 0 and int(it1[0]) == int(it[v])
+        assert _rel(xd[v].cpu().numpy(), x1[0].cpu().numpy()) <= 1e-6
+    R.close()
+
+
 def test_pcg_warm_start_and_gamma(lib):
     print("\n[case] pcg gamma", flush=True)
     torch = _dev()
