@@ -133,12 +133,12 @@ def test_pcg_on_register_fft_axes(lib, n, prec):
         assert abs(int(it[0]) - it_o) <= 1
 
 
-@pytest.mark.parametrize("grains,nz,nv", [(300, 4, 3), (12, 48, 6)])
+@pytest.mark.parametrize("grains,nz,nv", [(300, 4, 3), (200, 4, 3), (12, 48, 6), (150, 40, 7)])
 def test_plane_pass_grain_table_and_persistent_loop(lib, grains, nz, nv):
-    """n0 = n1 = 64 (FP32 plane pass): more grains than the stiffness table staged in
-    LDS holds (the table is read from global memory), and more planes than the device
-    has compute units (each workgroup takes several planes, loading the next while it
-    transforms the current one)."""
+    """n0 = n1 = 64 (FP32 plane pass): up to 256 grains the stiffness table is staged in
+    LDS, beyond it is read from global memory.  With more planes than the device has
+    compute units, each workgroup takes several planes, loading the next while it
+    transforms the current one."""
     n = (64, 64, nz)
     print(f"\n[case] plane pass n={n} grains={grains} nvec={nv}", flush=True)
     rve = inputs.polycrystal(n, (L, L, L), grains, 91, 0)
