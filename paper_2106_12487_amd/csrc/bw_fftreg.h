@@ -597,40 +597,45 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
       // loads of all eight points at once and spill them
       __builtin_amdgcn_sched_barrier(0);
     }
-    // inverse 2D FFT and store, pair by pair, each pair followed by the loads of
-    // that pair of the next plane into the same registers.  After the last plane
-    // the loads read plane 0 (a valid address shared by all workgroups, so they
-    // hit in L2) and the values are not used: a load that is always issued keeps
-    // the stored and the loaded values from being live at once.
-    const V* Wn = plane_ptr(pn < nplanes ? pn : 0);
+    // inverse 2D FFT and store, pair by pair; PF: each pair followed by the loads
+    // of that pair of the next plane into the same registers (two instances, so
+    // that the stored and the loaded values are never live at once)
+    const auto finish = [&](auto PF, const V* Wn) {
 #pragma unroll
-    for (int c = 0; c < 6; c += 2) {
-      fft64_dit_pair<T, false>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i0
-      __syncthreads();            // every wavefront has read the previous transposition
+      for (int c = 0; c < 6; c += 2) {
+        fft64_dit_pair<T, false>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i0
+        __syncthreads();          // every wavefront has read the previous transposition
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        tr[0][plane_tslot(j + 8 * m, line)] = x[c][m];
-        tr[1][plane_tslot(j + 8 * m, line)] = x[c + 1][m];
+        for (int m = 0; m < 8; ++m) {
+          tr[0][plane_tslot(j + 8 * m, line)] = x[c][m];
+          tr[1][plane_tslot(j + 8 * m, line)] = x[c + 1][m];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {                  // (i0 = line, i1 = j + 8m)
+          x[c][m] = tr[0][plane_tslot(line, j + 8 * m)];
+          x[c + 1][m] = tr[1][plane_tslot(line, j + 8 * m)];
+        }
+        fft64_dit_pair<T, false>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i1
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          Wv[(size_t)c * nvox + line * 64 + j + 8 * m] = x[c][m];
+          Wv[(size_t)(c + 1) * nvox + line * 64 + j + 8 * m] = x[c + 1][m];
+        }
+        if (decltype(PF)::value) {
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            x[c][m] = Wn[(size_t)c * nvox + line * 64 + j + 8 * m];
+            x[c + 1][m] = Wn[(size_t)(c + 1) * nvox + line * 64 + j + 8 * m];
+          }
+        }
       }
-      __syncthreads();
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {                    // (i0 = line, i1 = j + 8m)
-        x[c][m] = tr[0][plane_tslot(line, j + 8 * m)];
-        x[c + 1][m] = tr[1][plane_tslot(line, j + 8 * m)];
-      }
-      fft64_dit_pair<T, false>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i1
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        Wv[(size_t)c * nvox + line * 64 + j + 8 * m] = x[c][m];
-        Wv[(size_t)(c + 1) * nvox + line * 64 + j + 8 * m] = x[c + 1][m];
-      }
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        x[c][m] = Wn[(size_t)c * nvox + line * 64 + j + 8 * m];
-        x[c + 1][m] = Wn[(size_t)(c + 1) * nvox + line * 64 + j + 8 * m];
-      }
+    };
+    if (pn >= nplanes) {
+      finish(std::false_type{}, Wv);
+      break;
     }
-    if (pn >= nplanes) break;
+    finish(std::true_type{}, plane_ptr(pn));
     p = pn;
   }
 }
