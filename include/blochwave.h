@@ -25,6 +25,9 @@
  * Stiffness  per grain, 21 entries of the 6x6 Voigt matrix (engineering shear
  *            strain [e11, e22, e33, 2e23, 2e13, 2e12]), upper triangle,
  *            row-major, in the sample frame.
+ * Counts     a zero count (nvec, nrhs, nk, nmodes where the call allows 0) is a
+ *            no-op that returns 0; the buffers it would address may then be
+ *            NULL.
  * Memory     pointers named *_host are host memory; all vector arguments are
  *            device memory owned by the caller.  The library owns only what
  *            bw_create_rve allocates (freed by bw_destroy_rve) plus cached
@@ -186,7 +189,9 @@ int bw_pcg_solve(bw_rve* rve, const double k_host[3], const void* b, void* x, in
  * M-orthogonal complement.  BW_LANCZOS advances one Krylov vector per wave
  * vector, so an exactly degenerate eigenvalue (homogeneous cells, symmetric
  * cells at symmetric k) is found once; BW_SUBSPACE (a block method) resolves
- * such multiplicities.  Synchronizes `stream`. */
+ * such multiplicities.  BW_LANCZOS needs ncv <= 3 n0 n1 n2 - 3 (the dimension
+ * of the Krylov space without the rigid translations) and returns BW_EINVAL on
+ * smaller cells.  Synchronizes `stream`. */
 int bw_lowest_modes(bw_rve* rve, const double* k_list_host, int32_t nk, int32_t nmodes,
                     const bw_eig_opts* opts, double* omega_host, double* err_host,
                     void* modes, bw_stats* stats_host, void* stream);

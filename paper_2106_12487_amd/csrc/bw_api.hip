@@ -619,10 +619,11 @@ extern "C" int bw_rve_info(const bw_rve* r, int32_t n[3], int32_t* precision, do
 
 extern "C" int bw_apply_K(bw_rve* r, const double k[3], const void* u, void* y, int32_t nvec, void* stream) {
   BW_GUARD_BEGIN
-  BW_REQUIRE(r && k && u && y, BW_EINVAL, "null argument");
+  BW_REQUIRE(r && k, BW_EINVAL, "null argument");
   BW_REQUIRE(nvec >= 0, BW_EINVAL, "nvec < 0");
-  BW_REQUIRE(u != y, BW_EINVAL, "u and y must not alias");
   if (nvec == 0) return BW_OK;
+  BW_REQUIRE(u && y, BW_EINVAL, "null argument");
+  BW_REQUIRE(u != y, BW_EINVAL, "u and y must not alias");
   hipStream_t s = (hipStream_t)stream;
   const double* q = qtab_for(r, k, nvec, s);
   if (r->precision == BW_FP64) {
@@ -639,10 +640,11 @@ extern "C" int bw_apply_K(bw_rve* r, const double k[3], const void* u, void* y, 
 
 extern "C" int bw_apply_M(bw_rve* r, const void* u, void* y, int32_t nvec, void* stream) {
   BW_GUARD_BEGIN
-  BW_REQUIRE(r && u && y, BW_EINVAL, "null argument");
+  BW_REQUIRE(r, BW_EINVAL, "null argument");
   BW_REQUIRE(nvec >= 0, BW_EINVAL, "nvec < 0");
-  BW_REQUIRE(u != y, BW_EINVAL, "u and y must not alias");
   if (nvec == 0) return BW_OK;
+  BW_REQUIRE(u && y, BW_EINVAL, "null argument");
+  BW_REQUIRE(u != y, BW_EINVAL, "u and y must not alias");
   hipStream_t s = (hipStream_t)stream;
   if (r->precision == BW_FP64) {
     auto* W = ws<double>(r).work((size_t)nvec * 6 * r->g.nvox);
@@ -658,9 +660,10 @@ extern "C" int bw_apply_M(bw_rve* r, const void* u, void* y, int32_t nvec, void*
 
 extern "C" int bw_apply_P(bw_rve* r, const double k[3], const void* u, void* y, int32_t nvec, void* stream) {
   BW_GUARD_BEGIN
-  BW_REQUIRE(r && k && u && y, BW_EINVAL, "null argument");
+  BW_REQUIRE(r && k, BW_EINVAL, "null argument");
   BW_REQUIRE(nvec >= 0, BW_EINVAL, "nvec < 0");
   if (nvec == 0) return BW_OK;
+  BW_REQUIRE(u && y, BW_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)stream;
   const double* q = qtab_for(r, k, nvec, s);
   const double sc = 1.0 / K_scale(r);
@@ -794,11 +797,12 @@ static int pcg_entry(bw_rve* r, const double* k, const void* b, void* x, int nrh
 extern "C" int bw_pcg_solve(bw_rve* r, const double k[3], const void* b, void* x, int32_t nrhs, double rtol,
                             int32_t maxit, int32_t* iters, double* relres, void* stream) {
   BW_GUARD_BEGIN
-  BW_REQUIRE(r && k && b && x, BW_EINVAL, "null argument");
+  BW_REQUIRE(r && k, BW_EINVAL, "null argument");
   BW_REQUIRE(nrhs >= 0, BW_EINVAL, "nrhs < 0");
   BW_REQUIRE(rtol > 0 && rtol < 1, BW_EINVAL, "rtol must be in (0, 1)");
-  BW_REQUIRE(b != x, BW_EINVAL, "b and x must not alias");
   if (nrhs == 0) return BW_OK;
+  BW_REQUIRE(b && x, BW_EINVAL, "null argument");
+  BW_REQUIRE(b != x, BW_EINVAL, "b and x must not alias");
   if (maxit <= 0) maxit = 20000;
   hipStream_t s = (hipStream_t)stream;
   if (r->precision == BW_FP64) return pcg_entry<double>(r, k, b, x, nrhs, rtol, maxit, iters, relres, s);

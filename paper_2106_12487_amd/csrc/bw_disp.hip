@@ -375,12 +375,13 @@ void mode_fields(bw_rve* r, const double* k, int nm, const cplx<T>* Uh, cplx<T>*
 extern "C" int bw_mode_fields(bw_rve* r, const double k[3], int32_t nmodes, const void* modes, void* u_out,
                               void* eps_out, double* phase_host, void* stream) {
   try {
-    BW_REQUIRE(r && k && modes && u_out, BW_EINVAL, "null argument");
+    BW_REQUIRE(r && k, BW_EINVAL, "null argument");
     BW_REQUIRE(nmodes >= 0, BW_EINVAL, "nmodes < 0");
-    BW_REQUIRE(modes != u_out && (!eps_out || (eps_out != modes && eps_out != u_out)), BW_EINVAL,
-               "modes, u_out and eps_out must not alias");
     for (int a = 0; a < 3; ++a) BW_REQUIRE(std::isfinite(k[a]), BW_EINVAL, "non-finite wave vector");
     if (nmodes == 0) return BW_OK;
+    BW_REQUIRE(modes && u_out, BW_EINVAL, "null argument");
+    BW_REQUIRE(modes != u_out && (!eps_out || (eps_out != modes && eps_out != u_out)), BW_EINVAL,
+               "modes, u_out and eps_out must not alias");
     hipStream_t s = (hipStream_t)stream;
     if (r->precision == BW_FP64)
       mode_fields<double>(r, k, nmodes, (const cplx<double>*)modes, (cplx<double>*)u_out, (cplx<double>*)eps_out,

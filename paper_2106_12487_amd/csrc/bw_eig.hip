@@ -574,6 +574,11 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
   }
   const int m = o.ncv > 0 ? o.ncv : std::max(2 * nwmax + 1, 20);
   BW_REQUIRE(m <= GEIG_QMAX && m >= nwmax + 2, BW_EINVAL, "ncv must satisfy nmodes + 2 <= ncv <= 48");
+  // the Krylov space of K^-1 M (rigid translations removed) has at most 3 N - 3
+  // dimensions: a longer basis would break down and fill with rounding noise
+  BW_REQUIRE((long)m <= 3L * g.nvox - 3, BW_EINVAL,
+             "the Lanczos basis (ncv = " + std::to_string(m) +
+                 " vectors) exceeds the cell's degrees of freedom less 3; use the subspace method");
   const int kk = std::min({m - 1, nwmax + (m - nwmax) / 2, GRAM_QMAX});  // vectors kept at a restart
   const int qsel = std::min(m, nwmax + 2);                                // Ritz vectors refined in FP64
   Workspace<T>& w = wl<T>(r);
@@ -858,9 +863,14 @@ using namespace bw;
 extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int32_t nmodes, const bw_eig_opts* opts,
                                double* omega, double* err, void* modes, bw_stats* stats, void* stream) {
   try {
-    BW_REQUIRE(r && k_list && omega, BW_EINVAL, "null argument");
+    BW_REQUIRE(r, BW_EINVAL, "null argument");
     BW_REQUIRE(nk >= 0, BW_EINVAL, "nk < 0");
     BW_REQUIRE(nmodes >= 1, BW_EINVAL, "nmodes must be >= 1");
+    if (nk == 0) {
+      if (stats) std::memset(stats, 0, sizeof(*stats));
+      return BW_OK;
+    }
+    BW_REQUIRE(k_list && omega, BW_EINVAL, "null argument");
     BW_REQUIRE((long)nmodes <= 3 * r->g.nvox, BW_EINVAL, "more modes than degrees of freedom");
     EigOpts o{};
     if (opts) {

@@ -1,0 +1,82 @@
+"""Edge cases through the C ABI: empty batches (no vectors, right-hand sides, wave
+vectors or modes) are no-ops; the smallest cells (2 and 8 voxels) against the dense
+oracle; a Lanczos basis longer than a small cell's Krylov space is refused."""
+import numpy as np
+import pytest
+
+from oracle import solvers
+from oracle.operators import Operators
+from paper_2106_12487_amd import inputs
+
+pytestmark = pytest.mark.gpu
+L = inputs.L_MM
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_empty_batches_are_no_ops(lib, prec):
+    torch = _torch()
+    rve = inputs.polycrystal((8, 8, 8), (L, L, L), 4, 96, 0)
+    R = lib.Rve.from_inputs(rve, prec)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    e = torch.zeros((0, 3, 8, 8, 8), dtype=dt, device="cuda")
+    f = torch.zeros_like(e)
+    k = np.array([0.2, 0.1, 0.0]) * np.pi / L
+    print(f"\n[case] empty batches prec={prec}", flush=True)
+    lib.bw_apply_K(R, k, e, f)
+    lib.bw_apply_M(R, e, f)
+    lib.bw_apply_P(R, k, e, f)
+    code, it, rr = lib.bw_pcg_solve(R, k, e, f, 1e-6)
+    assert code == 0 and it.shape == (0,) and rr.shape == (0,)
+    for method, block in ((0, 8), (1, 0)):
+        w, err, code, st = lib.bw_lowest_modes(R, np.zeros((0, 3)), 4, method=method, block=block)
+        assert code == 0 and w.shape == (0, 4) and st["pcg_iterations"] == 0
+    assert lib.bw_mode_fields(R, k, e, f).shape == (0,)
+    _torch().cuda.synchronize()
+    R.close()
+
+
+def test_two_voxel_cell_matches_dense_oracle(lib):
+    """A 2 x 1 x 1 cell of two rotated Cu grains (6 degrees of freedom): off Gamma the
+    subspace method with a block of 5 gives the 4 lowest frequencies of the dense pencil;
+    Lanczos (a basis of at least 20 vectors) refuses the cell."""
+    rve = inputs.polycrystal((2, 1, 1), (L, L, L), 2, 86, 0)   # one voxel per grain
+    R = lib.Rve.from_inputs(rve, 0)
+    ks = np.array([[0.37 * np.pi / L, 0.0, 0.0], [0.2 * np.pi / L, 0.5 * np.pi / L, -0.3 * np.pi / L]])
+    w, err, code, _ = lib.bw_lowest_modes(R, ks, 4, method=0, block=5, tol_eig=1e-12, tol_lin=1e-12)
+    assert code == 0, lib.bw_last_error()
+    scale = np.sqrt(inputs.c21_to_voigt(rve.C21[0])[3, 3] / rve.rho[0]) * 2 * np.pi / L
+    for i, k in enumerate(ks):
+        lam, _ = solvers.dense_modes(Operators(rve, k), 4)
+        ref = np.sqrt(np.where(lam > 1e-12 * scale ** 2, lam, 0.0))   # rigid modes: rounding-level lam
+        print(f"\n[case] 2-voxel k#{i}: {w[i]} vs {ref}", flush=True)
+        assert np.abs(w[i] - ref).max() <= 1e-9 * scale
+    with pytest.raises(lib.BlochwaveError):
+        lib.bw_lowest_modes(R, ks[:1], 2, method=1)
+    R.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_eight_voxel_cell_lanczos_matches_dense_oracle(lib, prec):
+    """A 2 x 2 x 2 cell of three rotated Cu grains (24 degrees of freedom): Lanczos with its
+    default basis of 20 vectors (21 available without the rigid translations) gives the
+    6 lowest frequencies of the dense pencil."""
+    rve = inputs.polycrystal((2, 2, 2), (L, L, L), 3, 92, 0)
+    R = lib.Rve.from_inputs(rve, prec)
+    ks = np.array([[0.31 * np.pi / L, -0.12 * np.pi / L, 0.4 * np.pi / L], [0.0, 0.0, 0.0]])
+    w, err, code, _ = lib.bw_lowest_modes(R, ks, 6, method=1, tol_omega=1e-11 if prec == 0 else 5e-6,
+                                          tol_lin=1e-12 if prec == 0 else 1e-6)
+    assert code == 0, lib.bw_last_error()
+    scale = np.sqrt(inputs.c21_to_voigt(rve.C21[0])[3, 3] / rve.rho[0]) * 2 * np.pi / L
+    for i, k in enumerate(ks):
+        lam, _ = solvers.dense_modes(Operators(rve, k), 6)
+        ref = np.sqrt(np.where(lam > 1e-12 * scale ** 2, lam, 0.0))
+        print(f"\n[case] 8-voxel prec={prec} k#{i}: max abs diff / scale {np.abs(w[i] - ref).max() / scale:.2e}",
+              flush=True)
+        assert np.abs(w[i] - ref).max() <= (1e-9 if prec == 0 else 1e-5) * scale
+    R.close()
