@@ -254,13 +254,27 @@ def dispersion_post_arm(bw, rve_in, ks, tol_omega=5e-6):
         c, _ = bw.bw_long_wave_speeds(R, d)
         lw[name] = [round(float(v), 2) for v in c]
     t_lw = time.perf_counter() - t0
+    # static homogenization (six cell problems at k = 0): rho_bar c^2 along [100] against
+    # the long-wave speeds (the even grid's offset is ~1e-6)
+    bw.bw_effective_stiffness(R)                                        # warm-up (workspaces)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ce, it_h, code_h = bw.bw_effective_stiffness(R)
+    t_h = time.perf_counter() - t0
+    rho = float(np.mean(rve_in.rho[rve_in.grain_map]))
+    from paper_2106_12487_amd import inputs
+    T = inputs.voigt_to_tensor(Ce)
+    c_static = np.sqrt(np.sort(np.linalg.eigvalsh(T[:, 0, :, 0])) / rho)
     R.close()
     torch.cuda.empty_cache()
     return {"group_velocity_k_points_per_s": round(len(ks) / t_gv, 2), "modes": nm,
             "mode_fields_k_points_per_s": round(len(ks) / t_mf, 2),
             "acoustic_slopes_at_k1_m_per_s": [round(float(v), 2) for v in slopes[1, :3]],
             "long_wave_seconds_per_direction": round(t_lw / 3, 3), "long_wave_speeds_m_per_s": lw,
-            "status": int(code)}
+            "homogenization_seconds": round(t_h, 3), "homogenization_pcg_iterations": [int(v) for v in it_h],
+            "static_speeds_100_m_per_s": [round(float(v), 2) for v in c_static],
+            "status": int(code), "homogenization_status": int(code_h)}
+
 
 
 def fibre_arm(bw, tol_omega=5e-6):

@@ -363,6 +363,24 @@ int bw_long_wave_speeds(bw_rve* rve, const double dir[3], double h_frac, double 
 int bw_mode_fields(bw_rve* rve, const double k_host[3], int32_t nmodes, const void* modes, void* u_out,
                    void* eps_out, double* phase_host, void* stream);
 
+/* Effective stiffness of the cell by static homogenization, the long-wave
+ * limit of the Bloch problem (Sec. 5.1: the long-wave group velocity is the
+ * speed of the equivalent homogeneous medium).  For each unit macro strain E_j
+ * (Voigt order 11, 22, 33, 23, 13, 12, engineering shear) the periodic
+ * fluctuation u solves K(0) u^ = i B(xi)^H F[C(x) E_j] by the preconditioned CG
+ * of bw_pcg_solve (Sec. 3.3, Algorithm "InvA"); column j of the result is the
+ * volume mean of C(x) (E_j + eps(u)) with eps(u) = F^-1[i B(xi) u^] (its real
+ * part: on an even grid the Nyquist label -n/2 has no partner and the
+ * fluctuation is not real).  rho_bar c^2 of bw_long_wave_speeds are the
+ * Christoffel eigenvalues of this tensor up to the discretization's
+ * even-grid offset.  rtol: relative residual of the six cell problems (0 ->
+ * 1e-12 for BW_FP64, 1e-6 for BW_MIXED); maxit <= 0 -> 20000.  C66_host:
+ * float64[36], row-major, symmetrized, Pa; iters_host: optional int32[6].
+ * Returns BW_ENOTCONV (with C66_host filled) when a cell problem missed rtol.
+ * Synchronizes `stream`. */
+int bw_effective_stiffness(bw_rve* rve, double rtol, int32_t maxit, double* C66_host, int32_t* iters_host,
+                           void* stream);
+
 /* Diagnostics: a plain streaming copy of `bytes` (a multiple of 16, below
  * 2^39; 16-byte aligned device buffers, not overlapping) on `stream`, the
  * reference kernel for calibrating memory-traffic counters (its algorithmic

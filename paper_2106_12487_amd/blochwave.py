@@ -88,6 +88,7 @@ _SIGS = {
     "bw_group_velocity": (_I, [_P, _DP, _DP, _I, _P, _DP, _D, _DP, _P]),
     "bw_long_wave_speeds": (_I, [_P, _DP, _D, _D, _DP, _P]),
     "bw_mode_fields": (_I, [_P, _DP, _I, _P, _P, _P, _DP, _P]),
+    "bw_effective_stiffness": (_I, [_P, ctypes.c_double, _I, _DP, _IP, _P]),
 }
 
 
@@ -323,6 +324,16 @@ def bw_long_wave_speeds(rve: Rve, direction, h_frac: float = 0.02, tol_omega: fl
     code = _check(lib().bw_long_wave_speeds(rve.handle, d_p, float(h_frac), float(tol_omega),
                                             out.ctypes.data_as(_DP), _stream(stream)))
     return out, code
+
+
+def bw_effective_stiffness(rve: Rve, rtol: float = 0.0, maxit: int = 0, stream=None):
+    """(6 x 6 Voigt effective stiffness by static homogenization (Pa), PCG iterations of the
+    six cell problems, status)."""
+    C = np.zeros(36)
+    it = np.zeros(6, dtype=np.int32)
+    code = _check(lib().bw_effective_stiffness(rve.handle, float(rtol), int(maxit), C.ctypes.data_as(_DP),
+                                               it.ctypes.data_as(_IP), _stream(stream)))
+    return C.reshape(6, 6), it, code
 
 
 def bw_mode_fields(rve: Rve, k, modes, u_out, eps_out=None, stream=None) -> np.ndarray:

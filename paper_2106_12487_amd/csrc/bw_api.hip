@@ -186,6 +186,9 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
   cplx<T>* W = w.work((size_t)nvec * 6 * g.nvox);
   PcgDev pd = pcg_dev(r, nvec);
 
+  // x taken as 0: written as 0, so that a right-hand side that never iterates
+  // (already converged, e.g. b = 0) returns 0 and the true-residual check sees it
+  if (x0_zero) BW_HIP(hipMemsetAsync(x, 0, (size_t)nvec * n3 * sizeof(cplx<T>), s));
   if (r_ready) {
     launch_norms2<T>(r, b, rv, nvec, pd.rr, pd.rz /* ||b||^2 */, pd.partial, pd.max_blocks, s);
   } else {

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -227,27 +228,27 @@ extern "C" int bw_long_wave_speeds(bw_rve* r, const double dir[3], double h_frac
 // ---------------------------------------------------------------------------
 namespace {
 
-// unnormalized inverse 3D FFT of nv fields of nc components, in place
-template <typename T> void ifft3_nc(const bw_rve* r, cplx<T>* X, int nv, int nc, hipStream_t s) {
+// unnormalized 3D FFT (INV: inverse) of nv fields of nc components, in place
+template <typename T, bool INV> void fft3_nc(const bw_rve* r, cplx<T>* X, int nv, int nc, hipStream_t s) {
   const Geom& g = r->g;
   const long rows = (long)nc * g.n0 * g.n1;
   with_n(g.n2, [&](auto N2) {
     constexpr int n2c = decltype(N2)::value;
     RowTile rt = row_tile<T>(n2c, rows);
-    hipLaunchKernelGGL((k_row_plain<T, n2c, true>), dim3(nv * rt.tpv), dim3(NT), 0, s, (const cplx<T>*)X, X, rt,
+    hipLaunchKernelGGL((k_row_plain<T, n2c, INV>), dim3(nv * rt.tpv), dim3(NT), 0, s, (const cplx<T>*)X, X, rt,
                        (int)rows, twiddles<T>(r, 2), (const int*)nullptr);
   });
   if (g.n1 > 1)
     with_n(g.n1, [&](auto N1) {
       ColTile ct = axis1_tile<T>(N1, g.n2, (long)nc * g.n0 * g.n2);
-      hipLaunchKernelGGL((k_axis1<T, decltype(N1)::value, true>), dim3(nv * ct.tpv), dim3(NT), 0, s, X, g.n2,
+      hipLaunchKernelGGL((k_axis1<T, decltype(N1)::value, INV>), dim3(nv * ct.tpv), dim3(NT), 0, s, X, g.n2,
                          (long)nc * g.nvox, ct, twiddles<T>(r, 1), (const int*)nullptr);
     });
   if (g.n0 > 1) {
     const int n12 = g.n1 * g.n2;
     with_n(g.n0, [&](auto N0) {
       ColTile ct = axis1_tile<T>(N0, n12, (long)nc * n12);
-      hipLaunchKernelGGL((k_axis1<T, decltype(N0)::value, true>), dim3(nv * ct.tpv), dim3(NT), 0, s, X, n12,
+      hipLaunchKernelGGL((k_axis1<T, decltype(N0)::value, INV>), dim3(nv * ct.tpv), dim3(NT), 0, s, X, n12,
                          (long)nc * g.nvox, ct, twiddles<T>(r, 0), (const int*)nullptr);
     });
   }
@@ -334,7 +335,7 @@ void mode_fields(bw_rve* r, const double* k, int nm, const cplx<T>* Uh, cplx<T>*
   const Geom& g = r->g;
   const long n3 = 3 * g.nvox;
   BW_HIP(hipMemcpyAsync(u, Uh, (size_t)nm * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
-  ifft3_nc<T>(r, u, nm, 3, s);
+  fft3_nc<T, true>(r, u, nm, 3, s);
   const int bpv = 64;
   double* part = (double*)r->ws_misc.get((size_t)nm * bpv * 2 * sizeof(double) + (size_t)nm * sizeof(double2));
   double2* coef = (double2*)(part + (size_t)nm * bpv * 2);
@@ -363,11 +364,201 @@ void mode_fields(bw_rve* r, const double* k, int nm, const cplx<T>* Uh, cplx<T>*
     const double* dq = upload_qtable(r, qt, r->ws_q3, s);
     hipLaunchKernelGGL((k_strain_hat<T>), dim3(grid_of((long)nm * g.nvox)), dim3(256), 0, s, Uh, dq, eps, g.n0, g.n1,
                        g.n2, g.nvox, nm, 1.0 / r->ell);
-    ifft3_nc<T>(r, eps, nm, 6, s);
+    fft3_nc<T, true>(r, eps, nm, 6, s);
     hipLaunchKernelGGL((k_scale_fields<T>), dim3(grid_of((long)nm * 6 * g.nvox)), dim3(256), 0, s, eps,
                        6 * g.nvox, nm, (const double2*)coef);
   }
   BW_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// Static homogenization, the long-wave limit of the Bloch problem (Sec. 5.1).
+// For each unit macro strain E_j (Voigt, engineering shear) the periodic
+// fluctuation u solves K(0) u^ = i B(xi)^H F[C(x) E_j] (equilibrium of
+// C (E_j + eps(u)) with eps(u) = F^-1[i B(xi) u^]; PCG, Algorithm "InvA"), and
+// column j of C_eff is the volume mean of C(x) (E_j + eps(u)).  In the cell's
+// scaled units (C' = C / Cref, q' = q ell) the factors ell cancel:
+// u'^ = K'(0)^-1 b' with b' = i B(xi')^H F[C' E_j], eps = F^-1[i B(xi') u'^].
+// On an even grid the Nyquist label -n/2 has no partner +n/2, the fluctuation
+// is not real, and the real part of the mean stress is taken.
+// ---------------------------------------------------------------------------
+// S[j][c][x] = C'(x)_{c j}: the stress of E_j, real, all six j
+template <typename T>
+__global__ void k_unit_stress(const uint16_t* __restrict__ gmap, const T* __restrict__ C, cplx<T>* __restrict__ S,
+                              long nvox) {
+  for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < nvox; x += (long)gridDim.x * blockDim.x) {
+    const int g = gmap[x];
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        cplx<T> o;
+        o.x = C[g * 21 + vidx(c, j)];
+        o.y = 0;
+        S[((size_t)j * 6 + c) * nvox + x] = o;
+      }
+  }
+}
+
+// B = i B(q)^H S per Fourier voxel (q = qscale * table of one wave vector):
+// out_i = i sum_m q_m S_{i m} with the Voigt stress S
+template <typename T>
+__global__ void k_div_hat(const cplx<T>* __restrict__ S, const double* __restrict__ qtab, cplx<T>* __restrict__ B,
+                          int n0, int n1, int n2, long nvox, int nv, double qscale) {
+  const long total = (long)nv * nvox;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long v = e / nvox, x = e - v * nvox;
+    const int i2 = (int)(x % n2), i1 = (int)((x / n2) % n1), i0 = (int)(x / ((long)n1 * n2));
+    const double qa = qscale * qtab[i0], qb = qscale * qtab[n0 + i1], qc = qscale * qtab[n0 + n1 + i2];
+    double sr[6], si[6];
+    for (int c = 0; c < 6; ++c) {
+      const cplx<T> u = S[((size_t)v * 6 + c) * nvox + x];
+      sr[c] = (double)u.x;
+      si[c] = (double)u.y;
+    }
+    const double rr[3] = {qa * sr[0] + qb * sr[5] + qc * sr[4], qa * sr[5] + qb * sr[1] + qc * sr[3],
+                          qa * sr[4] + qb * sr[3] + qc * sr[2]};
+    const double ri[3] = {qa * si[0] + qb * si[5] + qc * si[4], qa * si[5] + qb * si[1] + qc * si[3],
+                          qa * si[4] + qb * si[3] + qc * si[2]};
+    for (int c = 0; c < 3; ++c) {
+      cplx<T> o;
+      o.x = (T)(-ri[c]);
+      o.y = (T)rr[c];
+      B[((size_t)v * 3 + c) * nvox + x] = o;
+    }
+  }
+}
+
+// per-block partial sums over voxels of C'(x) (E_j + Re(eps) inv_n), eps the
+// unnormalized inverse transform of the strain of field j; bpv blocks per j
+template <typename T>
+__global__ __launch_bounds__(256) void k_mean_stress(const uint16_t* __restrict__ gmap, const T* __restrict__ C,
+                                                     const cplx<T>* __restrict__ Eps, long nvox, double inv_n, int bpv,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[6][256];
+  const int j = blockIdx.x / bpv, b = blockIdx.x - j * bpv;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (long x = (long)b * 256 + threadIdx.x; x < nvox; x += (long)bpv * 256) {
+    const int g = gmap[x];
+    double e[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] = (c == j ? 1.0 : 0.0) + (double)Eps[((size_t)j * 6 + c) * nvox + x].x * inv_n;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double sa = 0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sa += (double)C[g * 21 + vidx(a, c)] * e[c];
+      acc[a] += sa;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) sh[a][threadIdx.x] = acc[a];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int a = 0; a < 6; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int a = 0; a < 6; ++a) part[((size_t)j * bpv + b) * 6 + a] = sh[a][0];
+}
+
+// per-block partial sums of |X|^2 over n elements per field, bpv blocks per field
+template <typename T>
+__global__ __launch_bounds__(256) void k_norm2(const cplx<T>* __restrict__ X, long n, int bpv,
+                                               double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int v = blockIdx.x / bpv, b = blockIdx.x - v * bpv;
+  double a = 0;
+  for (long e = (long)b * 256 + threadIdx.x; e < n; e += (long)bpv * 256) {
+    const cplx<T> u = X[(size_t)v * n + e];
+    a += (double)u.x * u.x + (double)u.y * u.y;
+  }
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)v * bpv + b] = sh[0];
+}
+
+template <typename T>
+std::vector<double> field_norms2(const cplx<T>* X, int nv, long n, double* part, int bpv, hipStream_t s) {
+  hipLaunchKernelGGL((k_norm2<T>), dim3((unsigned)(nv * bpv)), dim3(256), 0, s, X, n, bpv, part);
+  std::vector<double> ph((size_t)nv * bpv), out(nv, 0.0);
+  BW_HIP(hipMemcpyAsync(ph.data(), part, ph.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  BW_HIP(hipStreamSynchronize(s));
+  for (int v = 0; v < nv; ++v)
+    for (int b = 0; b < bpv; ++b) out[v] += ph[(size_t)v * bpv + b];
+  return out;
+}
+
+template <typename T>
+int effective_stiffness(bw_rve* r, double rtol, int maxit, double* Ceff, int32_t* iters, hipStream_t s) {
+  const Geom& g = r->g;
+  const long N = g.nvox;
+  const int bpv = 64;
+  char* base = (char*)r->ws_misc.get((size_t)72 * N * sizeof(cplx<T>) + (size_t)6 * bpv * 6 * sizeof(double));
+  cplx<T>* S = (cplx<T>*)base;   // 6 x 6 fields: unit stresses, then strains
+  cplx<T>* B = S + 36 * N;       // 6 x 3 right-hand sides
+  cplx<T>* X = B + 18 * N;       // 6 x 3 fluctuations
+  double* part = (double*)(X + 18 * N);
+  hipLaunchKernelGGL((k_unit_stress<T>), dim3(grid_of(N)), dim3(256), 0, s, (const uint16_t*)r->d_gmap, ctab<T>(r), S,
+                     N);
+  fft3_nc<T, false>(r, S, 6, 6, s);
+  const double k0[18] = {0};
+  QTable qt = make_qtable(r, k0, 1);
+  const double* dq = upload_qtable(r, qt, r->ws_q3, s);
+  hipLaunchKernelGGL((k_div_hat<T>), dim3(grid_of(6 * N)), dim3(256), 0, s, (const cplx<T>*)S, dq, B, g.n0, g.n1, g.n2,
+                     N, 6, 1.0);
+  // A right-hand side at the rounding level of its stress (a homogeneous cell: the
+  // transform of a uniform stress vanishes off xi = 0 up to rounding) is zero: its
+  // fluctuation is 0, which a tolerance relative to the noise itself cannot reach.
+  {
+    double qm2 = 0;
+    const int nax[3] = {g.n0, g.n1, g.n2};
+    for (int a = 0, o = 0; a < 3; o += nax[a], ++a) {
+      double m = 0;
+      for (int i = 0; i < nax[a]; ++i) m = std::max(m, qt.host[o + i] * qt.host[o + i]);
+      qm2 += m;
+    }
+    const double eps = 1e3 * std::numeric_limits<T>::epsilon();
+    const std::vector<double> ns = field_norms2<T>(S, 6, 6 * N, part, bpv, s);
+    const std::vector<double> nb = field_norms2<T>(B, 6, 3 * N, part, bpv, s);
+    for (int j = 0; j < 6; ++j)
+      if (nb[j] <= eps * eps * qm2 * ns[j])
+        BW_HIP(hipMemsetAsync(B + (size_t)j * 3 * N, 0, (size_t)3 * N * sizeof(cplx<T>), s));
+  }
+  const double* q6 = upload_qtable(r, make_qtable(r, k0, 6), r->ws_q2, s);
+  PcgResult res = pcg_run<T>(r, q6, qt, B, X, 6, rtol, maxit, true, s);
+  if (qt.null_index[0] >= 0) zero_voxel<T>(X, 6, N, qt.null_index[0], s);
+  hipLaunchKernelGGL((k_strain_hat<T>), dim3(grid_of(6 * N)), dim3(256), 0, s, (const cplx<T>*)X, dq, S, g.n0, g.n1,
+                     g.n2, N, 6, 1.0);
+  fft3_nc<T, true>(r, S, 6, 6, s);
+  hipLaunchKernelGGL((k_mean_stress<T>), dim3(6 * bpv), dim3(256), 0, s, (const uint16_t*)r->d_gmap, ctab<T>(r),
+                     (const cplx<T>*)S, N, 1.0 / (double)N, bpv, part);
+  std::vector<double> ph((size_t)6 * bpv * 6);
+  BW_HIP(hipMemcpyAsync(ph.data(), part, ph.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  BW_HIP(hipStreamSynchronize(s));
+  double Cs[6][6];
+  for (int j = 0; j < 6; ++j)
+    for (int a = 0; a < 6; ++a) {
+      double t = 0;
+      for (int b = 0; b < bpv; ++b) t += ph[((size_t)j * bpv + b) * 6 + a];
+      Cs[a][j] = t / (double)N;
+    }
+  for (int a = 0; a < 6; ++a)
+    for (int j = 0; j < 6; ++j) Ceff[a * 6 + j] = 0.5 * (Cs[a][j] + Cs[j][a]) * r->Cref;
+  for (int v = 0; v < 6; ++v)
+    if (iters) iters[v] = res.iters[v];
+  if (!res.converged) {
+    set_error("homogenization: some cell problem did not reach the tolerance within maxit");
+    return BW_ENOTCONV;
+  }
+  return BW_OK;
 }
 
 }  // namespace
@@ -391,6 +582,27 @@ extern "C" int bw_mode_fields(bw_rve* r, const double k[3], int32_t nmodes, cons
                          phase_host, s);
     BW_HIP(hipGetLastError());
     return BW_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal: ") + e.what());
+    return BW_EINVAL;
+  }
+}
+
+extern "C" int bw_effective_stiffness(bw_rve* r, double rtol, int32_t maxit, double* C66_host, int32_t* iters_host,
+                                      void* stream) {
+  try {
+    BW_REQUIRE(r && C66_host, BW_EINVAL, "null argument");
+    BW_REQUIRE(rtol >= 0 && rtol < 1, BW_EINVAL, "rtol must be in [0, 1)");
+    if (rtol == 0) rtol = r->precision == BW_FP64 ? 1e-12 : 1e-6;
+    if (maxit <= 0) maxit = 20000;
+    hipStream_t s = (hipStream_t)stream;
+    const int code = r->precision == BW_FP64 ? effective_stiffness<double>(r, rtol, maxit, C66_host, iters_host, s)
+                                             : effective_stiffness<float>(r, rtol, maxit, C66_host, iters_host, s);
+    BW_HIP(hipGetLastError());
+    return code;
   } catch (const Error& e) {
     set_error(e.msg);
     return e.code;

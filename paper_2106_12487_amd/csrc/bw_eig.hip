@@ -678,7 +678,6 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       for (int k = 0; k < nk; ++k) sc[k] = act[k] ? 1.0 : 0.0;
       upload_sc();
       launch_scale_copy<T>(MV + (size_t)j * n3, xk, B, n3, scd, nk, n3, nullptr, s);
-      BW_HIP(hipMemsetAsync(X, 0, (size_t)nk * n3 * sizeof(cplx<T>), s));
       PcgResult pr = pcg_run<T>(r, dq, qt, B, X, nk, fp32 ? std::max(o.tol_lin, 1e-6) : o.tol_lin, o.maxit_lin,
                                 true, s, false, false);
       cnt.pcg_iters += pr.total_iters;

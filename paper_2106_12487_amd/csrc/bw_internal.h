@@ -248,7 +248,7 @@ PcgDev pcg_dev(bw_rve* r, int nvec);
 const double* upload_qtable(bw_rve* r, const QTable& t, DevBuf& buf, hipStream_t s);
 double K_scale(const bw_rve* r);
 double M_scale(const bw_rve* r);
-// x0_zero: x is ignored and taken as 0.  r_ready: the caller already wrote the
+// x0_zero: x is ignored, taken as 0 and first set to 0.  r_ready: the caller already wrote the
 // initial residual b - K x into workspace vector 0.  true_check: confirm the
 // recurrence residual with a true residual before returning.
 template <typename T>

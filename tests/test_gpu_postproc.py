@@ -143,6 +143,29 @@ def test_long_wave_speeds_match_static_homogenization(lib, prec):
     R.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_effective_stiffness_matches_oracle(lib, prec):
+    """Static homogenization on the GPU (six PCG cell problems at k = 0) against the
+    oracle's, on a 16^3 / 12-grain Cu cell and a ragged 16 x 8 x 24 Cu/Al cell: 1e-10
+    (FP64) / 2e-5 (mixed) of the largest entry; a homogeneous cell gives C itself."""
+    for rve in (inputs.polycrystal((16, 16, 16), (L, L, L), 12, 94, 2),
+                inputs.polycrystal((16, 8, 24), (L, 0.5 * L, 1.5 * L), 9, 95, 0, phases=("cu", "al"))):
+        Co = postproc.effective_stiffness(rve)
+        R = lib.Rve.from_inputs(rve, prec)
+        C, it, code = lib.bw_effective_stiffness(R)
+        assert code == 0, lib.bw_last_error()
+        rel = np.abs(C - Co).max() / np.abs(Co).max()
+        print(f"\n[case] C_eff n={rve.n} prec={prec}: rel diff {rel:.2e}, iterations {it}", flush=True)
+        assert rel <= (1e-10 if prec == 0 else 2e-5)
+        R.close()
+    ni = inputs.NI
+    R = lib.Rve.from_inputs(inputs.homogeneous((8, 8, 8), (L, L, L), ni["C"], ni["rho"]), prec)
+    C, _, code = lib.bw_effective_stiffness(R)
+    assert code == 0
+    np.testing.assert_allclose(C, ni["C"], rtol=0, atol=(1e-12 if prec == 0 else 1e-6) * ni["C"].max())
+    R.close()
+
+
 def test_long_wave_speeds_bench_cell_within_voigt_reuss(lib):
     """The 64^3 / 64-grain Cu polycrystal of the bench (mixed path), three directions."""
     rve = inputs.workload_rve(2, 0)
