@@ -201,10 +201,19 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
   BW_HIP(hipMemcpyAsync(bb.data(), pd.rz, nvec * sizeof(double), hipMemcpyDeviceToHost, s));
   BW_HIP(hipStreamSynchronize(s));
   std::vector<int> act(nvec), it0(nvec, 0);
+  bool zeroed = false;
   for (int v = 0; v < nvec; ++v) {
     thr[v] = tol * tol * bb[v];
     act[v] = rr[v] > thr[v] ? 1 : 0;
+    if (bb[v] == 0 && act[v]) {
+      // b = 0 with a nonzero start: the solution is 0 (no relative tolerance applies)
+      BW_HIP(hipMemsetAsync(x + (size_t)v * n3, 0, n3 * sizeof(cplx<T>), s));
+      rr[v] = 0;
+      act[v] = 0;
+      zeroed = true;
+    }
   }
+  if (zeroed) BW_HIP(hipMemcpyAsync(pd.rr, rr.data(), nvec * sizeof(double), hipMemcpyHostToDevice, s));
   BW_HIP(hipMemcpyAsync(pd.bb, thr.data(), nvec * sizeof(double), hipMemcpyHostToDevice, s));
   BW_HIP(hipMemcpyAsync(pd.active, act.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
   BW_HIP(hipMemcpyAsync(pd.mask, act.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));

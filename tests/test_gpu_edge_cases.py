@@ -41,6 +41,29 @@ def test_empty_batches_are_no_ops(lib, prec):
     R.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pcg_zero_right_hand_side_returns_zero(lib, prec):
+    """b = 0 (next to a nonzero right-hand side): x = 0 whatever the initial guess, no
+    iterations, and the other vector solved as alone."""
+    torch = _torch()
+    rve = inputs.polycrystal((8, 8, 8), (L, L, L), 4, 96, 1)
+    R = lib.Rve.from_inputs(rve, prec)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    g = torch.Generator(device="cuda").manual_seed(3)
+    b = torch.randn((2, 3, 8, 8, 8), dtype=dt, device="cuda", generator=g)
+    b[0] = 0
+    x = torch.randn((2, 3, 8, 8, 8), dtype=dt, device="cuda", generator=g)
+    x1 = x[1:].clone()
+    k = np.array([0.3, -0.1, 0.2]) * np.pi / L
+    tol = 1e-10 if prec == 0 else 1e-5
+    code, it, rr = lib.bw_pcg_solve(R, k, b, x, tol)
+    assert code == 0 and it[0] == 0 and rr[0] == 0 and it[1] > 0
+    assert float(x[0].abs().max()) == 0.0
+    c1, it1, _ = lib.bw_pcg_solve(R, k, b[1:].contiguous(), x1, tol)
+    assert c1 == 0 and int(it1[0]) == int(it[1])
+    R.close()
+
+
 def test_two_voxel_cell_matches_dense_oracle(lib):
     """A 2 x 1 x 1 cell of two rotated Cu grains (6 degrees of freedom): off Gamma the
     subspace method with a block of 5 gives the 4 lowest frequencies of the dense pencil;
