@@ -953,7 +953,8 @@ extern "C" int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const 
   try {
     BW_REQUIRE(rves && k_lists && nks && omegas, BW_EINVAL, "null argument");
     BW_REQUIRE(nrve >= 0 && nrve <= 256, BW_EINVAL, "nrve out of range (0 .. 256)");
-    for (int i = 0; i < nrve; ++i) BW_REQUIRE(rves[i] && k_lists[i] && omegas[i], BW_EINVAL, "null cell argument");
+    for (int i = 0; i < nrve; ++i)
+      BW_REQUIRE(rves[i] && (nks[i] == 0 || (k_lists[i] && omegas[i])), BW_EINVAL, "null cell argument");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t cs = (hipStream_t)stream;
     // work already queued on the caller's stream precedes the batch

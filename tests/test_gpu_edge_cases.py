@@ -37,7 +37,14 @@ def test_empty_batches_are_no_ops(lib, prec):
         w, err, code, st = lib.bw_lowest_modes(R, np.zeros((0, 3)), 4, method=method, block=block)
         assert code == 0 and w.shape == (0, 4) and st["pcg_iterations"] == 0
     assert lib.bw_mode_fields(R, k, e, f).shape == (0,)
+    # several cells at once, one of them with no wave vectors
+    R2 = lib.Rve.from_inputs(inputs.polycrystal((8, 4, 8), (L, L, L), 3, 95, 0), prec)
+    oms, ers, code, st = lib.bw_lowest_modes_batched([R, R2], [np.zeros((0, 3)), [k]], 4, method=0, block=8)
+    assert code == 0 and oms[0].shape == (0, 4) and oms[1].shape == (1, 4) and np.all(oms[1] > 0)
+    w1, _, c1, _ = lib.bw_lowest_modes(R2, [k], 4, method=0, block=8)
+    assert c1 == 0 and np.array_equal(w1, oms[1])
     _torch().cuda.synchronize()
+    R2.close()
     R.close()
 
 
