@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_MFMA_TFLOPS = 78.6   # MI355X dense FP64 matrix
 
 # Algorithmic HBM bytes per voxel and per vector of each kernel, in words of one
 # complex number (8 B FP32 / 16 B FP64) plus the uint16 grain index where read.
@@ -110,6 +111,23 @@ def run_arm(bw, rve_in, ks, precision, steps, warmup, tol_lin, tol_eig, timing=F
         bw.bw_timing_enable(False)
     R.close()
     return dict(seconds=dt, stats=stats, max_bound=maxb, omega=w, code=code, timing=rep, breakdown=breakdown)
+
+
+def gram_mfma(breakdown, nvox):
+    """MFMA use of the Gram products X^H Y (FP64 complex, the Rayleigh-Ritz blocks) over the
+    last warmup step: achieved FLOP/s (8 real flops per complex multiply-add, n = 3 nvox
+    rows, sum of qx qy over the launches) against min(FP64 MFMA peak, intensity x 8 TB/s),
+    the intensity of a q x q block being 8 q^2 n / (2 q n 16 B) = q / 4 flop/B."""
+    g = (breakdown or {}).get("k_gram_mfma")
+    if not g or not g["launches"] or not g["ms"]:
+        return None
+    flops = 8.0 * 3 * nvox * g["units"]
+    q = (g["units"] / g["launches"]) ** 0.5
+    achieved = flops / (g["ms"] * 1e-3) / 1e12
+    bound = min(PEAK_FP64_MFMA_TFLOPS, q / 4.0 * PEAK_HBM_GBS / 1e3)
+    return {"kernel": "k_gram_mfma", "dtype": "f64", "launches": g["launches"], "mean_block": round(q, 2),
+            "achieved_TFLOPs": round(achieved, 3), "bound_TFLOPs": round(bound, 3),
+            "frac_of_bound": round(achieved / bound, 4), "peak_TFLOPs": PEAK_FP64_MFMA_TFLOPS}
 
 
 def dominant(rep):
@@ -425,6 +443,7 @@ def main():
     cbw = copy_bandwidth(bw)
     out["roofline"]["copy_GBps"] = round(cbw, 1)
     out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / cbw, 4)
+    out["mfma"] = gram_mfma(mixed["breakdown"], nvox)
     for kname, v in sorted((mixed["breakdown"] or {}).items(), key=lambda kv: -kv[1]["ms"]):
         print(f"[bench] kernel {kname:24s} launches {v['launches']:6d} total {v['ms']:9.1f} ms units {v['units']}",
               file=sys.stderr, flush=True)
