@@ -1,5 +1,7 @@
 // Dispersion post-processing: slopes of the branches (group velocity, Sec. 5.1
-// eq. c_group) and long-wave speeds of the three acoustic branches.
+// eq. c_group), long-wave speeds of the three acoustic branches, the static
+// homogenization they tend to (effective stiffness), and real-space mode fields
+// with strain maps (Sec. 5.2, eq. rotate_eigenvector).
 //
 // Slopes.  K(k) depends on k only through the shifted frequencies q = xi + k of
 // the strain and the divergence (Sec. 3.2 eq. hatA), each linear in q, so K is a
