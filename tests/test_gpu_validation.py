@@ -89,6 +89,29 @@ def test_homogeneous_2d_path_exact(lib):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_homogeneous_1d_exact(lib, prec):
+    """Sec. 4.1, 1D: homogeneous epoxy on 64 x 1 x 1 at wave vectors along x across the
+    first zone: the lowest 9 frequencies are c_L |xi + k| and c_T |xi + k| (twice) over
+    the grid's labels xi = 2 pi m / L (subspace method: the transverse pairs are exactly
+    degenerate)."""
+    ep = inputs.EPOXY
+    n = 64
+    rve = inputs.homogeneous((n, 1, 1), (L, L, L), ep["C"], ep["rho"])
+    ks = np.array([[t * np.pi / L, 0.0, 0.0] for t in (0.05, 0.3, 0.7, 1.0)])
+    w, err, _ = _modes(lib, rve, ks, 9, prec, method=0)
+    cL = np.sqrt(ep["C"][0, 0] / ep["rho"])
+    cT = np.sqrt(ep["C"][3, 3] / ep["rho"])
+    m = np.fft.fftfreq(n, 1.0 / n)
+    for i, k in enumerate(ks):
+        q = np.abs(2 * np.pi * m / L + k[0])
+        ref = np.sort(np.concatenate([cL * q, cT * q, cT * q]))[:9]
+        e = np.abs(w[i] - ref) / ref
+        print(f"\n[case] homogeneous 1D prec={prec} k#{i}: max rel err {e.max():.2e}", flush=True)
+        assert e.max() <= (1e-9 if prec == 0 else 1e-5)
+        assert np.all(e <= err[i] * 1.5 + 1e-12)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_fibre_composite_32_matches_dense_oracle(lib, prec):
     """Sec. 4.3 geometry (55% circular carbon fibres in epoxy) on 32 x 32 x 1 at two wave
     vectors of the M-Gamma-X-M path off the symmetry points, 10 modes, Lanczos as in the
