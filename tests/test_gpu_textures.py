@@ -62,3 +62,28 @@ def test_ni_bar_long_wave_speeds(lib, A):
     ref = np.sqrt(np.sort(np.linalg.eigvalsh(G)) / inputs.NI["rho"])
     print(f"\n[case] Ni bar A={A}: c {c}, harmonic mean {ref}", flush=True)
     np.testing.assert_allclose(c, ref, rtol=1e-7)
+
+
+def test_ni_bar_isotropic_grains_dispersion_exact(lib):
+    """Zener ratio 1: every grain is isotropic, so the bar is homogeneous whatever the
+    orientations, and the 1D spectrum is exactly c_L |xi + k| and c_T |xi + k| (twice) over
+    the grid's labels, at long and short waves alike (FP64, subspace method: the
+    transverse pairs are exactly degenerate)."""
+    _torch()
+    rve = inputs.ni_bar(256, 64, 50e-6, 50e-6, 1.0, 0)
+    Lb = rve.L[0]
+    C = inputs.c21_to_voigt(rve.C21[0])
+    rho = inputs.NI["rho"]
+    cL, cT = np.sqrt(C[0, 0] / rho), np.sqrt(C[3, 3] / rho)
+    ks = np.array([[t * np.pi / Lb, 0.0, 0.0] for t in (0.1, 0.5, 1.0)])
+    R = lib.Rve.from_inputs(rve, 0)
+    w, err, code, _ = lib.bw_lowest_modes(R, ks, 9, method=0, block=16, tol_omega=1e-11, tol_lin=1e-12)
+    assert code == 0, lib.bw_last_error()
+    R.close()
+    m = np.fft.fftfreq(256, 1.0 / 256)
+    for i, k in enumerate(ks):
+        q = np.abs(2 * np.pi * m / Lb + k[0])
+        ref = np.sort(np.concatenate([cL * q, cT * q, cT * q]))[:9]
+        e = np.abs(w[i] - ref) / ref
+        print(f"\n[case] Ni bar A=1 k#{i}: max rel err {e.max():.2e}", flush=True)
+        assert e.max() <= 1e-9
