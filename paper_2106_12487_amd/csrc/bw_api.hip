@@ -65,13 +65,15 @@ bool timing_enabled() { return g_timing.load(std::memory_order_relaxed); }
 
 namespace {
 std::atomic<bool> g_graphs{true};
-thread_local bool t_graphs_off = false;
 }
+std::recursive_mutex& capture_alloc_mutex() {
+  static std::recursive_mutex m;
+  return m;
+}
+
 // graphs are replayed only while no kernel timing is requested (timing brackets
-// every launch with events, which a replayed graph cannot do), and not on host
-// threads that opted out (see graphs_off_this_thread)
-bool graphs_enabled() { return !t_graphs_off && g_graphs.load(std::memory_order_relaxed) && !timing_enabled(); }
-void graphs_off_this_thread(bool off) { t_graphs_off = off; }
+// every launch with events, which a replayed graph cannot do)
+bool graphs_enabled() { return g_graphs.load(std::memory_order_relaxed) && !timing_enabled(); }
 
 KTimer::KTimer(const char* n, hipStream_t st, long u) : name(n), s(st), units(u) {
   if (!timing_enabled()) return;
@@ -235,6 +237,8 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
                                               (const void*)(long)nvec, (const void*)(long)chunk,
                                               (const void*)(long)sizeof(T)};
         if (!r->pcg_exec || r->pcg_key != key) {
+          // no allocation or free on another thread while this thread captures
+          std::lock_guard<std::recursive_mutex> lk(capture_alloc_mutex());
           if (r->pcg_exec) (void)hipGraphExecDestroy(r->pcg_exec);
           if (r->pcg_graph) (void)hipGraphDestroy(r->pcg_graph);
           r->pcg_exec = nullptr;

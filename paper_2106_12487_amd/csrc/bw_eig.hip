@@ -987,7 +987,6 @@ extern "C" int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const 
           return;
         }
         std::memset(&one[i], 0, sizeof(bw_stats));
-        if (nrve > 1) graphs_off_this_thread(true);   // concurrent cells: no stream capture
         code[i] = bw_lowest_modes(rves[i], k_lists[i], nks[i], nmodes, opts, omegas[i], errs ? errs[i] : nullptr,
                                   modes ? modes[i] : nullptr, &one[i], st[i]);
         if (code[i] != BW_OK) msg[i] = bw_last_error();

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,10 +45,6 @@ struct Error {
 // ---------------------------------------------------------------------------
 bool timing_enabled();
 bool graphs_enabled();
-// Stream capture on one host thread fails when another thread of the same
-// process allocates, frees or synchronizes meanwhile; drivers that run several
-// cells from concurrent host threads launch eagerly on those threads.
-void graphs_off_this_thread(bool off);
 struct KTimer {
   const char* name;
   hipStream_t s;
@@ -63,6 +60,10 @@ void timing_add_units(const char* name, long units);
     hipLaunchKernelGGL(kern, grid, block, shm, s, __VA_ARGS__); \
   } while (0)
 
+// Device allocation and freeing (hipFree synchronizes the device) must not
+// overlap a stream capture on another host thread: both hold this mutex.
+std::recursive_mutex& capture_alloc_mutex();
+
 // ---------------------------------------------------------------------------
 // device buffer with grow-on-demand semantics
 // ---------------------------------------------------------------------------
@@ -71,6 +72,7 @@ struct DevBuf {
   size_t bytes = 0;
   void* get(size_t need) {
     if (need > bytes) {
+      std::lock_guard<std::recursive_mutex> lk(capture_alloc_mutex());
       if (p) BW_HIP(hipFree(p));
       p = nullptr;
       bytes = 0;
@@ -81,7 +83,9 @@ struct DevBuf {
     return p;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    std::lock_guard<std::recursive_mutex> lk(capture_alloc_mutex());
+    (void)hipFree(p);
     p = nullptr;
     bytes = 0;
   }
