@@ -148,7 +148,7 @@ QTable make_qtable(const bw_rve* r, const double* k_host, int nk) {
 const double* upload_qtable(bw_rve* r, const QTable& t, DevBuf& buf, hipStream_t s) {
   const size_t bytes = t.host.size() * sizeof(double);
   double* d = (double*)buf.get(bytes);
-  BW_HIP(hipMemcpyAsync(d, t.host.data(), bytes, hipMemcpyHostToDevice, s));
+  h2d(d, t.host.data(), bytes, s);
   BW_HIP(hipStreamSynchronize(s));
   return d;
 }
@@ -215,11 +215,11 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
       zeroed = true;
     }
   }
-  if (zeroed) BW_HIP(hipMemcpyAsync(pd.rr, rr.data(), nvec * sizeof(double), hipMemcpyHostToDevice, s));
-  BW_HIP(hipMemcpyAsync(pd.bb, thr.data(), nvec * sizeof(double), hipMemcpyHostToDevice, s));
-  BW_HIP(hipMemcpyAsync(pd.active, act.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
-  BW_HIP(hipMemcpyAsync(pd.mask, act.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
-  BW_HIP(hipMemcpyAsync(pd.iters, it0.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
+  if (zeroed) h2d(pd.rr, rr.data(), nvec * sizeof(double), s);
+  h2d(pd.bb, thr.data(), nvec * sizeof(double), s);
+  h2d(pd.active, act.data(), nvec * sizeof(int), s);
+  h2d(pd.mask, act.data(), nvec * sizeof(int), s);
+  h2d(pd.iters, it0.data(), nvec * sizeof(int), s);
   launch_pcg_restart<T>(r, d_qtab, rv, nvec, pd, pd.mask, s);
   BW_HIP(hipStreamSynchronize(s));
 
@@ -283,7 +283,7 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
           act[v] = 0;
           cap = true;
         }
-      if (cap) BW_HIP(hipMemcpyAsync(pd.active, act.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
+      if (cap) h2d(pd.active, act.data(), nvec * sizeof(int), s);
       any = false;
       for (int v = 0; v < nvec; ++v) any |= act[v] != 0;
       if (any) continue;
@@ -308,8 +308,8 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
     if (!again) break;
     ++restarts;
     act = mask;
-    BW_HIP(hipMemcpyAsync(pd.active, act.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
-    BW_HIP(hipMemcpyAsync(pd.mask, mask.data(), nvec * sizeof(int), hipMemcpyHostToDevice, s));
+    h2d(pd.active, act.data(), nvec * sizeof(int), s);
+    h2d(pd.mask, mask.data(), nvec * sizeof(int), s);
     launch_pcg_restart<T>(r, d_qtab, rv, nvec, pd, pd.mask, s);
   }
   res.converged = true;

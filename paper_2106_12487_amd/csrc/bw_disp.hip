@@ -148,8 +148,8 @@ extern "C" int bw_group_velocity(bw_rve* r, const double k[3], const double dir[
       double2* dQ = dM + (size_t)q * q;
       double* dl = (double*)(dQ + (size_t)q * q);
       int* dinfo = (int*)(dl + q);
-      BW_HIP(hipMemcpyAsync(dK, Dc.data(), Dc.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-      BW_HIP(hipMemcpyAsync(dM, Bc.data(), Bc.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+      h2d(dK, Dc.data(), Dc.size() * sizeof(double2), s);
+      h2d(dM, Bc.data(), Bc.size() * sizeof(double2), s);
       launch_small_geig(dK, dM, q, dl, dQ, dinfo, s);
       std::vector<double> lam(q);
       int info = 0;
@@ -358,7 +358,7 @@ void mode_fields(bw_rve* r, const double* k, int nm, const cplx<T>* Uh, cplx<T>*
     // e^{-i phi} / N (the inverse transform above is unnormalized)
     cf[v] = double2{std::cos(phi) / (double)g.nvox, -std::sin(phi) / (double)g.nvox};
   }
-  BW_HIP(hipMemcpyAsync(coef, cf.data(), nm * sizeof(double2), hipMemcpyHostToDevice, s));
+  h2d(coef, cf.data(), nm * sizeof(double2), s);
   hipLaunchKernelGGL((k_scale_fields<T>), dim3(grid_of((long)nm * n3)), dim3(256), 0, s, u, n3, nm,
                      (const double2*)coef);
   if (eps) {

@@ -199,8 +199,8 @@ template <typename T>
 static void rigid_MN(bw_rve* r, long jstar, cplx<T>* N, cplx<T>* MN, Small& sm, Counters& c, hipStream_t s) {
   std::vector<long> vox = {jstar, jstar, jstar};
   std::vector<double> pol = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-  BW_HIP(hipMemcpyAsync(sm.vox, vox.data(), 3 * sizeof(long), hipMemcpyHostToDevice, s));
-  BW_HIP(hipMemcpyAsync(sm.pol, pol.data(), 9 * sizeof(double), hipMemcpyHostToDevice, s));
+  h2d(sm.vox, vox.data(), 3 * sizeof(long), s);
+  h2d(sm.pol, pol.data(), 9 * sizeof(double), s);
   launch_planewaves<T>(N, 3, r->g.nvox, sm.vox, sm.pol, s);
   apply_M_blk<T>(r, N, MN, 3, false, c, s);
   BW_HIP(hipStreamSynchronize(s));
@@ -239,7 +239,7 @@ static void rr64_bounds(bw_rve* r, const double* dq, cplx<double>*& U, int q, in
     KU = KU1;
     MU = MU1;
   } else {
-    BW_HIP(hipMemcpyAsync(sm.lam, lam.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
+    h2d(sm.lam, lam.data(), q * sizeof(double), s);
   }
   launch_lincomb<double>(KU, MU, sm.lam, R, n_want, n3, n3, s);
   apply_M_blk<double>(r, R, Z, n_want, true, cnt, s);
@@ -302,7 +302,7 @@ static void refine64(bw_rve* r, const double* dq, const QTable& qt, long jstar, 
       launch_deflate<double>(D64, MD, MN, n_want, r->g.nvox, jstar, sm.coef, s);
     }
     std::vector<double> ones(n_want, 1.0);
-    BW_HIP(hipMemcpyAsync(sm.sc, ones.data(), n_want * sizeof(double), hipMemcpyHostToDevice, s));
+    h2d(sm.sc, ones.data(), n_want * sizeof(double), s);
     U64 = (cplx<double>*)w64.v[3].p;
     launch_lincomb<double>(U64, D64, sm.sc, U64, n_want, n3, n3, s);  // U <- U - D
     BW_HIP(hipStreamSynchronize(s));
@@ -340,8 +340,8 @@ static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigO
     std::vector<long> vox;
     std::vector<double> pol;
     reference_start(r, qt, q, vox, pol);
-    BW_HIP(hipMemcpyAsync(sm.vox, vox.data(), q * sizeof(long), hipMemcpyHostToDevice, s));
-    BW_HIP(hipMemcpyAsync(sm.pol, pol.data(), 3 * q * sizeof(double), hipMemcpyHostToDevice, s));
+    h2d(sm.vox, vox.data(), q * sizeof(long), s);
+    h2d(sm.pol, pol.data(), 3 * q * sizeof(double), s);
     launch_planewaves<T>(U, q, g.nvox, sm.vox, sm.pol, s);
     BW_HIP(hipStreamSynchronize(s));
     lam_prev.clear();
@@ -355,9 +355,9 @@ static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigO
     std::vector<double> pol;
     reference_start(r, qt, nf, vox, pol);
     for (int i = 0; i < nf; ++i) vec[i] = keep + i;
-    BW_HIP(hipMemcpyAsync(sm.vox, vox.data(), nf * sizeof(long), hipMemcpyHostToDevice, s));
-    BW_HIP(hipMemcpyAsync(sm.vox + 128, vec.data(), nf * sizeof(long), hipMemcpyHostToDevice, s));
-    BW_HIP(hipMemcpyAsync(sm.pol, pol.data(), 3 * nf * sizeof(double), hipMemcpyHostToDevice, s));
+    h2d(sm.vox, vox.data(), nf * sizeof(long), s);
+    h2d(sm.vox + 128, vec.data(), nf * sizeof(long), s);
+    h2d(sm.pol, pol.data(), 3 * nf * sizeof(double), s);
     launch_set_entries<T>(U, n3, g.nvox, nf, sm.vox + 128, sm.vox, sm.pol, s, true);
     BW_HIP(hipStreamSynchronize(s));
   }
@@ -392,10 +392,10 @@ static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigO
         inv[p] = lam_prev[p] > 0 ? 1.0 / lam_prev[p] : 0.0;
         ninv[p] = -inv[p];
       }
-      BW_HIP(hipMemcpyAsync(sm.sc, inv.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
+      h2d(sm.sc, inv.data(), q * sizeof(double), s);
       launch_scale_cols<T>(U, sm.sc, Ub, q, n3, n3, s);  // x0 = U / lambda
       if (have_KU) {
-        BW_HIP(hipMemcpyAsync(sm.sc + 128, ninv.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
+        h2d(sm.sc + 128, ninv.data(), q * sizeof(double), s);
         launch_scale_cols<T>(R, sm.sc + 128, w.vec(0, (size_t)q * n3), q, n3, n3, s);  // r0 = -R / lambda
         r_ready = true;
       }
@@ -527,15 +527,15 @@ static void write_modes(bw_rve* r, const KOut& ko, int nmodes, void* modes, int 
   std::vector<double> pol = {a, 0, 0, 0, a, 0, 0, 0, a};
   std::vector<double> sc(std::max(ko.n_want, 1), a);
   if (ko.jstar >= 0) {
-    BW_HIP(hipMemcpyAsync(sm.vox, vox.data(), 3 * sizeof(long), hipMemcpyHostToDevice, s));
-    BW_HIP(hipMemcpyAsync(sm.pol, pol.data(), 9 * sizeof(double), hipMemcpyHostToDevice, s));
+    h2d(sm.vox, vox.data(), 3 * sizeof(long), s);
+    h2d(sm.pol, pol.data(), 9 * sizeof(double), s);
     launch_planewaves<T>(dst, 3, r->g.nvox, sm.vox, sm.pol, s);
     off = 3;
   }
   if (ko.n_want > 0) {
     // the FP64 Ritz block (refined) lives in the FP64 workspace slot 3 for both paths
     const cplx<double>* U = (const cplx<double>*)ws<double>(r).v[3].p;
-    BW_HIP(hipMemcpyAsync(sm.sc, sc.data(), ko.n_want * sizeof(double), hipMemcpyHostToDevice, s));
+    h2d(sm.sc, sc.data(), ko.n_want * sizeof(double), s);
     if (sizeof(T) == 8) {
       launch_scale_cols<double>(U, sm.sc, (cplx<double>*)(dst + (size_t)off * n3), ko.n_want, n3, n3, s);
     } else {
@@ -617,8 +617,8 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
                                                : (o.tol_omega > 0 ? o.tol_omega : o.tol_eig);
   const double bound_target = o.tol_omega > 0 ? o.tol_omega : 5.0 * o.tol_eig;
   const double lscale = r->Cref / (r->rho_bar * r->ell * r->ell);
-  auto upload_act = [&]() { BW_HIP(hipMemcpyAsync(actd, act.data(), nk * sizeof(int), hipMemcpyHostToDevice, s)); };
-  auto upload_sc = [&]() { BW_HIP(hipMemcpyAsync(scd, sc.data(), nk * sizeof(double), hipMemcpyHostToDevice, s)); };
+  auto upload_act = [&]() { h2d(actd, act.data(), nk * sizeof(int), s); };
+  auto upload_sc = [&]() { h2d(scd, sc.data(), nk * sizeof(double), s); };
 
   // start vectors: the lowest reference plane wave plus a little of the next three
   BW_HIP(hipMemsetAsync(B, 0, (size_t)nk * n3 * sizeof(cplx<T>), s));
@@ -638,9 +638,9 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
     }
     for (size_t e0 = 0; e0 < vec.size(); e0 += 80) {
       const int ne = (int)std::min<size_t>(80, vec.size() - e0);
-      BW_HIP(hipMemcpyAsync(sm.vox, vox.data() + e0, ne * sizeof(long), hipMemcpyHostToDevice, s));
-      BW_HIP(hipMemcpyAsync(sm.pol, val.data() + 3 * e0, 3 * ne * sizeof(double), hipMemcpyHostToDevice, s));
-      BW_HIP(hipMemcpyAsync(sm.vox + 128, vec.data() + e0, ne * sizeof(long), hipMemcpyHostToDevice, s));
+      h2d(sm.vox, vox.data() + e0, ne * sizeof(long), s);
+      h2d(sm.pol, val.data() + 3 * e0, 3 * ne * sizeof(double), s);
+      h2d(sm.vox + 128, vec.data() + e0, ne * sizeof(long), s);
       launch_set_entries<T>(B, n3, g.nvox, ne, sm.vox + 128, sm.vox, sm.pol, s);
       BW_HIP(hipStreamSynchronize(s));
     }
@@ -731,7 +731,7 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
     double2* Sd_dev = (double2*)w.v[10].get((size_t)nb * m * m * sizeof(double2));
     double* th_dev = (double*)w.v[11].get((size_t)nb * m * sizeof(double) + (size_t)nb * sizeof(int) + 64);
     int* inf_dev = (int*)(th_dev + (size_t)nb * m);
-    BW_HIP(hipMemcpyAsync(Hd_dev, Hall.data(), Hall.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    h2d(Hd_dev, Hall.data(), Hall.size() * sizeof(double), s);
     launch_small_eig_batched(Hd_dev, m, nb, th_dev, Sd_dev, inf_dev, s);
     BW_HIP(hipMemcpyAsync(thall.data(), th_dev, thall.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     BW_HIP(hipMemcpyAsync(Sall.data(), Sd_dev, Sall.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
@@ -757,7 +757,7 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
         std::vector<double2> Qs((size_t)m * qsel);
         for (int p = 0; p < m; ++p)
           for (int c = 0; c < qsel; ++c) Qs[(size_t)p * qsel + c] = Sm[(size_t)p * m + (m - 1 - c)];
-        BW_HIP(hipMemcpyAsync(sm.Q, Qs.data(), Qs.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+        h2d(sm.Q, Qs.data(), Qs.size() * sizeof(double2), s);
         cplx<double>* U64 = ws<double>(r).vec(3, (size_t)qsel * n3);
         if (fp32) {
           launch_ritz<T>(V + (size_t)k * xk, m, sm.Q, qsel, TMP, qsel, n3, n3, s);
@@ -806,7 +806,7 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       std::vector<double2> Qk((size_t)m * kk);
       for (int p = 0; p < m; ++p)
         for (int c = 0; c < kk; ++c) Qk[(size_t)p * kk + c] = Sm[(size_t)p * m + (m - 1 - c)];
-      BW_HIP(hipMemcpyAsync(sm.Q, Qk.data(), Qk.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+      h2d(sm.Q, Qk.data(), Qk.size() * sizeof(double2), s);
       cplx<T>* Vk = V + (size_t)k * xk;
       cplx<T>* MVk = MV + (size_t)k * xk;
       launch_ritz<T>(Vk, m, sm.Q, kk, TMP, kk, n3, n3, s);

@@ -123,32 +123,30 @@ void launch_gram(const cplx<T>* X, int qx, const cplx<T>* Y, int qy, long n, lon
 // ---------------------------------------------------------------------------
 // Ritz update Y_j = sum_p X_p Q[p][j]
 // ---------------------------------------------------------------------------
-template <typename T>
+// Y[:, j] = sum_p X[:, p] Q[p][j] (FP64 accumulation).  The coefficients are
+// the same for every lane, so they are read with scalar loads; QO bounds qout
+// at compile time (fewer accumulators, higher occupancy).
+template <typename T, int QO>
 __global__ __launch_bounds__(256) void k_ritz(const cplx<T>* __restrict__ X, int q, const double2* __restrict__ Q,
                                               int ldq, cplx<T>* __restrict__ Y, int qout, long n, long vstride) {
-  __shared__ double2 Qs[GEIG_QMAX * GRAM_QMAX];
-  for (int idx = threadIdx.x; idx < q * qout; idx += 256) {
-    const int p = idx / qout, j = idx - p * qout;
-    Qs[idx] = Q[(size_t)p * ldq + j];
-  }
-  __syncthreads();
   for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
-    double2 acc[GRAM_QMAX];
+    double2 acc[QO];
 #pragma unroll
-    for (int j = 0; j < GRAM_QMAX; ++j) acc[j] = make_double2(0, 0);
+    for (int j = 0; j < QO; ++j) acc[j] = make_double2(0, 0);
     for (int p = 0; p < q; ++p) {
       const double2 x = to_d2(X[(size_t)p * vstride + e]);
+      const double2* __restrict__ Qp = Q + (size_t)p * ldq;
 #pragma unroll
-      for (int j = 0; j < GRAM_QMAX; ++j) {
+      for (int j = 0; j < QO; ++j) {
         if (j < qout) {
-          const double2 c = Qs[p * qout + j];
+          const double2 c = Qp[j];
           acc[j].x += x.x * c.x - x.y * c.y;
           acc[j].y += x.x * c.y + x.y * c.x;
         }
       }
     }
 #pragma unroll
-    for (int j = 0; j < GRAM_QMAX; ++j)
+    for (int j = 0; j < QO; ++j)
       if (j < qout) Y[(size_t)j * vstride + e] = from_d2<T>(acc[j]);
   }
 }
@@ -159,8 +157,15 @@ void launch_ritz(const cplx<T>* X, int q, const double2* Q, int ldq, cplx<T>* Y,
   BW_REQUIRE(q <= GEIG_QMAX && qout <= GRAM_QMAX, BW_EINVAL, "Ritz block too large");
   long nb = (n + 255) / 256;
   if (nb > 2048) nb = 2048;
-  BW_LAUNCH("k_ritz", (long)q * qout, (k_ritz<T>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y, qout, n,
-            vstride);
+  if (qout <= 8)
+    BW_LAUNCH("k_ritz", (long)q * qout, (k_ritz<T, 8>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y, qout, n,
+              vstride);
+  else if (qout <= 16)
+    BW_LAUNCH("k_ritz", (long)q * qout, (k_ritz<T, 16>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y, qout,
+              n, vstride);
+  else
+    BW_LAUNCH("k_ritz", (long)q * qout, (k_ritz<T, GRAM_QMAX>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y,
+              qout, n, vstride);
 }
 
 // ---------------------------------------------------------------------------

@@ -91,6 +91,14 @@ struct DevBuf {
   }
 };
 
+// Host-to-device copy of a host buffer that the caller may change or free as
+// soon as this returns: a copy from pageable memory may read the host buffer
+// only when it executes on the stream, so the stream is synchronized first.
+inline void h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  BW_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+  BW_HIP(hipStreamSynchronize(s));
+}
+
 // Bloch data of a batch: per vector the scaled shifted wavevector tables
 // q_a(j) = m_a(j) L0 / L_a + k_a L0 / (2 pi), concatenated [n0 | n1 | n2].
 struct QTable {

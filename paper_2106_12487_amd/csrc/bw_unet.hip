@@ -1229,8 +1229,8 @@ extern "C" int bw_pcg_solve_learned(bw_rve* r, bw_unet* u, const double k_host[3
       h_coef[v] = beta;
       restart_v[v] = 0;
     }
-    BW_HIP(hipMemcpyAsync(d_coef, h_coef.data(), (size_t)nrhs * sizeof(double2), hipMemcpyHostToDevice, s));
-    BW_HIP(hipMemcpyAsync(d_skip, h_skip.data(), (size_t)nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+    h2d(d_coef, h_coef.data(), (size_t)nrhs * sizeof(double2), s);
+    h2d(d_skip, h_skip.data(), (size_t)nrhs * sizeof(int), s);
     hipLaunchKernelGGL(k_fcg_dir, vec_grid(n3, nrhs), dim3(256), 0, s, P, (const float2*)Z, (const double2*)d_coef,
                        (const int*)d_skip, n3);
     // step: alpha = <p, r> / <p, K p>
@@ -1247,7 +1247,7 @@ extern "C" int bw_pcg_solve_learned(bw_rve* r, bw_unet* u, const double k_host[3
       h_coef[nrhs + v] = make_double2(active[v] ? pkp : 0.0, 0.0);
       if (active[v] && !(pkp > 0)) restart_v[v] = 1;
     }
-    BW_HIP(hipMemcpyAsync(d_coef, h_coef.data(), (size_t)nrhs * sizeof(double2), hipMemcpyHostToDevice, s));
+    h2d(d_coef, h_coef.data(), (size_t)nrhs * sizeof(double2), s);
     hipLaunchKernelGGL(k_fcg_update, vec_grid(n3, nrhs), dim3(256), 0, s, xx, R, (const float2*)P,
                        (const float2*)KP, (const double2*)d_coef, n3);
     dots(R, R, d_dots);
