@@ -78,6 +78,40 @@ def test_apply_K_M_P_match_oracle(lib, n, grains, kk, prec):
     R.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n", [64, 128])
+def test_apply_K_plane_waves_homogeneous_closed_form(lib, n, prec):
+    """Full-size closed form: in a homogeneous cubic crystal K maps a single Fourier
+    coefficient at xi to Gamma(xi + k) times it (the acoustic tensor C_ijkl q_j q_l) and
+    nothing else; five plane waves at once, including a Nyquist label, on n^3 (64^3 runs
+    the plane pass, 128^3 the five-pass path)."""
+    torch = _dev()
+    ni = inputs.NI
+    rve = inputs.homogeneous((n, n, n), (L, L, L), ni["C"], ni["rho"])
+    R = lib.Rve.from_inputs(rve, prec)
+    k = np.array([0.23, -0.41, 0.17]) * np.pi / L
+    rng = np.random.default_rng(5)
+    idx = [(0, 0, 0), (1, 2, 3), (n - 1, 5, n // 2), (n // 2, n // 2, n // 2), (7, n - 9, 11)]
+    pol = rng.standard_normal((len(idx), 3)) + 1j * rng.standard_normal((len(idx), 3))
+    u = np.zeros((1, 3, n, n, n), dtype=np.complex128)
+    for (a, b, c), v in zip(idx, pol):
+        u[0, :, a, b, c] = v
+    y = _dev().empty_like(_to_dev(u, prec))
+    lib.bw_apply_K(R, k, _to_dev(u, prec), y)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy()
+    T = inputs.voigt_to_tensor(ni["C"])
+    lab = np.fft.fftfreq(n, 1.0 / n)
+    ref = np.zeros_like(u)
+    for (a, b, c), v in zip(idx, pol):
+        q = 2 * np.pi * np.array([lab[a], lab[b], lab[c]]) / L + k
+        ref[0, :, a, b, c] = np.einsum("ijkl,j,l->ik", T, q, q) @ v
+    err = np.abs(yh - ref).max() / np.abs(ref).max()
+    print(f"\n[case] plane waves homogeneous n={n} prec={prec}: rel err {err:.2e}", flush=True)
+    assert err <= (1e-12 if prec == 0 else 5e-6)
+    R.close()
+
+
 def test_rve_info_volume_averages(lib):
     rve = inputs.polycrystal((16, 16, 16), (L, L, L), 8, 1, 0)
     R = lib.Rve.from_inputs(rve, 0)
