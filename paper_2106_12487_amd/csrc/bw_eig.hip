@@ -630,10 +630,18 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       std::vector<long> vx;
       std::vector<double> pl;
       reference_start(r, q1, 4, vx, pl);
-      for (int e = 0; e < 4; ++e) {
-        vec.push_back(k);
-        vox.push_back(vx[e]);
-        for (int c = 0; c < 3; ++c) val.push_back(pl[3 * e + c] * (e == 0 ? 1.0 : 0.1));
+      // plane waves at one voxel (several polarizations of one wave) are summed
+      // here, so that every element of B is written by one thread only
+      const size_t first = vox.size();
+      for (size_t e = 0; e < vx.size(); ++e) {
+        size_t at = first;
+        while (at < vox.size() && vox[at] != vx[e]) ++at;
+        if (at == vox.size()) {
+          vec.push_back(k);
+          vox.push_back(vx[e]);
+          val.insert(val.end(), 3, 0.0);
+        }
+        for (int c = 0; c < 3; ++c) val[3 * at + c] += pl[3 * e + c] * (e == 0 ? 1.0 : 0.1);
       }
     }
     for (size_t e0 = 0; e0 < vec.size(); e0 += 80) {

@@ -206,3 +206,21 @@ def test_cual32_two_phase_cell_against_stored_oracle(lib, prec):
     nz = w_o > 1e-6 * _omega_ref(rve)
     assert np.all(e[nz] <= err[nz] * 1.5 + 1e-12)
     R.close()
+
+
+def test_lanczos_batch_repeats_bit_for_bit(lib):
+    """A batch of 16 wave vectors of the 64^3 workload through one Lanczos cycle, twice:
+    equal frequencies and PCG iteration totals bit for bit.  Two of a wave vector's
+    start plane waves may share a voxel (two polarizations of one wave): they are
+    summed before the start vectors are written, one element per thread, so no two
+    threads of different wavefronts write the same element."""
+    rve = inputs.workload_rve(2, 0)
+    ks = inputs.workload_kpoints(2)[:16]
+    R = lib.Rve.from_inputs(rve, lib.BW_MIXED)
+    kw = dict(method=lib.BW_LANCZOS, tol_omega=5e-6, tol_lin=1e-6, maxit_outer=1)
+    runs = [lib.bw_lowest_modes(R, ks, 12, **kw) for _ in range(2)]
+    print(f"\n[case] cu64 Lanczos 16 wave vectors, one cycle: pcg {[r[3]['pcg_iterations'] for r in runs]}",
+          flush=True)
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][3]["pcg_iterations"] == runs[1][3]["pcg_iterations"]
+    R.close()
