@@ -557,6 +557,20 @@ static void write_modes(bw_rve* r, const KOut& ko, int nmodes, void* modes, int 
 // the same subspace as implicit restarts with the unwanted Ritz values as
 // exact shifts).  Converged wave vectors leave the batch.
 // ---------------------------------------------------------------------------
+// 64-bit seed from the bits of a wave vector (splitmix64 finalizer per component).
+static unsigned long long wave_vector_seed(const double* k) {
+  unsigned long long h = 0x2106124870ULL;
+  for (int a = 0; a < 3; ++a) {
+    unsigned long long b;
+    std::memcpy(&b, k + a, sizeof(b));
+    h = (h ^ b) + 0x9e3779b97f4a7c15ULL;
+    h = (h ^ (h >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    h = (h ^ (h >> 27)) * 0x94d049bb133111ebULL;
+    h ^= h >> 31;
+  }
+  return h;
+}
+
 template <typename T>
 static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, const EigOpts& o, double* omega,
                          double* err, void* modes, int kofs, Counters& cnt, hipStream_t s) {
@@ -657,7 +671,11 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
   // so that the Krylov space is not confined to the reference plane waves: for a
   // homogeneous cell they are exact eigenvectors and the iteration would break
   // down after four steps
-  launch_add_hash<T>(B, n3, n3, nk, 0x2106124870ULL, 1e-3 / std::sqrt((double)n3), s);
+  // The seed is a function of the wave vector itself, so that a wave vector's start
+  // (and result) does not depend on the batch it is solved in.
+  for (int k = 0; k < nk; ++k)
+    launch_add_hash<T>(B + (size_t)k * n3, n3, n3, 1, wave_vector_seed(k_list + 3 * k), 1e-3 / std::sqrt((double)n3),
+                       s);
   apply_M_blk<T>(r, B, MF, nk, false, cnt, s);
   deflate_batch(B, MF, act);
   launch_dots<T>(B, MF, nk, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);

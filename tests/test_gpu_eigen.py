@@ -213,7 +213,9 @@ def test_lanczos_batch_repeats_bit_for_bit(lib):
     equal frequencies and PCG iteration totals bit for bit.  Two of a wave vector's
     start plane waves may share a voxel (two polarizations of one wave): they are
     summed before the start vectors are written, one element per thread, so no two
-    threads of different wavefronts write the same element."""
+    threads of different wavefronts write the same element.  The start vector's small
+    pseudo-random part is seeded by the wave vector itself, so a wave vector solved
+    alone (same basis length: not Gamma) gives its row of the batch bit for bit."""
     rve = inputs.workload_rve(2, 0)
     ks = inputs.workload_kpoints(2)[:16]
     R = lib.Rve.from_inputs(rve, lib.BW_MIXED)
@@ -223,4 +225,8 @@ def test_lanczos_batch_repeats_bit_for_bit(lib):
           flush=True)
     assert np.array_equal(runs[0][0], runs[1][0])
     assert runs[0][3]["pcg_iterations"] == runs[1][3]["pcg_iterations"]
+    for i in (5, 10):
+        assert np.linalg.norm(ks[i]) > 0
+        w1 = lib.bw_lowest_modes(R, ks[i:i + 1], 12, **kw)[0]
+        assert np.array_equal(w1[0], runs[0][0][i]), i
     R.close()
