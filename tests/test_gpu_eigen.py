@@ -230,3 +230,21 @@ def test_lanczos_batch_repeats_bit_for_bit(lib):
         w1 = lib.bw_lowest_modes(R, ks[i:i + 1], 12, **kw)[0]
         assert np.array_equal(w1[0], runs[0][0][i]), i
     R.close()
+
+
+def test_lanczos_batch_split_matches_one_batch(lib):
+    """Eight wave vectors of the 64^3 workload to convergence (mixed path, bound-based
+    stopping), once as one batch and once split into batches of 3 (`kbatch`): every step
+    of the batched Lanczos is per wave vector, so frequencies and error bounds agree bit
+    for bit."""
+    rve = inputs.workload_rve(2, 0)
+    ks = inputs.workload_kpoints(2)[1:9]
+    R = lib.Rve.from_inputs(rve, lib.BW_MIXED)
+    kw = dict(method=lib.BW_LANCZOS, tol_omega=5e-6, tol_lin=1e-6)
+    w0, e0, c0, s0 = lib.bw_lowest_modes(R, ks, 12, **kw)
+    w1, e1, c1, s1 = lib.bw_lowest_modes(R, ks, 12, kbatch=3, **kw)
+    print(f"\n[case] cu64 Lanczos 8 wave vectors, one batch vs batches of 3: pcg {s0['pcg_iterations']} vs "
+          f"{s1['pcg_iterations']}", flush=True)
+    assert c0 == 0 and c1 == 0, lib.bw_last_error()
+    assert np.array_equal(w0, w1) and np.array_equal(e0, e1)
+    R.close()
