@@ -496,11 +496,14 @@ __device__ __forceinline__ void fft64_dit_pair(cplx<T> (&a)[8], cplx<T> (&b)[8],
 // passes of K in one read and one write of the work array.
 //
 // One workgroup per CU holds a plane in registers (two planes would not fit the
-// register file).  The workgroups are persistent: plane p = blockIdx.x,
-// blockIdx.x + gridDim.x, ... (planes of inactive vectors skipped), and as soon
-// as a component pair of plane p is stored, the same registers receive that
-// pair of the next plane, so the loads of the next plane overlap the
-// transforms of this one.
+// register file).  The workgroups are persistent: they take the planes of the
+// active vectors (all vectors when `active` is null) in turn, ordinal a =
+// blockIdx.x, blockIdx.x + gridDim.x, ..., and as soon as a component pair of a
+// plane is stored, the same registers receive that pair of the next plane, so the
+// loads of the next plane overlap the transforms of this one.  The active vectors
+// are first listed in LDS, so that the planes are dealt out evenly whichever
+// vectors have converged (beyond PLANE_LIST vectors the ordinal runs over all
+// planes and those of inactive vectors are skipped).
 // ---------------------------------------------------------------------------
 constexpr int PLANE_NT = 512;       // 64 lines x 8 threads
 // Transposition slot of (i0, i1): row i0, column i1 XOR a swizzle of i0's low
@@ -516,6 +519,7 @@ __device__ __forceinline__ int plane_tslot(int i0, int i1) {
 // grain indices of a plane are loaded when its transforms start, so neither
 // load is waited for in the contraction.
 constexpr int PLANE_CL_MAX = 256;
+constexpr int PLANE_LIST = 256;     // vectors listed in LDS
 template <typename T, int PCG = 0, bool CL = false>
 __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W, int n2, int nplanes, long nvox,
                                                          const uint16_t* __restrict__ gmapT, const T* __restrict__ Ctab,
@@ -526,14 +530,40 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
   __shared__ V lds[2][NB];
   __shared__ V tr[2][64 * 64];        // transpositions of a pair of components (workgroup-wide)
   __shared__ T cl[CL ? PLANE_CL_MAX * 21 : 1];
-  // the next plane of this workgroup at or after q whose vector is active (uniform)
-  const auto next_plane = [&](int q) {
-    while (q < nplanes && active && !active[q / n2]) q += gridDim.x;
-    return q;
-  };
-  int p = next_plane(blockIdx.x);
-  if (p >= nplanes) return;
+  __shared__ int alist[PLANE_LIST];
+  __shared__ int nact_s;
   const int tid = threadIdx.x;
+  const int nvec = nplanes / n2;
+  const bool listed = active != nullptr && nvec <= PLANE_LIST;
+  if (listed) {
+    if (tid < 64) {   // wavefront 0: the active vectors in order
+      int base = 0;
+      for (int c = 0; c < nvec; c += 64) {
+        const int v = c + tid;
+        const bool f = v < nvec && active[v] != 0;
+        const unsigned long long m = __ballot(f);
+        if (f) alist[base + __popcll(m & ((1ull << tid) - 1ull))] = v;
+        base += __popcll(m);
+      }
+      if (tid == 0) nact_s = base;
+    }
+    __syncthreads();
+  }
+  const int nlisted = listed ? nact_s * n2 : 0;
+  // plane of ordinal a (uniform), or nplanes when there is none; unlisted, a is
+  // advanced past the planes of inactive vectors
+  const auto plane_at = [&](int& a) {
+    if (listed) {
+      if (a >= nlisted) return nplanes;
+      const int i = a / n2;
+      return alist[i] * n2 + (a - i * n2);
+    }
+    while (a < nplanes && active && !active[a / n2]) a += gridDim.x;
+    return a < nplanes ? a : nplanes;
+  };
+  int a = blockIdx.x;
+  int p = plane_at(a);
+  if (p >= nplanes) return;
   if (CL)   // with the scale folded in; visible after the first barrier
     for (int i = tid; i < ngrains * 21; i += PLANE_NT) cl[i] = Ctab[i] * scale;
   const T* __restrict__ Cg = CL ? cl : Ctab;
@@ -559,7 +589,8 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
     int line = tid >> 3, j = tid & 7;
     asm volatile("" : "+v"(line), "+v"(j));
     const RowSlotR<64> slot{line * (64 + 8)};
-    const int pn = next_plane(p + gridDim.x);
+    int an = a + gridDim.x;
+    const int pn = plane_at(an);
     const int i2 = p % n2;
     V* Wv = plane_ptr(p);
     int gm[8];                    // grain of point (i0 = j + 8m, i1 = line)
@@ -637,6 +668,7 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
     }
     finish(std::true_type{}, plane_ptr(pn));
     p = pn;
+    a = an;
   }
 }
 
