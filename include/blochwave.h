@@ -76,7 +76,9 @@ typedef struct bw_rve bw_rve;
 typedef struct bw_eig_opts {
   int32_t method;      /* BW_SUBSPACE (default) or BW_LANCZOS                    */
   int32_t block;       /* subspace block q; 0 -> min(2 nmodes, nmodes + 8)       */
-  int32_t ncv;         /* Lanczos basis size; 0 -> max(2 nmodes + 1, 20)         */
+  int32_t ncv;         /* Lanczos basis size; 0 -> max(2 nw + 1, 20), nw = nmodes,
+                          or nmodes - 3 (the rigid translations are not sought)
+                          when every wave vector of the batch is Gamma-like      */
   int32_t maxit_outer; /* outer iterations / restarts per k; 0 -> 200            */
   int32_t maxit_lin;   /* PCG iterations per solve; 0 -> 20000                   */
   int32_t warm_start;  /* subspace: start k from the previous k's Ritz block     */
@@ -91,7 +93,13 @@ typedef struct bw_eig_opts {
                           subspace algorithm with TOL_eig                        */
   int32_t kbatch;      /* Lanczos: wave vectors advanced together (one PCG right-
                           hand side each per Lanczos step); 0 -> as many as fit
-                          in about 48 GB, at most 64; 1 -> one k at a time       */
+                          in about 48 GB, at most 64; 1 -> one k at a time.
+                          Every step is per wave vector (the start vector's
+                          pseudo-random part is seeded by k itself), so a wave
+                          vector's results do not depend on kbatch or on the
+                          other wave vectors of the call, except that with
+                          ncv = 0 a batch of Gamma-like wave vectors only gets
+                          the shorter default basis of nmodes - 3 wanted modes */
 } bw_eig_opts;
 
 /* Statistics of the last solver call (all optional outputs). */
