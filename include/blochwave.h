@@ -87,9 +87,10 @@ typedef struct bw_eig_opts {
                           1e-6 (MIXED inner solves)                              */
   double tol_omega;    /* > 0: stop a wave vector as soon as every wanted mode
                           carries an a-posteriori bound on its relative omega
-                          error <= tol_omega (the inner PCG tolerance then adapts
-                          to the outer residual, never looser than 1e-2 nor
-                          tighter than tol_lin); 0: the err1 / err2 rule of the
+                          error <= tol_omega (with the subspace method the inner
+                          PCG tolerance then adapts to the outer residual, never
+                          looser than 1e-2 nor tighter than tol_lin; Lanczos
+                          keeps tol_lin); 0: the err1 / err2 rule of the
                           subspace algorithm with TOL_eig                        */
   int32_t kbatch;      /* Lanczos: wave vectors advanced together (one PCG right-
                           hand side each per Lanczos step); 0 -> as many as fit
