@@ -212,6 +212,37 @@ def test_pcg_batch_over_persistent_planes_matches_single_solves(lib):
     R.close()
 
 
+def test_pcg_beyond_listed_vectors_matches_split_batches(lib):
+    """260 right-hand sides on 64 x 64 x 16: more vectors than the plane pass lists in LDS,
+    so its workgroups step over all planes and skip those of inactive vectors (every third
+    right-hand side is zero: inactive from the start); the same solves as two batches of 130
+    (listed path) give the same iterations and solutions bit for bit."""
+    torch = _dev()
+    n = (64, 64, 16)
+    rve = inputs.polycrystal(n, (L, L, L), 7, 91, 0)
+    k = np.array([0.3, -0.2, 0.1]) * np.pi / L
+    b = _rand((260, 3) + n, 17)
+    b *= np.linspace(0.5, 2.0, 260)[:, None, None, None, None]
+    b[::3] = 0.0
+    R = lib.Rve.from_inputs(rve, 1)
+    bd = _to_dev(b, 1)
+    xd = torch.zeros_like(bd)
+    code, it, rr = lib.bw_pcg_solve(R, k, bd, xd, 1e-6, 500)
+    assert code == 0 and np.all(rr <= 1e-6)
+    halves = []
+    for h in (slice(0, 130), slice(130, 260)):
+        xh = torch.zeros_like(bd[h])
+        ch, ith, _ = lib.bw_pcg_solve(R, k, bd[h].contiguous(), xh, 1e-6, 500)
+        assert ch == 0 and np.array_equal(ith, it[h])
+        halves.append(xh)
+    xs = torch.cat(halves)
+    print(f"\n[case] pcg 260 rhs 64x64x16 iterations {it.min()}..{it.max()}, bitwise equal to two batches: "
+          f"{bool(torch.equal(xs, xd))}", flush=True)
+    assert torch.equal(xs, xd)
+    assert np.all(it[::3] == 0) and float(xd[::3].abs().max()) == 0.0
+    R.close()
+
+
 def test_pcg_warm_start_and_gamma(lib):
     print("\n[case] pcg gamma", flush=True)
     torch = _dev()
