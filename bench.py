@@ -410,7 +410,7 @@ def cpu_baseline(rve_in, ks, budget_s):
 def main():
     a = _args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+        print(json.dumps({"error": "the solver runs on one GPU; sharding across GPUs is described, not implemented",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import numpy as np
