@@ -187,6 +187,7 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
   cplx<T>* Ap = w.vec(2, (size_t)nvec * n3);
   cplx<T>* W = w.work((size_t)nvec * 6 * g.nvox);
   PcgDev pd = pcg_dev(r, nvec);
+  pd.maxit = maxit;
 
   // x taken as 0: written as 0, so that a right-hand side that never iterates
   // (already converged, e.g. b = 0) returns 0 and the true-residual check sees it
@@ -223,7 +224,9 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
   launch_pcg_restart<T>(r, d_qtab, rv, nvec, pd, pd.mask, s);
   BW_HIP(hipStreamSynchronize(s));
 
-  const int chunk = g.nvox >= (1 << 18) ? 4 : 8;
+  // iterations per host check: a vector stops on the device when it converges or
+  // reaches maxit, so the chunk length only sets how often the host looks
+  const int chunk = 8;
   std::vector<int> its(nvec), mask(nvec, 0), its_prev(nvec, 0);
   int restarts = 0;
   for (;;) {
@@ -235,7 +238,7 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
         // identical arguments every time (per-vector scalars live on the device)
         const std::vector<const void*> key = {(const void*)d_qtab, x, rv, p, Ap, W, pd.rz, pd.partial,
                                               (const void*)(long)nvec, (const void*)(long)chunk,
-                                              (const void*)(long)sizeof(T)};
+                                              (const void*)(long)sizeof(T), (const void*)(long)maxit};
         if (!r->pcg_exec || r->pcg_key != key) {
           // no allocation or free on another thread while this thread captures
           std::lock_guard<std::recursive_mutex> lk(capture_alloc_mutex());
@@ -352,6 +355,7 @@ PcgDev pcg_dev(bw_rve* r, int nvec) {
   pd.mask = ip + 2 * nvec;
   pd.counter = (unsigned*)(ip + 3 * nvec);
   pd.max_blocks = maxb;
+  pd.maxit = 0x7fffffff;
   if (r->pcg_counters_nvec < nvec) {
     BW_HIP(hipMemset(pd.counter, 0, nvec * sizeof(unsigned)));
     r->pcg_counters_nvec = nvec;

@@ -223,6 +223,7 @@ struct PcgDev {
   double* partial;  // [nvec][max_blocks] partial sums (2 per block)
   unsigned* counter;  // [nvec] last-block counters
   int max_blocks;
+  int maxit;        // a vector stops after this many iterations (with the convergence test)
 };
 
 template <typename T>

@@ -170,8 +170,9 @@ static __global__ __launch_bounds__(NT) void k_finalize(int op, int nblk, PcgDev
       pd.beta[v] = old != 0.0 ? tot[0] / old : 0.0;
       pd.rz[v] = tot[0];
       pd.rr[v] = tot[1];
-      pd.iters[v] += 1;
-      if (tot[1] <= pd.bb[v]) pd.active[v] = 0;
+      const int it = pd.iters[v] + 1;
+      pd.iters[v] = it;
+      if (tot[1] <= pd.bb[v] || it >= pd.maxit) pd.active[v] = 0;
     }
   } else if (op == FIN_RESID) {
     double tot[2];

@@ -264,6 +264,26 @@ def test_pcg_warm_start_and_gamma(lib):
         lib.bw_pcg_solve(R, k, _to_dev(b, 0), torch.zeros_like(bd), 1e-10, 100)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pcg_stops_exactly_at_maxit(lib, prec):
+    """maxit is exact: with a tolerance no solve reaches, every right-hand side stops after
+    maxit iterations (5 and 13, not multiples of the iterations run between two host
+    checks), a zero right-hand side after none, and the status is BW_ENOTCONV."""
+    torch = _dev()
+    rve = inputs.polycrystal((16, 16, 16), (L, L, L), 5, 93, 0)
+    k = np.array([0.2, 0.3, -0.1]) * np.pi / L
+    b = _rand((3, 3, 16, 16, 16), 21)
+    b[1] = 0.0
+    R = lib.Rve.from_inputs(rve, prec)
+    for maxit in (5, 13):
+        xd = torch.zeros_like(_to_dev(b, prec))
+        code, it, rr = lib.bw_pcg_solve(R, k, _to_dev(b, prec), xd, 1e-30, maxit)
+        print(f"\n[case] pcg maxit {maxit} prec={prec}: iterations {it}, status {code}", flush=True)
+        assert code == lib.BW_ENOTCONV
+        assert it.tolist() == [maxit, 0, maxit]
+    R.close()
+
+
 def test_invalid_arguments(lib):
     rve = inputs.polycrystal((8, 8, 8), (L, L, L), 3, 96, 2)
     with pytest.raises(lib.BlochwaveError):
