@@ -547,16 +547,6 @@ static void write_modes(bw_rve* r, const KOut& ko, int nmodes, void* modes, int 
   BW_HIP(hipStreamSynchronize(s));
 }
 
-// ---------------------------------------------------------------------------
-// batched thick-restart shift-invert Lanczos (Sec. 3.3, implicitly restarted
-// Lanczos on the shifted-inverse operator).  Every wave vector of the batch
-// runs its own Lanczos process on OP = K(k)^-1 M in the M inner product with
-// full re-orthogonalization; the solves of one Lanczos step of all of them
-// share one batched PCG (one right-hand side per wave vector).  A restart
-// keeps the leading Ritz vectors and the residual direction (thick restart:
-// the same subspace as implicit restarts with the unwanted Ritz values as
-// exact shifts).  Converged wave vectors leave the batch.
-// ---------------------------------------------------------------------------
 // 64-bit seed from the bits of a wave vector (splitmix64 finalizer per component).
 static unsigned long long wave_vector_seed(const double* k) {
   unsigned long long h = 0x2106124870ULL;
@@ -571,6 +561,16 @@ static unsigned long long wave_vector_seed(const double* k) {
   return h;
 }
 
+// ---------------------------------------------------------------------------
+// batched thick-restart shift-invert Lanczos (Sec. 3.3, implicitly restarted
+// Lanczos on the shifted-inverse operator).  Every wave vector of the batch
+// runs its own Lanczos process on OP = K(k)^-1 M in the M inner product with
+// full re-orthogonalization; the solves of one Lanczos step of all of them
+// share one batched PCG (one right-hand side per wave vector).  A restart
+// keeps the leading Ritz vectors and the residual direction (thick restart:
+// the same subspace as implicit restarts with the unwanted Ritz values as
+// exact shifts).  Converged wave vectors leave the batch.
+// ---------------------------------------------------------------------------
 template <typename T>
 static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, const EigOpts& o, double* omega,
                          double* err, void* modes, int kofs, Counters& cnt, hipStream_t s) {
