@@ -169,6 +169,16 @@ static void reference_start(const bw_rve* r, const QTable& qt, int count, std::v
   }
 }
 
+// The entries written by launch_set_entries must address distinct elements (one
+// thread per element): checked on the host lists before they are uploaded.
+static void require_distinct_entries(const std::vector<long>& vec, const std::vector<long>& vox) {
+  std::vector<std::pair<long, long>> pr(vec.size());
+  for (size_t i = 0; i < vec.size(); ++i) pr[i] = {vec[i], vox[i]};
+  std::sort(pr.begin(), pr.end());
+  BW_REQUIRE(std::adjacent_find(pr.begin(), pr.end()) == pr.end(), BW_EINVAL,
+             "internal: two start-vector entries address the same element");
+}
+
 // ---------------------------------------------------------------------------
 // per-k subspace iteration
 // ---------------------------------------------------------------------------
@@ -355,6 +365,7 @@ static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigO
     std::vector<double> pol;
     reference_start(r, qt, nf, vox, pol);
     for (int i = 0; i < nf; ++i) vec[i] = keep + i;
+    require_distinct_entries(vec, vox);
     h2d(sm.vox, vox.data(), nf * sizeof(long), s);
     h2d(sm.vox + 128, vec.data(), nf * sizeof(long), s);
     h2d(sm.pol, pol.data(), 3 * nf * sizeof(double), s);
@@ -658,6 +669,7 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
         for (int c = 0; c < 3; ++c) val[3 * at + c] += pl[3 * e + c] * (e == 0 ? 1.0 : 0.1);
       }
     }
+    require_distinct_entries(vec, vox);
     for (size_t e0 = 0; e0 < vec.size(); e0 += 80) {
       const int ne = (int)std::min<size_t>(80, vec.size() - e0);
       h2d(sm.vox, vox.data() + e0, ne * sizeof(long), s);
