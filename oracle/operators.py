@@ -26,9 +26,10 @@ from __future__ import annotations
 
 import numpy as np
 
-from paper_2106_12487_amd.inputs import RVE, c21_to_voigt, voigt_to_tensor
+from paper_2106_12487_amd.inputs import RVE
 
 from .fourier import fft3, ifft3, shifted_wavevector
+from .voigt import c21_to_voigt, voigt_to_tensor
 
 
 class Operators:

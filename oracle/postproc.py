@@ -53,11 +53,10 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from paper_2106_12487_amd.inputs import voigt_to_tensor
-
 from .fourier import fft3, ifft3
 from .operators import Operators
 from .solvers import lowest_modes, pcg
+from .voigt import voigt_to_tensor
 
 
 def _strain_const(d, U):

@@ -176,20 +176,29 @@ def c_axis_texture(tilt: np.ndarray, psi: np.ndarray) -> np.ndarray:
 # --------------------------------------------------------------------------
 # periodic Voronoi
 # --------------------------------------------------------------------------
-def voronoi_grain_map(n, L, seeds: np.ndarray, chunk: int = 1 << 16) -> np.ndarray:
+def voronoi_grain_map(n, L, seeds: np.ndarray, chunk: int = 1 << 16, candidates: int = 8) -> np.ndarray:
     """Nearest seed (minimum-image Euclidean distance) of each voxel centre.
 
-    Ties go to the lowest seed index.  Returns uint16 [n0, n1, n2].
+    Ties go to the lowest seed index.  Returns uint16 [n0, n1, n2].  A periodic
+    k-d tree proposes the `candidates` nearest seeds of each voxel; the minimum-image
+    distances to those are then compared exactly as for the full set (the true
+    nearest seed, and any seed within rounding of it, is always among them).
     """
+    from scipy.spatial import cKDTree
     n = tuple(int(v) for v in n)
     L = np.asarray(L, dtype=np.float64)
     axes = [(np.arange(n[a]) + 0.5) * (L[a] / n[a]) for a in range(3)]
     X = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    kc = min(candidates, seeds.shape[0])
+    tree = cKDTree(np.mod(seeds, L), boxsize=L)
     out = np.empty(X.shape[0], dtype=np.uint16)
     for s in range(0, X.shape[0], chunk):
-        d = X[s:s + chunk, None, :] - seeds[None, :, :]
+        _, cand = tree.query(X[s:s + chunk], k=kc)
+        cand = np.sort(np.asarray(cand).reshape(-1, kc), axis=1)      # ascending seed index
+        d = X[s:s + chunk, None, :] - seeds[cand]
         d -= L * np.round(d / L)
-        out[s:s + chunk] = np.argmin(np.einsum("vgk,vgk->vg", d, d), axis=1)
+        best = np.argmin(np.einsum("vgk,vgk->vg", d, d), axis=1)
+        out[s:s + chunk] = cand[np.arange(cand.shape[0]), best]
     return out.reshape(n)
 
 

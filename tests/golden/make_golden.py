@@ -7,6 +7,12 @@ here touches the HIP path.  Usage:
     python tests/golden/make_golden.py cu64      # 64^3, 64 grains, sampled k of the path (Lanczos)
     python tests/golden/make_golden.py cual32    # 32^3 Cu/Al cell of the uneven workload, 4 k (Lanczos)
     python tests/golden/make_golden.py fibre128  # 128 x 128 x 1 epoxy / 55% circular carbon fibres, 4 k (Lanczos)
+    python tests/golden/make_golden.py ti128:11  # 128^3 / 512-grain textured Ti, one path index per process
+    python tests/golden/make_golden.py ti128-merge  # joins the ti128 parts into ti128.json
+
+The 128^3 Ti set takes one to three hours per wave vector on a few host cores, so each
+wave vector runs in a process of its own (tests/golden/ti128_k<index>.json) and the
+parts are joined afterwards.
 
 Output: tests/golden/<name>.json with the wave vectors (rad/m), omega (rad/s)
 and the oracle settings.
@@ -33,8 +39,27 @@ def nearest_path_indices(config, labels):
     return [int(np.argmin(np.linalg.norm(ks - P[c], axis=1))) for c in labels]
 
 
+TI128_INDICES = [11, 22, 58]   # next to X on Gamma-X, next to M on X-M, next to R on Gamma-R
+
+
+def merge_ti128():
+    """Joins the per-wave-vector parts of the 128^3 Ti set (same settings) into ti128.json."""
+    parts = []
+    for i in TI128_INDICES:
+        with open(os.path.join(HERE, f"ti128_k{i}.json")) as f:
+            parts.append(json.load(f))
+    out = {key: parts[0][key] for key in ("config", "nmodes", "block", "method", "tol_eig", "tol_lin")}
+    out["name"] = "ti128"
+    for key in ("k_index", "k", "omega", "seconds", "pcg_iters", "outer"):
+        out[key] = [v for p in parts for v in p[key]]
+    with open(os.path.join(HERE, "ti128.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def run(name):
     method = "subspace"
+    tol = 1e-12
     if name == "cu16":
         cfg, nmodes, block = 1, 6, 12
         idx = list(range(11))
@@ -55,6 +80,14 @@ def run(name):
         cfg, nmodes, block = None, 10, 16
         idx = [18, 50, 60, 75]
         method = "lanczos"
+    elif name.startswith("ti128:"):
+        # the large textured workload: 128^3, 512 grains, hexagonal Ti with a c-axis
+        # texture; 12 modes at one wave vector next to a symmetry point of the path
+        cfg, nmodes, block = 4, 12, 16
+        idx = [int(name.split(":")[1])]
+        name = f"ti128_k{idx[0]}"
+        method = "lanczos"
+        tol = 1e-11
     else:
         raise SystemExit(f"unknown golden set {name}")
     if cfg is None:
@@ -63,14 +96,14 @@ def run(name):
     else:
         rve = inputs.workload_rve(cfg, 0)
         ks = inputs.workload_kpoints(cfg)[idx]
-    out = dict(name=name, config=cfg, nmodes=nmodes, block=block, method=method, tol_eig=1e-12, tol_lin=1e-12,
+    out = dict(name=name, config=cfg, nmodes=nmodes, block=block, method=method, tol_eig=tol, tol_lin=tol,
                k_index=idx, k=ks.tolist(), omega=[], seconds=[], pcg_iters=[], outer=[])
     path = os.path.join(HERE, f"{name}.json")
     for i, k in enumerate(ks):
         t = time.time()
         st = []
         w = solvers.lowest_modes(rve, k[None], nmodes, method=method, block=block,
-                                 tol_eig=1e-12, tol_lin=1e-12, dense_max=0, warm_start=False, stats=st)
+                                 tol_eig=tol, tol_lin=tol, dense_max=0, warm_start=False, stats=st)
         out["omega"].append(w[0].tolist())
         out["pcg_iters"].append(int(st[0]["pcg_iters"]))
         out["outer"].append(int(st[0].get("outer", st[0].get("restarts", 0))))
@@ -83,4 +116,7 @@ def run(name):
 
 if __name__ == "__main__":
     for n in sys.argv[1:]:
-        run(n)
+        if n == "ti128-merge":
+            merge_ti128()
+        else:
+            run(n)

@@ -31,6 +31,31 @@ def test_voronoi_brute_force_small():
         assert g[idx] == best
 
 
+def _voronoi_all_seeds(n, Lv, seeds):
+    """Every voxel against every seed (minimum image), lowest index on ties."""
+    axes = [(np.arange(n[a]) + 0.5) * (Lv[a] / n[a]) for a in range(3)]
+    X = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    d = X[:, None, :] - seeds[None, :, :]
+    d -= np.asarray(Lv) * np.round(d / np.asarray(Lv))
+    return np.argmin(np.einsum("vgk,vgk->vg", d, d), axis=1).reshape(n)
+
+
+def test_voronoi_candidates_match_all_seeds():
+    # the k-d tree only proposes candidates; the assignment equals the comparison with
+    # every seed, on an uneven grid with many grains and on exact ties (lowest index wins)
+    rng = np.random.default_rng(7)
+    seeds = rng.random((300, 3)) * np.array([L, 2 * L, L])
+    n = (24, 40, 17)
+    assert np.array_equal(inputs.voronoi_grain_map(n, (L, 2 * L, L), seeds),
+                          _voronoi_all_seeds(n, (L, 2 * L, L), seeds))
+    # unit cell, seeds at x = 1/4 and 3/4: the voxel plane x = 1/2 of a 3-voxel grid is
+    # exactly equidistant (and so is x = 1/6 vs 5/6 through the periodic image)
+    tie = np.array([[0.75, 0.5, 0.5], [0.25, 0.5, 0.5]])
+    g = inputs.voronoi_grain_map((3, 2, 2), (1.0, 1.0, 1.0), tie)
+    assert np.array_equal(g, _voronoi_all_seeds((3, 2, 2), (1.0, 1.0, 1.0), tie))
+    assert np.all(g[1] == 0)
+
+
 def test_haar_rotations_are_rotations_and_unbiased():
     R = inputs.haar_rotations(np.random.default_rng(0).random((4000, 3)))
     assert np.allclose(np.einsum("nij,nkj->nik", R, R), np.eye(3), atol=1e-12)

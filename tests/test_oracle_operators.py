@@ -156,3 +156,29 @@ def test_near_reciprocal_lattice_wave_vector_is_snapped():
     assert int(ops.null_mask.sum()) == 1
     w = np.linalg.eigvalsh(ops.dense("K"))
     assert np.sum(np.abs(w) <= 1e-9 * w.max()) == 3
+
+
+def test_oracle_voigt_maps():
+    """The oracle's own Voigt <-> tensor maps: the isotropic tensor from its Lame
+    constants, the minor and major symmetries, and the 21 <-> 6x6 round trip."""
+    from oracle import voigt
+    lam_, mu = 51.0e9, 26.0e9
+    d = np.eye(3)
+    iso = (lam_ * np.einsum("ij,kl->ijkl", d, d)
+           + mu * (np.einsum("ik,jl->ijkl", d, d) + np.einsum("il,jk->ijkl", d, d)))
+    C6 = np.zeros((6, 6))
+    C6[:3, :3] = lam_
+    C6[[0, 1, 2], [0, 1, 2]] = lam_ + 2 * mu
+    C6[[3, 4, 5], [3, 4, 5]] = mu
+    assert np.array_equal(voigt.voigt_to_tensor(C6), iso)
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((6, 6))
+    S = A + A.T
+    T = voigt.voigt_to_tensor(S)
+    assert np.array_equal(T, T.transpose(1, 0, 2, 3)) and np.array_equal(T, T.transpose(0, 1, 3, 2))
+    assert np.array_equal(T, T.transpose(2, 3, 0, 1))
+    assert T[1, 2, 0, 1] == S[3, 5] and T[0, 2, 2, 2] == S[4, 2]
+    c21 = S[np.triu_indices(6)]
+    assert np.array_equal(voigt.c21_to_voigt(c21), S)
+    # the row-major upper-triangle order: entry 6 is (1, 1), entry 11 is (2, 2)
+    assert voigt.c21_to_voigt(np.arange(21.0))[1, 1] == 6 and voigt.c21_to_voigt(np.arange(21.0))[2, 2] == 11
