@@ -31,14 +31,24 @@ struct EigOpts {
   int kbatch;
 };
 
-// Relative omega bound from a residual norm in the M^-1 norm: Kato-Temple when
-// the Ritz gap allows it, else the residual bound itself.
-static double omega_bound(double res, const std::vector<double>& lam, int p, int q) {
+// Relative omega bound of Ritz pair p from the residual norms res[0 .. nres) of
+// the Ritz pairs (M^-1 norm): Kato-Temple where the gap allows it, else the
+// residual bound itself.  The gap to a neighbouring Ritz value theta_j is taken
+// less that pair's own residual norm (an eigenvalue lies within res[j] of
+// theta_j, whereas theta_j alone only bounds the next eigenvalue from above and
+// can overstate the gap); pairs whose residual is not known (j >= nres) are not
+// used, and without a known neighbour above p the residual bound is returned.
+static double omega_bound(const double* res, int nres, const std::vector<double>& lam, int p) {
+  const double rp = res[p];
   double gap = INFINITY;
-  for (int j = 0; j < q; ++j)
-    if (j != p) gap = std::min(gap, std::fabs(lam[j] - lam[p]));
-  double dl = res;
-  if (gap > 2 * res) dl = std::min(res, res * res / (gap - res));
+  bool above = false;
+  for (int j = 0; j < nres; ++j) {
+    if (j == p) continue;
+    gap = std::min(gap, std::fabs(lam[j] - lam[p]) - res[j]);
+    if (j > p) above = true;
+  }
+  double dl = rp;
+  if (above && gap > rp) dl = std::min(rp, rp * rp / gap);
   return lam[p] > 0 ? 0.5 * dl / lam[p] : dl;
 }
 
@@ -161,6 +171,10 @@ static void reference_start(const bw_rve* r, const QTable& qt, int count, std::v
     if (a.v != b.v) return a.v < b.v;
     return a.p < b.p;
   });
+  // a Gamma-like k has 3 N - 3 plane waves (the xi + k = 0 voxel carries none)
+  BW_REQUIRE(count >= 0 && (size_t)count <= es.size(), BW_EINVAL,
+             "more start vectors (" + std::to_string(count) + ") than reference plane waves (" +
+                 std::to_string(es.size()) + ")");
   vox.resize(count);
   pol.resize(3 * count);
   for (int i = 0; i < count; ++i) {
@@ -230,6 +244,8 @@ static void rr64_bounds(bw_rve* r, const double* dq, cplx<double>*& U, int q, in
   cplx<double>* R = w.vec(9, (size_t)q * n3);
   cplx<double>* Z = w.vec(11, (size_t)q * n3);
   lam.resize(q);
+  // residuals of the wanted pairs and of the next one (its gap enters the bound)
+  const int nr = n_want > 0 ? std::min(q, n_want + 1) : 0;
   if (do_rr) {
     cplx<double>* U2 = w.vec(4, (size_t)q * n3);
     cplx<double>* KU0 = w.vec(5, (size_t)q * n3);
@@ -242,8 +258,8 @@ static void rr64_bounds(bw_rve* r, const double* dq, cplx<double>*& U, int q, in
     launch_gram<double>(U, q, MU0, q, n3, n3, sm.Mq, r->ws_red, r->d_ctr, s);
     launch_small_geig(sm.Kq, sm.Mq, q, sm.lam, sm.Q, sm.info, s);
     launch_ritz<double>(U, q, sm.Q, q, U2, q, n3, n3, s);
-    launch_ritz<double>(KU0, q, sm.Q, q, KU1, n_want, n3, n3, s);
-    launch_ritz<double>(MU0, q, sm.Q, q, MU1, n_want, n3, n3, s);
+    launch_ritz<double>(KU0, q, sm.Q, q, KU1, nr, n3, n3, s);
+    launch_ritz<double>(MU0, q, sm.Q, q, MU1, nr, n3, n3, s);
     std::swap(w.v[3], w.v[4]);
     U = (cplx<double>*)w.v[3].p;
     KU = KU1;
@@ -251,20 +267,22 @@ static void rr64_bounds(bw_rve* r, const double* dq, cplx<double>*& U, int q, in
   } else {
     h2d(sm.lam, lam.data(), q * sizeof(double), s);
   }
-  launch_lincomb<double>(KU, MU, sm.lam, R, n_want, n3, n3, s);
-  apply_M_blk<double>(r, R, Z, n_want, true, cnt, s);
-  launch_dots<double>(R, Z, n_want, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
-  std::vector<double2> rn(n_want);
+  launch_lincomb<double>(KU, MU, sm.lam, R, nr, n3, n3, s);
+  apply_M_blk<double>(r, R, Z, nr, true, cnt, s);
+  launch_dots<double>(R, Z, nr, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
+  std::vector<double2> rn(nr);
   int info = 0;
   if (do_rr) {
     BW_HIP(hipMemcpyAsync(lam.data(), sm.lam, q * sizeof(double), hipMemcpyDeviceToHost, s));
     BW_HIP(hipMemcpyAsync(&info, sm.info, sizeof(int), hipMemcpyDeviceToHost, s));
   }
-  BW_HIP(hipMemcpyAsync(rn.data(), sm.dots, n_want * sizeof(double2), hipMemcpyDeviceToHost, s));
+  if (nr > 0) BW_HIP(hipMemcpyAsync(rn.data(), sm.dots, nr * sizeof(double2), hipMemcpyDeviceToHost, s));
   BW_HIP(hipStreamSynchronize(s));
   BW_REQUIRE(info == 0, BW_EINVAL, "Rayleigh-Ritz Gram matrix not positive definite");
+  std::vector<double> res(nr);
+  for (int p = 0; p < nr; ++p) res[p] = std::sqrt(std::max(rn[p].x, 0.0));
   bound.assign(n_want, 0.0);
-  for (int p = 0; p < n_want; ++p) bound[p] = omega_bound(std::sqrt(std::max(rn[p].x, 0.0)), lam, p, q);
+  for (int p = 0; p < n_want; ++p) bound[p] = omega_bound(res.data(), nr, lam, p);
 }
 
 // FP64 refinement of a block of Ritz vectors (mixed-precision path): FP64
@@ -293,6 +311,12 @@ static void refine64(bw_rve* r, const double* dq, const QTable& qt, long jstar, 
       launch_convert<double, float>(R, (cplx<float>*)Rt, (size_t)n_want * n3, s);
     else
       BW_HIP(hipMemcpyAsync(Rt, R, (size_t)n_want * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
+    // At a Gamma-like k, K D = R is solvable only for the part of R orthogonal to
+    // null(K) (the rigid translations, i.e. the xi + k = 0 coefficients).  R has a
+    // component there at the rounding level of the block's M-orthogonality to the
+    // translations, which the preconditioned iteration cannot reduce (P^ is zero
+    // at that voxel): left in, it holds the residual above the tolerance until maxit.
+    if (jstar >= 0) zero_voxel<T>(Rt, n_want, r->g.nvox, jstar, s);
     BW_HIP(hipMemsetAsync(D, 0, (size_t)n_want * n3 * sizeof(cplx<T>), s));
     PcgResult pr = pcg_run<T>(r, dq, qt, Rt, D, n_want, sizeof(T) == 4 ? 1e-6 : 1e-10, 2000, true, s, false, false);
     cnt.pcg_iters += pr.total_iters;
@@ -431,15 +455,16 @@ static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigO
     apply_K_blk<T>(r, dq, U, KU, q, cnt, s);
     launch_lincomb<T>(KU, MU, sm.lam, R, q, n3, n3, s);                    // R = K U - lambda M U
     have_KU = true;
-    launch_dots<T>(R, R, nw, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
-    launch_dots<T>(MU, MU, nw, n3, n3, sm.dots + 128, r->ws_red2, r->d_ctr + 320, s);
-    std::vector<double2> rr(nw), mm(nw);
+    const int nr = std::min(q, nw + 1);   // the wanted pairs and the next one
+    launch_dots<T>(R, R, nr, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
+    launch_dots<T>(MU, MU, nr, n3, n3, sm.dots + 128, r->ws_red2, r->d_ctr + 320, s);
+    std::vector<double2> rr(nr), mm(nr);
     int info = 0;
     BW_HIP(hipMemcpyAsync(lam.data(), sm.lam, q * sizeof(double), hipMemcpyDeviceToHost, s));
     BW_HIP(hipMemcpyAsync(&info, sm.info, sizeof(int), hipMemcpyDeviceToHost, s));
     if (nw > 0) {
-      BW_HIP(hipMemcpyAsync(rr.data(), sm.dots, nw * sizeof(double2), hipMemcpyDeviceToHost, s));
-      BW_HIP(hipMemcpyAsync(mm.data(), sm.dots + 128, nw * sizeof(double2), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipMemcpyAsync(rr.data(), sm.dots, nr * sizeof(double2), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipMemcpyAsync(mm.data(), sm.dots + 128, nr * sizeof(double2), hipMemcpyDeviceToHost, s));
     }
     BW_HIP(hipStreamSynchronize(s));
     BW_REQUIRE(info == 0, BW_EINVAL, "subspace Gram matrix lost positive definiteness (block rank deficient)");
@@ -468,8 +493,9 @@ static KOut subspace_k(bw_rve* r, const double* k, int nmodes, int q, const EigO
     bool bounds_ok = false;
     if (o.tol_omega > 0 && nw > 0) {
       double worst = 0;
-      for (int p = 0; p < nw; ++p)
-        worst = std::max(worst, omega_bound(std::sqrt(std::max(rr[p].x, 0.0) / r->rho_min_s), lam, p, q));
+      std::vector<double> res(nr);
+      for (int p = 0; p < nr; ++p) res[p] = std::sqrt(std::max(rr[p].x, 0.0) / r->rho_min_s);
+      for (int p = 0; p < nw; ++p) worst = std::max(worst, omega_bound(res.data(), nr, lam, p));
       bounds_ok = worst <= o.tol_omega && std::isfinite(err1);
     }
     const bool rule = o.tol_omega > 0 ? (bounds_ok || (fp32 && stalled && err1 <= tol))
@@ -716,6 +742,10 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       for (int k = 0; k < nk; ++k) sc[k] = act[k] ? 1.0 : 0.0;
       upload_sc();
       launch_scale_copy<T>(MV + (size_t)j * n3, xk, B, n3, scd, nk, n3, nullptr, s);
+      // M v_j has no xi + k = 0 part for v_j M-orthogonal to the rigid translations;
+      // drop the rounding left there, which the preconditioned iteration cannot reduce
+      for (int k = 0; k < nk; ++k)
+        if (act[k] && qt.null_index[k] >= 0) zero_voxel<T>(B + (size_t)k * n3, 1, g.nvox, qt.null_index[k], s);
       PcgResult pr = pcg_run<T>(r, dq, qt, B, X, nk, fp32 ? std::max(o.tol_lin, 1e-6) : o.tol_lin, o.maxit_lin,
                                 true, s, false, false);
       cnt.pcg_iters += pr.total_iters;
@@ -933,6 +963,11 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
     if (o.method == BW_SUBSPACE) {
       BW_REQUIRE(o.block > nmodes && o.block <= GRAM_QMAX, BW_EINVAL, "block must satisfy nmodes < block <= 32");
       BW_REQUIRE((long)o.block <= 3 * r->g.nvox, BW_EINVAL, "block larger than the number of degrees of freedom");
+      // at a Gamma-like k the rigid translations leave 3 N - 3 degrees of freedom
+      const QTable qt = make_qtable(r, k_list, nk);
+      for (int k = 0; k < nk; ++k)
+        BW_REQUIRE(qt.null_index[k] < 0 || (long)o.block <= 3 * r->g.nvox - 3, BW_EINVAL,
+                   "block larger than the degrees of freedom at a Gamma-like wave vector (3 N - 3)");
     }
     hipStream_t s = (hipStream_t)stream;
     r->ws_red.get(16u << 20);
@@ -993,6 +1028,13 @@ extern "C" int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const 
     BW_REQUIRE(nrve >= 0 && nrve <= 256, BW_EINVAL, "nrve out of range (0 .. 256)");
     for (int i = 0; i < nrve; ++i)
       BW_REQUIRE(rves[i] && (nks[i] == 0 || (k_lists[i] && omegas[i])), BW_EINVAL, "null cell argument");
+    {
+      // one host thread per cell: a handle is not thread-safe, so each may appear once
+      std::vector<const bw_rve*> hs(rves, rves + nrve);
+      std::sort(hs.begin(), hs.end());
+      BW_REQUIRE(std::adjacent_find(hs.begin(), hs.end()) == hs.end(), BW_EINVAL,
+                 "the same cell handle appears twice in the batch");
+    }
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t cs = (hipStream_t)stream;
     // work already queued on the caller's stream precedes the batch

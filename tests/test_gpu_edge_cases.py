@@ -110,3 +110,32 @@ def test_eight_voxel_cell_lanczos_matches_dense_oracle(lib, prec):
               flush=True)
         assert np.abs(w[i] - ref).max() <= (1e-9 if prec == 0 else 1e-5) * scale
     R.close()
+
+
+def test_block_beyond_gamma_degrees_of_freedom_is_refused(lib):
+    """At Gamma a 2-voxel cell has 3 N - 3 = 3 degrees of freedom besides the rigid
+    translations: a subspace block of 5 (valid off Gamma) is refused before any
+    kernel runs, in a call that mixes Gamma with another wave vector too."""
+    rve = inputs.polycrystal((2, 1, 1), (L, L, L), 2, 86, 0)
+    R = lib.Rve.from_inputs(rve, 0)
+    print("\n[case] 2-voxel Gamma, block 5", flush=True)
+    for ks in ([[0.0, 0.0, 0.0]], [[0.37 * np.pi / L, 0.0, 0.0], [0.0, 0.0, 0.0]]):
+        with pytest.raises(lib.BlochwaveError) as e:
+            lib.bw_lowest_modes(R, ks, 4, method=0, block=5)
+        assert e.value.code == lib.BW_EINVAL and "Gamma" in str(e.value)
+    # off Gamma the same block is valid
+    w, _, code, _ = lib.bw_lowest_modes(R, [[0.37 * np.pi / L, 0.0, 0.0]], 4, method=0, block=5)
+    assert code == 0 and np.all(w > 0)
+    R.close()
+
+
+def test_batched_call_refuses_a_repeated_handle(lib):
+    """A handle is not thread-safe and the batched call runs one host thread per cell:
+    the same handle twice is refused before any thread or stream is created."""
+    R = lib.Rve.from_inputs(inputs.polycrystal((8, 8, 8), (L, L, L), 4, 96, 0), 1)
+    k = [[0.2 * np.pi / L, 0.0, 0.0]]
+    print("\n[case] batched [R, R]", flush=True)
+    with pytest.raises(lib.BlochwaveError) as e:
+        lib.bw_lowest_modes_batched([R, R], [k, k], 4, method=0, block=8)
+    assert e.value.code == lib.BW_EINVAL and "twice" in str(e.value)
+    R.close()
