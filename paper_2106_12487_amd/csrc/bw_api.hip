@@ -221,7 +221,7 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
   h2d(pd.active, act.data(), nvec * sizeof(int), s);
   h2d(pd.mask, act.data(), nvec * sizeof(int), s);
   h2d(pd.iters, it0.data(), nvec * sizeof(int), s);
-  launch_pcg_restart<T>(r, d_qtab, rv, nvec, pd, pd.mask, s);
+  launch_pcg_restart<T>(r, d_qtab, rv, nvec, pd, pd.mask, s, Ap);
   BW_HIP(hipStreamSynchronize(s));
 
   // iterations per host check: a vector stops on the device when it converges or
@@ -277,7 +277,8 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
         for (int v = 0; v < nvec; ++v) d += its[v] - its_prev[v];
         its_prev = its;
         for (const char* nm : {"k_strain_row_pcg", "k_axis1_inv_pcg", "k_axis0_contract_pcg", "k_axis1_fwd_pcg",
-                               "k_plane_contract_pcg", "k_row_div_pcg", "k_pcg_update"})
+                               "k_plane_contract_pcg", "k_row_div_pcg", "k_slab_strain_pcg", "k_slab_div_pcg",
+                               "k_pcg_update"})
           timing_add_units(nm, d);
       }
       bool cap = false;
@@ -313,7 +314,7 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
     act = mask;
     h2d(pd.active, act.data(), nvec * sizeof(int), s);
     h2d(pd.mask, mask.data(), nvec * sizeof(int), s);
-    launch_pcg_restart<T>(r, d_qtab, rv, nvec, pd, pd.mask, s);
+    launch_pcg_restart<T>(r, d_qtab, rv, nvec, pd, pd.mask, s, Ap);
   }
   res.converged = true;
   for (int v = 0; v < nvec; ++v) {
@@ -741,11 +742,17 @@ template <typename T> static double autotune_impl(bw_rve* r, int nvec, hipStream
     r->tune_cap[a] = 0;
   }
   r->tune_plane = 1;
+  r->tune_slab = 1;
   const double t_default = time_apply();
   if (r->d_gmapT && sizeof(T) == 4) {
     r->tune_plane = 0;
     const double t_noplane = time_apply();
     r->tune_plane = t_noplane < t_default ? 0 : 1;
+  }
+  if (slab_path<T>(r)) {
+    r->tune_slab = 0;
+    const double t_noslab = time_apply();
+    r->tune_slab = t_noslab < t_default ? 0 : 1;
   }
   const int n[3] = {g.n0, g.n1, g.n2};
   for (int a : {2, 1, 0}) {
@@ -847,6 +854,7 @@ extern "C" int bw_fft_schedule(bw_rve* r, int32_t reg[3], int32_t cap[3], int32_
   if (set) {
     for (int a = 0; a < 3; ++a) BW_REQUIRE(cap[a] >= 0, BW_EINVAL, "tile cap must be >= 0");
     r->tune_plane = reg[0] && reg[1] ? 1 : 0;
+    r->tune_slab = reg[1] && reg[2] ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
       r->tune_reg[a] = reg[a] ? 1 : 0;
       r->tune_cap[a] = cap[a];

@@ -180,6 +180,7 @@ struct bw_rve {
   int tune_reg[3] = {1, 1, 1};
   int tune_cap[3] = {0, 0, 0};
   int tune_plane = 1;   // FP32 cells with n0 = n1 = 64: the fused plane pass
+  int tune_slab = 1;    // FP32 cells with n1 = n2 = 128: the three-pass slab path
   // captured PCG chunk (replayed with hipGraphLaunch while its key matches)
   hipStream_t cap_stream = nullptr;
   hipGraph_t pcg_graph = nullptr;
@@ -226,9 +227,10 @@ struct PcgDev {
   int maxit;        // a vector stops after this many iterations (with the convergence test)
 };
 
+// (on the FP32 slab path the update also leaves z = P^ r in Ap for the next direction)
 template <typename T>
 void launch_pcg_update(const bw_rve* r, const double* d_qtab, cplx<T>* x, cplx<T>* rv,
-                       const cplx<T>* p, const cplx<T>* Ap, int nvec, const PcgDev& pd,
+                       const cplx<T>* p, cplx<T>* Ap, int nvec, const PcgDev& pd,
                        hipStream_t s);
 // ||r||^2 and ||b||^2 of a given residual (no writes)
 template <typename T>
@@ -239,10 +241,10 @@ template <typename T>
 void launch_residual(const bw_rve* r, const double* d_qtab, const cplx<T>* b, const cplx<T>* x,
                      cplx<T>* rv, cplx<T>* tmp, cplx<T>* W, int nvec, double* d_rr, double* d_bb,
                      double* d_partial, unsigned* d_counter, int max_blocks, hipStream_t s);
-// z = P^ r, <r, z> -> rz, beta = 0 for restart
+// z = P^ r, <r, z> -> rz, beta = 0 for restart (z also written to Ap on the FP32 slab path)
 template <typename T>
 void launch_pcg_restart(const bw_rve* r, const double* d_qtab, const cplx<T>* rv, int nvec,
-                        const PcgDev& pd, const int* d_mask, hipStream_t s);
+                        const PcgDev& pd, const int* d_mask, hipStream_t s, cplx<T>* Ap);
 
 template <typename T>
 void launch_pcg_apply(const bw_rve* r, const double* d_qtab, const cplx<T>* rv, cplx<T>* p, cplx<T>* Ap,

@@ -611,9 +611,10 @@ __global__ __launch_bounds__(NT) void k_apply_P(const cplx<T>* __restrict__ U, c
 
 // x += alpha p; r -= alpha Kp; z = P^ r; <r, z>, ||r||^2; last block: beta,
 // convergence flag (recurrence residual below the threshold).
-template <typename T>
+// WZ: also write z over K p (the next direction update reads it there).
+template <typename T, bool WZ = false>
 __global__ __launch_bounds__(NT) void k_pcg_update(cplx<T>* __restrict__ x, cplx<T>* __restrict__ r,
-                                                   const cplx<T>* __restrict__ p, const cplx<T>* __restrict__ Ap,
+                                                   const cplx<T>* __restrict__ p, cplx<T>* __restrict__ Ap,
                                                    const double* __restrict__ qtab, VoxIdx vi, long nvox, int bpv,
                                                    C21v<T> C0, PcgDev pd) {
   using V = cplx<T>;
@@ -641,6 +642,7 @@ __global__ __launch_bounds__(NT) void k_pcg_update(cplx<T>* __restrict__ x, cplx
     for (int c = 0; c < 3; ++c) {
       rz += (double)rv[c].x * z[c].x + (double)rv[c].y * z[c].y;
       rr += (double)rv[c].x * rv[c].x + (double)rv[c].y * rv[c].y;
+      if (WZ) Ap[((size_t)v * 3 + c) * nvox + vox] = z[c];
     }
   }
   const double vals[2] = {rz, rr};
@@ -691,7 +693,7 @@ __global__ __launch_bounds__(NT) void k_norms2(const cplx<T>* __restrict__ bv, c
 template <typename T>
 __global__ __launch_bounds__(NT) void k_pcg_restart(const cplx<T>* __restrict__ r, const double* __restrict__ qtab,
                                                     VoxIdx vi, long nvox, int bpv, C21v<T> C0, PcgDev pd,
-                                                    const int* __restrict__ mask) {
+                                                    const int* __restrict__ mask, cplx<T>* __restrict__ zout) {
   using V = cplx<T>;
   __shared__ double sh[NT / 64];
   const int v = blockIdx.x / bpv;
@@ -707,7 +709,10 @@ __global__ __launch_bounds__(NT) void k_pcg_restart(const cplx<T>* __restrict__ 
     for (int c = 0; c < 3; ++c) rv[c] = r[((size_t)v * 3 + c) * nvox + vox];
     precond3<T, V>(C0, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], rv, z);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) rz += (double)rv[c].x * z[c].x + (double)rv[c].y * z[c].y;
+    for (int c = 0; c < 3; ++c) {
+      rz += (double)rv[c].x * z[c].x + (double)rv[c].y * z[c].y;
+      if (zout) zout[((size_t)v * 3 + c) * nvox + vox] = z[c];
+    }
   }
   const double vals[1] = {rz};
   store_partials<1>(vals, pd.partial, v, b, pd.max_blocks, sh);
@@ -798,6 +803,7 @@ inline int pw_blocks(long nvox) {
 
 }  // namespace bw
 #include "bw_fftreg.h"
+#include "bw_slab.h"
 namespace bw {
 
 // ---------------------------------------------------------------------------
@@ -813,6 +819,10 @@ template <class F> void with_reg(int n, F&& f) {
     default: throw Error{BW_EUNSUPPORTED, "no register FFT of length " + std::to_string(n)};
   }
 }
+template <typename T, int OP>
+void launch_axis0(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* active, hipStream_t s,
+                  const T* tab_override);
+
 // Middle passes shared by K and M: inverse axis 1, axis-0 op, forward axis 1.
 template <typename T, int OP>
 void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* active, hipStream_t s,
@@ -851,6 +861,17 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
     });
   };
   if (g.n1 > 1) axis1(std::true_type{});
+  launch_axis0<T, OP>(r, W, nvec, scale, active, s, tab_override);
+  if (g.n1 > 1) axis1(std::false_type{});
+}
+
+// Axis-0 pass shared by K and M: inverse FFT along axis 0, pointwise op, forward FFT.
+template <typename T, int OP>
+void launch_axis0(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* active, hipStream_t s,
+                  const T* tab_override) {
+  const Geom& g = r->g;
+  constexpr int NC = OP == 0 ? 6 : 3;
+  const long n12 = (long)g.n1 * g.n2;
   const T* tab = tab_override ? tab_override : (OP == 0 ? ctab<T>(r) : rhotab<T>(r));
   const char* name0 = active ? "k_axis0_contract_pcg" : (OP == 0 ? "k_axis0_contract" : "k_axis0_mass");
   const long units0 = active ? 0 : nvec;
@@ -876,7 +897,15 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
                   n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
     });
   }
-  if (g.n1 > 1) axis1(std::false_type{});
+}
+
+// The three-pass slab path (FP32, n1 = n2 = 128; bw_slab.h).  In PCG mode it takes
+// the preconditioned residual z = P^ r from the K p buffer, where the update and
+// restart kernels leave it.
+template <typename T> inline bool slab_path(const bw_rve* r) {
+  const Geom& g = r->g;
+  return std::is_same<T, float>::value && r->tune_slab && g.n1 == SLAB_N && g.n2 == SLAB_N && g.n0 > 1 &&
+         size_supported(g.n0) && 6L * g.nvox < (1L << 31);
 }
 
 template <typename T>
@@ -885,6 +914,29 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   const Geom& g = r->g;
   const int* active = mode == 1 ? pd->active : nullptr;
   PcgDev dummy{};
+  if constexpr (std::is_same<T, float>::value) {
+    if (slab_path<T>(r)) {
+      const dim3 grid(nvec * g.n0);
+      const float2* tw = twiddles<T>(r, 2);
+      if (mode == 0)
+        BW_LAUNCH("k_slab_strain", nvec, (k_slab_strain<0>), grid, dim3(SLAB_NT), 0, s, u, (float2*)nullptr, W,
+                  d_qtab, g.n0, g.nvox, tw, active, (const double*)nullptr);
+      else   // u = r is not read: z = P^ r waits in y (the K p buffer)
+        BW_LAUNCH("k_slab_strain_pcg", 0, (k_slab_strain<1>), grid, dim3(SLAB_NT), 0, s, (const float2*)y, pp, W,
+                  d_qtab, g.n0, g.nvox, tw, active, pd->beta);
+      launch_axis0<T, 0>(r, W, nvec, (T)(1.0 / (double)g.nvox), active, s, nullptr);
+      if (mode == 0)
+        BW_LAUNCH("k_slab_div", nvec, (k_slab_div<0>), grid, dim3(SLAB_NT), 0, s, (const float2*)W, y, d_qtab, g.n0,
+                  g.nvox, tw, active, (const float2*)nullptr, dummy, (float)scale);
+      else {
+        BW_LAUNCH("k_slab_div_pcg", 0, (k_slab_div<1>), grid, dim3(SLAB_NT), 0, s, (const float2*)W, y, d_qtab,
+                  g.n0, g.nvox, tw, active, (const float2*)pp, *pd, (float)scale);
+        hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_ALPHA, g.n0, *pd, (const int*)nullptr,
+                           (double*)nullptr, (double*)nullptr);
+      }
+      return;
+    }
+  }
   const bool reg2 = r->tune_reg[2] && reg_len(g.n2) && ((long)g.n0 * g.n1) % reg_lines(g.n2) == 0;
   const int tpvr = reg2 ? (int)(((long)g.n0 * g.n1) / reg_lines(g.n2)) : 0;
   // fused plane pass (FP32, n0 = n1 = 64): strain and stress in the transposed work layout
@@ -1049,11 +1101,15 @@ void launch_pcg_apply(const bw_rve* r, const double* d_qtab, const cplx<T>* rv, 
 
 template <typename T>
 void launch_pcg_update(const bw_rve* r, const double* d_qtab, cplx<T>* x, cplx<T>* rv, const cplx<T>* p,
-                       const cplx<T>* Ap, int nvec, const PcgDev& pd, hipStream_t s) {
+                       cplx<T>* Ap, int nvec, const PcgDev& pd, hipStream_t s) {
   const Geom& g = r->g;
   const int bpv = pw_blocks(g.nvox);
-  BW_LAUNCH("k_pcg_update", 0, (k_pcg_update<T>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
-                     voxidx(g), g.nvox, bpv, c0v<T>(r), pd);
+  if (slab_path<T>(r))
+    BW_LAUNCH("k_pcg_update", 0, (k_pcg_update<T, true>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
+              voxidx(g), g.nvox, bpv, c0v<T>(r), pd);
+  else
+    BW_LAUNCH("k_pcg_update", 0, (k_pcg_update<T>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
+              voxidx(g), g.nvox, bpv, c0v<T>(r), pd);
   hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_BETA, bpv, pd, (const int*)nullptr,
                      (double*)nullptr, (double*)nullptr);
 }
@@ -1089,11 +1145,11 @@ void launch_norms2(const bw_rve* r, const cplx<T>* b, const cplx<T>* rv, int nve
 
 template <typename T>
 void launch_pcg_restart(const bw_rve* r, const double* d_qtab, const cplx<T>* rv, int nvec, const PcgDev& pd,
-                        const int* d_mask, hipStream_t s) {
+                        const int* d_mask, hipStream_t s, cplx<T>* Ap) {
   const Geom& g = r->g;
   const int bpv = pw_blocks(g.nvox);
   hipLaunchKernelGGL((k_pcg_restart<T>), dim3(nvec * bpv), dim3(NT), 0, s, rv, d_qtab, voxidx(g),
-                     g.nvox, bpv, c0v<T>(r), pd, d_mask);
+                     g.nvox, bpv, c0v<T>(r), pd, d_mask, slab_path<T>(r) ? Ap : (cplx<T>*)nullptr);
   hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_RESTART, bpv, pd, d_mask, (double*)nullptr,
                      (double*)nullptr);
 }
@@ -1130,11 +1186,11 @@ template <typename T> void zero_voxel(cplx<T>* x, int nvec, long nvox, long vox,
   template void launch_pcg_apply<T>(const bw_rve*, const double*, const cplx<T>*, cplx<T>*, cplx<T>*, cplx<T>*,     \
                                     int, const PcgDev&, hipStream_t);                                              \
   template void launch_pcg_update<T>(const bw_rve*, const double*, cplx<T>*, cplx<T>*, const cplx<T>*,              \
-                                     const cplx<T>*, int, const PcgDev&, hipStream_t);                             \
+                                     cplx<T>*, int, const PcgDev&, hipStream_t);                                   \
   template void launch_residual<T>(const bw_rve*, const double*, const cplx<T>*, const cplx<T>*, cplx<T>*,          \
                                    cplx<T>*, cplx<T>*, int, double*, double*, double*, unsigned*, int, hipStream_t); \
   template void launch_pcg_restart<T>(const bw_rve*, const double*, const cplx<T>*, int, const PcgDev&, const int*, \
-                                      hipStream_t);                                                                 \
+                                      hipStream_t, cplx<T>*);                                                       \
   template void launch_norms2<T>(const bw_rve*, const cplx<T>*, const cplx<T>*, int, double*, double*, double*, int, \
                                  hipStream_t);                                                                      \
   template void scale_vectors<T>(cplx<T>*, size_t, double, hipStream_t);                                           \

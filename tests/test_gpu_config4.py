@@ -11,9 +11,18 @@ periodic Voronoi, hexagonal Ti constants with c-axes spread about z.
   because M = F diag(rho) F^-1 has the densities as eigenvalues); the
   frequencies agree with the FP64 path (solved independently to 5e-7) to
   1e-5, and each reported a-posteriori bound (<= 1e-5) covers that
-  difference.  The oracle's own eigen-solvers are far too slow at 6.3 M
-  unknowns; residuals and the FP64 path are the checks that hold at any size.
+  difference;
+* the 12 lowest frequencies at three wave vectors of the path (next to X on
+  Gamma-X, next to M on X-M, next to R on Gamma-R) against stored values of the
+  oracle's shift-invert Lanczos at tolerance 1e-11 (tests/golden/ti128.json,
+  written by tests/golden/make_golden.py, about an hour per wave vector on the
+  host): the mixed path to 1e-5 with bounds covering the error, the FP64 path to
+  1e-9, and the block subspace method (a different algorithm and start, so a
+  branch that the single-vector iterations both missed would show) to 1e-5.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -92,4 +101,40 @@ def test_config4_mixed_modes_residual_bounds_and_fp64_agreement(lib, ti128):
     d = np.abs(om - om64) / np.maximum(om64, om_scale)
     assert d.max() <= 1e-5, d.max()
     assert np.all(d <= err + 1e-9), (d - err).max()
+    R64.close()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ti128.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="stored 128^3 oracle values not written yet")
+def test_config4_lowest_modes_match_stored_oracle(lib, ti128):
+    torch = _torch()
+    g = json.load(open(GOLDEN))
+    ks = np.array(g["k"])
+    ref = np.array(g["omega"])
+    nm = g["nmodes"]
+    om_scale = 2 * np.pi / inputs.L_MM * np.sqrt(Operators(ti128, ks[0]).C0[3, 3] / float(np.mean(ti128.rho)))
+    print(f"\n[case] 128^3 Ti vs stored oracle at path indices {g['k_index']}", flush=True)
+    Rm = lib.Rve.from_inputs(ti128, lib.BW_MIXED)
+    lib.bw_autotune(Rm, len(ks))
+    om, err, code, st = lib.bw_lowest_modes(Rm, ks, nm, method=lib.BW_LANCZOS, tol_omega=5e-6, tol_lin=1e-6)
+    assert code == 0, lib.bw_last_error()
+    d = np.abs(om - ref) / np.maximum(ref, om_scale)
+    print(f"[case] mixed Lanczos: max rel err {d.max():.2e}, max bound {err.max():.2e}", flush=True)
+    assert d.max() <= 1e-5
+    assert np.all(d <= err + 1e-9), (d - err).max()
+    om_s, err_s, code_s, _ = lib.bw_lowest_modes(Rm, ks, nm, method=lib.BW_SUBSPACE, block=16, tol_omega=5e-6,
+                                                 tol_lin=1e-6, warm_start=False)
+    assert code_s == 0, lib.bw_last_error()
+    d_s = np.abs(om_s - ref) / np.maximum(ref, om_scale)
+    print(f"[case] mixed subspace: max rel err {d_s.max():.2e}", flush=True)
+    assert d_s.max() <= 1e-5
+    Rm.close()
+    R64 = lib.Rve.from_inputs(ti128, lib.BW_FP64)
+    om64, err64, code64, _ = lib.bw_lowest_modes(R64, ks, nm, method=lib.BW_LANCZOS, tol_omega=1e-10, tol_lin=1e-10)
+    assert code64 == 0, lib.bw_last_error()
+    d64 = np.abs(om64 - ref) / np.maximum(ref, om_scale)
+    print(f"[case] FP64 Lanczos: max rel err {d64.max():.2e}", flush=True)
+    assert d64.max() <= 1e-9
     R64.close()

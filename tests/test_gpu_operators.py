@@ -52,6 +52,10 @@ CASES = [
     ((32, 16, 16), 5, [0.0, -0.5, 0.5]),
     # n0 = n1 = 64: the fused plane pass on the transposed work layout (FP32)
     ((64, 64, 16), 7, [0.3, 0.45, -0.2]),
+    # n1 = n2 = 128: the three-pass slab path (FP32; register or generic axis-0 pass)
+    ((16, 128, 128), 9, [0.3, -0.2, 0.45]),
+    ((8, 128, 128), 6, [1.0, 0.0, 0.5]),
+    ((4, 128, 128), 3, [0.0, 0.0, 0.0]),
 ]
 
 
@@ -350,3 +354,37 @@ def test_fft_schedules_and_autotune_keep_parity(lib, n):
         torch.cuda.synchronize()
         assert _rel(y.cpu().numpy(), ref) <= TOL[prec]
         R.close()
+
+
+@pytest.mark.parametrize("kk", [[0.3, -0.2, 0.45], [0.0, 0.0, 0.0]])
+def test_pcg_on_the_slab_path(lib, kk):
+    """PCG on the three-pass slab path (FP32, n1 = n2 = 128), where the update kernel
+    hands z = P^ r to the next direction through the K p buffer: the solutions have the
+    oracle's true residual and agree with the five-pass path's to the FP32 bar, in the
+    same number of iterations (+-1); at Gamma the right-hand sides have no xi = 0 part."""
+    torch = _dev()
+    rve = inputs.polycrystal((8, 128, 128), (L, L, L), 12, 98, 0)
+    k = np.array(kk) * np.pi / L
+    ops = Operators(rve, k)
+    b = _rand((3, 3, 8, 128, 128), 21)
+    if not np.any(k):
+        b[:, :, 0, 0, 0] = 0.0
+    print(f"\n[case] slab PCG k={kk}", flush=True)
+    out = {}
+    for slab in (True, False):
+        R = lib.Rve.from_inputs(rve, 1)
+        if not slab:
+            lib.bw_fft_schedule(R, reg=[1, 1, 0], cap=[0, 0, 0])   # row kernels generic: no slab path
+        bd = _to_dev(b, 1)
+        x = torch.zeros_like(bd)
+        code, it, rr = lib.bw_pcg_solve(R, k, bd, x, 1e-5)
+        assert code == 0, lib.bw_last_error()
+        out[slab] = (x.cpu().numpy().astype(np.complex128), it)
+        R.close()
+    xs, its = out[True]
+    xf, itf = out[False]
+    assert np.all(np.abs(its - itf) <= 1), (its, itf)
+    for v in range(3):
+        res = np.linalg.norm(ops.apply_K(xs[v]) - b[v]) / np.linalg.norm(b[v])
+        assert res <= 2e-5, (v, res)
+        assert np.linalg.norm(xs[v] - xf[v]) <= 2e-5 * np.linalg.norm(xf[v])
