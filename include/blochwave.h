@@ -158,6 +158,22 @@ int bw_rve_info(const bw_rve* rve, int32_t n[3], int32_t* precision, double C0_2
 int bw_apply_K(bw_rve* rve, const double k_host[3], const void* u, void* y, int32_t nvec,
                void* stream);
 
+/* y = K(k) u exactly as bw_apply_K (same kernels, same results), for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops): the call allocates nothing.  Its work array (6 nvec n0 n1 n2 complex
+ * numbers in the cell's precision, rounded up to 256 bytes) and its table of
+ * shifted wave numbers (nvec (n0 + n1 + n2) doubles) live in a scratch area of
+ * the library of BW_NOALLOC_SCRATCH_BYTES (64 MiB) in each device's memory,
+ * held until the process ends; larger requests return BW_EINVAL (e.g. FP32 at
+ * 64^3: up to 5 vectors; at 128^3 none).  Every call on a device uses that
+ * device's one area: calls that overlap on one device (concurrent streams or
+ * threads) race and give wrong results.  The cell must already exist (its
+ * tables are allocated by bw_create_rve), and kernel timing must be off (it
+ * creates events). */
+#define BW_NOALLOC_SCRATCH_BYTES (64u << 20)
+int bw_apply_K_noalloc(bw_rve* rve, const double k_host[3], const void* u, void* y, int32_t nvec,
+                       void* stream);
+
 /* y = M u (Sec. 3.2 eq. hatM).  Same layout rules as bw_apply_K. */
 int bw_apply_M(bw_rve* rve, const void* u, void* y, int32_t nvec, void* stream);
 

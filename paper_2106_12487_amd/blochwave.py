@@ -59,6 +59,7 @@ _SIGS = {
     "bw_destroy_rve": (None, [_P]),
     "bw_rve_info": (_I, [_P, _IP, _IP, _DP, _DP]),
     "bw_apply_K": (_I, [_P, _DP, _P, _P, _I, _P]),
+    "bw_apply_K_noalloc": (_I, [_P, _DP, _P, _P, _I, _P]),
     "bw_apply_M": (_I, [_P, _P, _P, _I, _P]),
     "bw_apply_P": (_I, [_P, _DP, _P, _P, _I, _P]),
     "bw_pcg_solve": (_I, [_P, _DP, _P, _P, _I, _D, _I, _IP, _DP, _P]),
@@ -237,6 +238,12 @@ def bw_fft_schedule(rve: Rve, reg=None, cap=None):
 def bw_apply_K(rve: Rve, k, u, y, stream=None) -> None:
     k_arr, k_p = _darr(k)
     _check(lib().bw_apply_K(rve.handle, k_p, _dptr(u), _dptr(y), int(u.shape[0]), _stream(stream)))
+
+
+def bw_apply_K_noalloc(rve: Rve, k, u, y, stream=None) -> None:
+    """y = K(k) u with no device allocation (library scratch area; see the header)."""
+    k_arr, k_p = _darr(np.asarray(k, dtype=np.float64).reshape(3))
+    _check(lib().bw_apply_K_noalloc(rve.handle, k_p, _dptr(u), _dptr(y), int(u.shape[0]), _stream(stream)))
 
 
 def bw_apply_M(rve: Rve, u, y, stream=None) -> None:

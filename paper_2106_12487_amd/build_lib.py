@@ -24,7 +24,7 @@ FLAGS = [
     "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
 
-SOURCES = ["bw_api.hip", "bw_ops_f64.hip", "bw_ops_f32.hip", "bw_eig.hip", "bw_gram.hip", "bw_unet.hip", "bw_disp.hip"]
+SOURCES = ["bw_api.hip", "bw_ops_f64.hip", "bw_ops_f32.hip", "bw_eig.hip", "bw_gram.hip", "bw_unet.hip", "bw_disp.hip", "bw_noalloc.hip"]
 
 
 def _compile(src: str) -> str:
