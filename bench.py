@@ -44,6 +44,12 @@ KERNEL_WORDS = {
     "k_row_div_pcg": (12, 0),        # read 6 stress components and p; write K p
     "k_row_div": (9, 0),
     "k_pcg_update": (18, 0),         # read x, r, p, Kp; write x, r
+    "k_pcg_update_z": (21, 0),       # the same, and z = P^ r over Kp (slab path)
+    # three-pass slab path (n1 = n2 = 128): 2D transforms of (vector, i0) slabs
+    "k_slab_strain_pcg": (15, 0),    # read z, p; write p and 6 strain components
+    "k_slab_strain": (9, 0),
+    "k_slab_div_pcg": (12, 0),       # read 6 stress components and p; write K p
+    "k_slab_div": (9, 0),
     "k_axis1_inv_mass": (6, 0), "k_axis1_fwd_mass": (6, 0), "k_axis0_mass": (6, 2),
     "k_row_inv_mass": (6, 0), "k_row_fwd_mass": (6, 0),
 }
@@ -168,7 +174,8 @@ def roofline(rep, nvox, word_bytes, workload):
 
 
 KERNEL_SOURCES = ("paper_2106_12487_amd/csrc/bw_ops_impl.h", "paper_2106_12487_amd/csrc/bw_fftreg.h",
-                  "paper_2106_12487_amd/csrc/bw_fft.h", "paper_2106_12487_amd/csrc/bw_internal.h")
+                  "paper_2106_12487_amd/csrc/bw_slab.h", "paper_2106_12487_amd/csrc/bw_fft.h",
+                  "paper_2106_12487_amd/csrc/bw_internal.h")
 
 
 def kernel_sources_hash() -> str:

@@ -278,7 +278,7 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
         its_prev = its;
         for (const char* nm : {"k_strain_row_pcg", "k_axis1_inv_pcg", "k_axis0_contract_pcg", "k_axis1_fwd_pcg",
                                "k_plane_contract_pcg", "k_row_div_pcg", "k_slab_strain_pcg", "k_slab_div_pcg",
-                               "k_pcg_update"})
+                               "k_pcg_update", "k_pcg_update_z"})
           timing_add_units(nm, d);
       }
       bool cap = false;
@@ -520,6 +520,22 @@ extern "C" int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3]
       rs += w * rho_host[gi];
     }
     r->rho_bar = rs;
+    {
+      // one density in every occupied grain: take it as the mean exactly, so that the
+      // scaled density is exactly 1 and M' is the identity (the solvers then copy
+      // instead of transforming, and the Lanczos basis is its own M-image)
+      double r0 = -1;
+      bool uni = true;
+      for (int gi = 0; gi < n_grains && uni; ++gi) {
+        if (count[gi] == 0) continue;
+        if (r0 < 0) r0 = rho_host[gi];
+        else if (rho_host[gi] != r0) uni = false;
+      }
+      if (uni && r0 > 0) {
+        r->rho_bar = r0;
+        r->rho_unit = 1;
+      }
+    }
     r->Cref = r->C0_si[0];
     r->ell = L[0] / (2.0 * M_PI);
     for (int i = 0; i < 21; ++i) r->C0s[i] = r->C0_si[i] / r->Cref;

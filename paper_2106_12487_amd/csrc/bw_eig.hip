@@ -214,7 +214,11 @@ template <typename T> static void apply_K_blk(bw_rve* r, const double* dq, const
 template <typename T> static void apply_M_blk(bw_rve* r, const cplx<T>* u, cplx<T>* y, int nv, bool inverse,
                                                Counters& c, hipStream_t s) {
   if (nv <= 0) return;
-  launch_apply_Minv_or_M<T>(r, u, y, nv, inverse, ws<T>(r).work((size_t)nv * 6 * r->g.nvox), s);
+  if (r->rho_unit) {   // one density: M' and its inverse are the identity
+    BW_HIP(hipMemcpyAsync(y, u, (size_t)nv * 3 * r->g.nvox * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
+  } else {
+    launch_apply_Minv_or_M<T>(r, u, y, nv, inverse, ws<T>(r).work((size_t)nv * 6 * r->g.nvox), s);
+  }
   c.map += nv;
 }
 
@@ -635,7 +639,9 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
   Workspace<T>& w = wl<T>(r);
   const long xk = (long)(m + 1) * n3;
   cplx<T>* V = w.vec(0, (size_t)nk * xk);
-  cplx<T>* MV = w.vec(1, (size_t)nk * xk);
+  // with M' = I the basis is its own M-image: no second basis to store or restart
+  const bool unit = r->rho_unit != 0;
+  cplx<T>* MV = unit ? V : w.vec(1, (size_t)nk * xk);
   cplx<T>* B = w.vec(2, (size_t)nk * n3);
   cplx<T>* X = w.vec(3, (size_t)nk * n3);
   cplx<T>* MF = w.vec(4, (size_t)nk * n3);
@@ -723,7 +729,7 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
   for (int k = 0; k < nk; ++k) sc[k] = 1.0 / std::sqrt(bb[k].x);
   upload_sc();
   launch_scale_copy<T>(B, n3, V, xk, scd, nk, n3, nullptr, s);
-  launch_scale_copy<T>(MF, n3, MV, xk, scd, nk, n3, nullptr, s);
+  if (!unit) launch_scale_copy<T>(MF, n3, MV, xk, scd, nk, n3, nullptr, s);
 
   std::vector<std::vector<double>> H(nk, std::vector<double>((size_t)m * m, 0.0));
   std::vector<double2> hh(hcount), hh2(hcount);
@@ -782,7 +788,7 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       }
       upload_sc();
       launch_scale_copy<T>(X, n3, V + (size_t)(j + 1) * n3, xk, scd, nk, n3, actd, s);
-      launch_scale_copy<T>(MF, n3, MV + (size_t)(j + 1) * n3, xk, scd, nk, n3, actd, s);
+      if (!unit) launch_scale_copy<T>(MF, n3, MV + (size_t)(j + 1) * n3, xk, scd, nk, n3, actd, s);
     }
     ++cycles;
     cnt.outer += 1;
@@ -879,12 +885,14 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       cplx<T>* MVk = MV + (size_t)k * xk;
       launch_ritz<T>(Vk, m, sm.Q, kk, TMP, kk, n3, n3, s);
       BW_HIP(hipMemcpyAsync(Vk, TMP, (size_t)kk * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
-      launch_ritz<T>(MVk, m, sm.Q, kk, TMP, kk, n3, n3, s);
-      BW_HIP(hipMemcpyAsync(MVk, TMP, (size_t)kk * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
       BW_HIP(hipMemcpyAsync(Vk + (size_t)kk * n3, Vk + (size_t)m * n3, n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice,
                             s));
-      BW_HIP(hipMemcpyAsync(MVk + (size_t)kk * n3, MVk + (size_t)m * n3, n3 * sizeof(cplx<T>),
-                            hipMemcpyDeviceToDevice, s));
+      if (!unit) {
+        launch_ritz<T>(MVk, m, sm.Q, kk, TMP, kk, n3, n3, s);
+        BW_HIP(hipMemcpyAsync(MVk, TMP, (size_t)kk * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
+        BW_HIP(hipMemcpyAsync(MVk + (size_t)kk * n3, MVk + (size_t)m * n3, n3 * sizeof(cplx<T>),
+                              hipMemcpyDeviceToDevice, s));
+      }
       std::fill(H[k].begin(), H[k].end(), 0.0);
       for (int c = 0; c < kk; ++c) H[k][(size_t)c * m + c] = thv[m - 1 - c];
       BW_HIP(hipStreamSynchronize(s));

@@ -578,23 +578,18 @@ void launch_small_eig_batched(const double2* H, int q, int nb, double* lam, doub
 // ---------------------------------------------------------------------------
 // batched per-k basis products (Lanczos)
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(NT) void k_mdot(const cplx<T>* __restrict__ X, long xk, long xi,
-                                             const cplx<T>* __restrict__ Y, long yk, long n, const int* act,
-                                             double* partial, int bpv) {
-  __shared__ double sh[NT / 64];
-  const int b = blockIdx.x, i = blockIdx.y, k = blockIdx.z;
-  if (act && !act[k]) return;
-  const cplx<T>* x = X + (size_t)k * xk + (size_t)i * xi;
-  const cplx<T>* y = Y + (size_t)k * yk;
-  double sr = 0, si = 0;
-  for (long e = (long)b * NT + threadIdx.x; e < n; e += (long)bpv * NT) {
-    const double2 a = to_d2(x[e]), c = to_d2(y[e]);
-    sr += a.x * c.x + a.y * c.y;
-    si += a.x * c.y - a.y * c.x;
+// Work units for the kernel timing: J basis vectors per active wave vector (the
+// activity flags are read back only while timing is on).
+static long active_units(const int* act, int nk, int J, hipStream_t s) {
+  if (!timing_enabled()) return 0;
+  std::vector<int> a(nk, 1);
+  if (act) {
+    BW_HIP(hipMemcpyAsync(a.data(), act, nk * sizeof(int), hipMemcpyDeviceToHost, s));
+    BW_HIP(hipStreamSynchronize(s));
   }
-  const double vals[2] = {sr, si};
-  store_partials<2>(vals, partial, (int)(k * gridDim.y + i), b, bpv, sh);
+  long u = 0;
+  for (int k = 0; k < nk; ++k) u += a[k] ? J : 0;
+  return u;
 }
 
 __global__ __launch_bounds__(NT) void k_mdot_finalize(const double* __restrict__ partial, int bpv, int J,
@@ -608,6 +603,53 @@ __global__ __launch_bounds__(NT) void k_mdot_finalize(const double* __restrict__
   if (threadIdx.x == 0) out[(size_t)k * ldo + i] = make_double2(tot[0], tot[1]);
 }
 
+// The same products eight basis vectors per workgroup: the right-hand vector is
+// read once per group of eight instead of once per basis vector.  Per element
+// and per basis vector the accumulation order is that of k_mdot (same slices,
+// same wavefront and workgroup sums), so the results are identical.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mdot8(const cplx<T>* __restrict__ X, long xk, long xi, int J,
+                                              const cplx<T>* __restrict__ Y, long yk, long n, const int* act,
+                                              double* partial, int bpv) {
+  __shared__ double sh[16][NT / 64];
+  const int b = blockIdx.x, g = blockIdx.y, k = blockIdx.z;
+  if (act && !act[k]) return;
+  const int i0 = 8 * g;
+  const int ni = J - i0 < 8 ? J - i0 : 8;
+  const cplx<T>* x = X + (size_t)k * xk + (size_t)i0 * xi;
+  const cplx<T>* y = Y + (size_t)k * yk;
+  double sr[8], si[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) sr[i] = si[i] = 0.0;
+  for (long e = (long)b * NT + threadIdx.x; e < n; e += (long)bpv * NT) {
+    const double2 c = to_d2(y[e]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i < ni) {
+        const double2 a = to_d2(x[(size_t)i * xi + e]);
+        sr[i] += a.x * c.x + a.y * c.y;
+        si[i] += a.x * c.y - a.y * c.x;
+      }
+    }
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double r0 = wave_sum(sr[i]), r1 = wave_sum(si[i]);
+    if (l == 0) {
+      sh[2 * i][w] = r0;
+      sh[2 * i + 1][w] = r1;
+    }
+  }
+  __syncthreads();
+  const int v = threadIdx.x;
+  if (v < 2 * ni) {
+    double acc = 0;
+    for (int ww = 0; ww < NT / 64; ++ww) acc += sh[v][ww];
+    partial[((size_t)(k * J + i0 + (v >> 1)) * bpv + b) * 2 + (v & 1)] = acc;
+  }
+}
+
 template <typename T>
 void launch_mdot(const cplx<T>* X, long xk, long xi, int J, const cplx<T>* Y, long yk, int nk, long n,
                  const int* act, double2* out, int ldo, DevBuf& scratch, hipStream_t s) {
@@ -615,8 +657,8 @@ void launch_mdot(const cplx<T>* X, long xk, long xi, int J, const cplx<T>* Y, lo
   int bpv = pw_blocks(n);
   if (bpv > 256) bpv = 256;
   double* partial = (double*)scratch.get((size_t)nk * J * bpv * 2 * sizeof(double));
-  BW_LAUNCH("k_mdot", (long)nk * J, (k_mdot<T>), dim3(bpv, J, nk), dim3(NT), 0, s, X, xk, xi, Y, yk, n, act, partial,
-            bpv);
+  BW_LAUNCH("k_mdot", active_units(act, nk, J, s), (k_mdot8<T>), dim3(bpv, (J + 7) / 8, nk), dim3(NT), 0, s, X, xk, xi, J, Y, yk, n, act,
+            partial, bpv);
   hipLaunchKernelGGL(k_mdot_finalize, dim3(nk * J), dim3(NT), 0, s, (const double*)partial, bpv, J, act, out, ldo);
 }
 
@@ -648,7 +690,7 @@ void launch_mlincomb(cplx<T>* Y, long yk, const cplx<T>* X, long xk, long xi, in
   if (J <= 0 || nk <= 0) return;
   long nb = (n + 255) / 256;
   if (nb > 1024) nb = 1024;
-  BW_LAUNCH("k_mlincomb", (long)nk * J, (k_mlincomb<T>), dim3((unsigned)nb, 1, nk), dim3(256), 0, s, Y, yk, X, xk,
+  BW_LAUNCH("k_mlincomb", active_units(act, nk, J, s), (k_mlincomb<T>), dim3((unsigned)nb, 1, nk), dim3(256), 0, s, Y, yk, X, xk,
             xi, J, c, ldc, sign, n, act);
 }
 

@@ -147,6 +147,7 @@ struct bw_rve {
   // nondimensionalization: C' = C / Cref, q' = q * ell, rho' = rho / rho_bar
   double Cref, ell, rho_bar;
   double rho_min_s;  // smallest scaled density (bounds the M^-1 norm)
+  int rho_unit = 0;  // every occupied grain has the mean density: M' = identity
   double C0_si[21];     // volume-averaged stiffness (Pa)
   double C0s[21];       // scaled
   std::vector<double> C21s_host;  // G x 21 scaled

@@ -1105,7 +1105,7 @@ void launch_pcg_update(const bw_rve* r, const double* d_qtab, cplx<T>* x, cplx<T
   const Geom& g = r->g;
   const int bpv = pw_blocks(g.nvox);
   if (slab_path<T>(r))
-    BW_LAUNCH("k_pcg_update", 0, (k_pcg_update<T, true>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
+    BW_LAUNCH("k_pcg_update_z", 0, (k_pcg_update<T, true>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
               voxidx(g), g.nvox, bpv, c0v<T>(r), pd);
   else
     BW_LAUNCH("k_pcg_update", 0, (k_pcg_update<T>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
