@@ -67,6 +67,7 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--method", type=int, default=1, help="0 = subspace iteration, 1 = batched Lanczos")
     ap.add_argument("--skip-cu64", action="store_true", help="do not run the 64^3 Cu polycrystal arm")
+    ap.add_argument("--skip-learned", action="store_true", help="do not train / run the learned preconditioner arm")
     ap.add_argument("--skip-operator-arm", action="store_true", help="do not time bw_apply_K at 64^3 and 128^3")
     ap.add_argument("--skip-uneven", action="store_true", help="do not run the batched uneven-cells arm")
     ap.add_argument("--skip-fibre", action="store_true", help="do not run the long-fibre composite arm")
@@ -436,6 +437,60 @@ def cpu_baseline(rve_in, k, budget_s, golden):
                         f"{len(g['pcg_iters'])} wave vectors); extrapolated"))
 
 
+def learned_arm(bw, ti_rve, ti_ks, cells=8, steps=400, lr=2e-4):
+    """The learned preconditioner on the workload it is meant for: a network trained (residual
+    loss, on the GPU) on plain-PCG residuals of `cells` 64^3 Cu cells of 16-256 grains, then
+    (a) flexible PCG on an unseen 128^3 / 512-grain Cu cell against the plain preconditioner,
+    (b) the 12 lowest modes at one wave vector of the 128^3 Ti path with the learned inner
+    solves against the plain mixed path (k-points/s, status)."""
+    import numpy as np
+    import torch
+    from paper_2106_12487_amd import train_precond as tp
+    t0 = time.perf_counter()
+    tc = [tp.training_cell(i) for i in range(cells)]
+    pairs = tp.make_pairs(tc, 2, 4)
+    net = bw.UNet(seed=1)
+    t1 = time.perf_counter()
+    losses = tp.train(net, tc, pairs, steps, lr)
+    t_train = time.perf_counter() - t1
+    del pairs
+    for _, R in tc:
+        R.close()
+    torch.cuda.empty_cache()
+    ev_cell = tp.eval_cell(128, 0)
+    ev = tp.evaluate(net, [ev_cell], 1, 4)
+    ev_cell[1].close()
+    R = bw.Rve.from_inputs(ti_rve, bw.BW_MIXED)
+    bw.bw_autotune(R, 1)
+    k = ti_ks[[17]]
+    kw = dict(method=bw.BW_LANCZOS, tol_omega=TOL_OMEGA, tol_lin=1e-6)
+    bw.bw_lowest_modes(R, k, 12, **kw)                                  # warm-up (workspaces)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    w0, e0, c0, st0 = bw.bw_lowest_modes(R, k, 12, **kw)
+    t_plain = time.perf_counter() - t2
+    t2 = time.perf_counter()
+    w1, e1, c1, st1 = bw.bw_lowest_modes(R, k, 12, net=net, **kw)
+    t_learned = time.perf_counter() - t2
+    R.close()
+    net.close()
+    torch.cuda.empty_cache()
+    scale = float(np.max(w0))
+    return {"training": {"cells": cells, "grid": 64, "grains": "16-256", "pairs_batches": steps,
+                         "loss": "residual ||K z - r||^2 / ||r||^2", "loss_first_50": float(np.mean(losses[:50])),
+                         "loss_last_50": float(np.mean(losses[-50:])), "seconds": round(t_train, 1),
+                         "setup_seconds": round(t1 - t0, 1)},
+            "fpcg_cu128_512g": {"plain_iters": ev["plain_iters"], "learned_iters": ev["learned_iters"],
+                                "iter_ratio": round(ev["iter_ratio"], 3), "time_ratio": round(ev["time_ratio"], 2),
+                                "fallbacks": ev["fallbacks"]},
+            "lanczos_ti128_one_k": {"plain_k_points_per_s": round(1 / t_plain, 3),
+                                    "learned_k_points_per_s": round(1 / t_learned, 3),
+                                    "ratio": round(t_plain / t_learned, 3), "status": int(c1),
+                                    "pcg_iterations": [st0["pcg_iterations"], st1["pcg_iterations"]],
+                                    "max_error_bound": float(e1.max()),
+                                    "max_rel_diff_vs_plain": float(np.abs(w1 - w0).max() / scale)}}
+
+
 def segments(ks, nseg):
     """The path split into nseg consecutive segments of (nearly) equal length."""
     import numpy as np
@@ -527,6 +582,9 @@ def main():
             out["arms"]["max_rel_diff_vs_fp64"] = float((np.abs(last - ref) / np.maximum(ref, scale)).max())
         print(f"[bench] fp64 arm: {out['arms']['fp64_plain_one_k']['value']} k-points/s, speedup "
               f"{out['arms']['speedup_over_fp64_plain']}", file=sys.stderr, flush=True)
+    if not a.skip_learned:
+        out["arms"]["learned_preconditioner"] = learned_arm(bw, rve_in, ks)
+        print(f"[bench] learned arm: {out['arms']['learned_preconditioner']}", file=sys.stderr, flush=True)
     if not a.skip_cu64:
         out["arms"]["cu64_64g_gxmgr"] = cu64_arm(bw, fp64=not a.skip_fp64)
         print(f"[bench] cu64 arm: {out['arms']['cu64_64g_gxmgr']}", file=sys.stderr, flush=True)

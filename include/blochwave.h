@@ -39,8 +39,10 @@
  *            argument, BW_ENOMEM allocation failed, BW_EHIP a HIP runtime
  *            error, BW_EUNSUPPORTED grid size without a compiled FFT);
  *            > 0 = warning with valid outputs (BW_ENOTCONV an iteration hit its
- *            limit, results carry their error bounds).  bw_last_error() returns a
- *            thread-local message for the last non-zero status.
+ *            limit, results carry their error bounds; BW_ESTALL the learned
+ *            preconditioner stalled and the solve finished with the plain one).
+ *            bw_last_error() returns a thread-local message for the last non-zero
+ *            status.
  * Threads    a cell handle is not thread-safe; different handles may be used
  *            concurrently on different streams.
  */
@@ -56,6 +58,7 @@ extern "C" {
 
 #define BW_OK 0
 #define BW_ENOTCONV 1
+#define BW_ESTALL 2
 #define BW_EINVAL (-1)
 #define BW_ENOMEM (-2)
 #define BW_EHIP (-3)
@@ -71,6 +74,11 @@ extern "C" {
 #define BW_LANCZOS 1  /* Sec. 3.3, shift-invert restarted Lanczos           */
 
 typedef struct bw_rve bw_rve;
+typedef struct bw_unet bw_unet;   /* the learned preconditioner (below) */
+
+/* preconditioner of the inner solves */
+#define BW_PLAIN 0    /* P(C0, xi + k)^-1 of the homogeneous reference medium (Sec. 3.3) */
+#define BW_LEARNED 1  /* plus the network correction, in flexible PCG (bw_pcg_solve_learned) */
 
 /* Options of bw_lowest_modes.  Zero-initialized fields take the defaults shown. */
 typedef struct bw_eig_opts {
@@ -101,6 +109,12 @@ typedef struct bw_eig_opts {
                           other wave vectors of the call, except that with
                           ncv = 0 a batch of Gamma-like wave vectors only gets
                           the shorter default basis of nmodes - 3 wanted modes */
+  int32_t precond;     /* BW_PLAIN (default) or BW_LEARNED: the Lanczos inner
+                          solves of a BW_MIXED cell by flexible PCG with `net`
+                          (grids multiple of 4; the FP64 refinement keeps P^).
+                          A right-hand side whose learned steps stall finishes
+                          with P^ and the call returns BW_ESTALL (valid results) */
+  const bw_unet* net;  /* the network for BW_LEARNED                              */
 } bw_eig_opts;
 
 /* Statistics of the last solver call (all optional outputs). */
@@ -283,8 +297,6 @@ int64_t bw_timing_report(char* buf, int64_t len);
  * output channels 6..15 of layer 8 are padding: their weights are held at 0.
  * Concatenations put the upsampled coarse channels first, then the skip.
  * ------------------------------------------------------------------------ */
-typedef struct bw_unet bw_unet;
-
 /* Number of FP32 parameters of the network. */
 int64_t bw_unet_param_count(void);
 
@@ -326,6 +338,16 @@ int bw_unet_apply(bw_unet* net, bw_rve* rve, const double* k_host, const void* r
  * the loss before the step.  Synchronizes `stream`. */
 int bw_unet_train_step(bw_unet* net, bw_rve* rve, const double* k_host, const void* r, const void* x_star,
                        int32_t nrhs, double lr, double* loss_host, void* stream);
+
+/* One Adam step (as bw_unet_train_step) on the residual loss
+ *   mean over the nrhs residuals of ||K(k) z - r||^2 / ||r||^2,
+ * z the learned preconditioner applied to r (Euclidean norms of the Fourier
+ * coefficients; the gradient through K is one more K apply, K being Hermitian).
+ * Needs no solutions: the pairs are residuals alone, e.g. those of plain PCG
+ * iterates.  loss_host (optional) receives the loss before the step.
+ * Synchronizes `stream`. */
+int bw_unet_train_step_residual(bw_unet* net, bw_rve* rve, const double* k_host, const void* r, int32_t nrhs,
+                                double lr, double* loss_host, void* stream);
 
 /* Solve K(k) x = b by flexible preconditioned CG with the learned
  * preconditioner (net may be NULL: the plain P^, which reproduces

@@ -15,8 +15,11 @@ with s the RMS of F^-1(P^ r) over voxels and components and phi = arg(sum of
 (F^-1 P^ r)^2) / 2.  N is a 3-level U-Net of 3x3x3 periodic convolutions
 (16 / 32 / 64 channels), ReLU, 2x2x2 average pooling, nearest upsampling with
 skip concatenation (upsampled channels first) and a 1x1x1 head (16 outputs,
-the first 6 used).  The training loss is the mean squared error between the
-first 6 outputs and e^{-i phi} F^-1(x* - P^ r) / s for x* = K^-1 r.
+the first 6 used).  The supervised training loss is the mean squared error
+between the first 6 outputs and e^{-i phi} F^-1(x* - P^ r) / s for x* = K^-1 r;
+the residual loss is the batch mean of ||K z - r||^2 / ||r||^2 (Euclidean norms
+of the Fourier coefficients), whose gradient with respect to conj z is
+K (K z - r) / ||r||^2 since K is Hermitian.
 
 Everything is FP64 and written for clarity (np.roll per tap).  With
 bf16_operands=True every convolution first rounds its input and its weights to
@@ -33,7 +36,8 @@ scipy.ndimage.correlate with periodic ("wrap") boundaries; pooling and
 upsampling against their adjoint identities; the hand-written backward pass
 against central finite differences of the forward pass; the feature map
 against its scale and phase invariances; a zero head reproduces P^ r; the
-bfloat16 rounding against torch's CPU conversion.
+bfloat16 rounding against torch's CPU conversion; the residual loss's gradient
+against central finite differences of the loss.
 """
 from __future__ import annotations
 
@@ -249,3 +253,35 @@ def loss(ops, w, R, Xs, pscale: float = 1.0) -> float:
     x, _, _, _ = features(ops, R, pscale)
     out = forward(w, x, ops.n)
     return float(np.mean((out[:, :, :6] - target(ops, R, Xs, pscale)) ** 2))
+
+
+def residual_loss(ops, w, R, pscale: float = 1.0, bf16_operands: bool = False) -> float:
+    """Mean over the batch of ||K z - R||^2 / ||R||^2 with z = apply(ops, w, R)."""
+    nb = R.shape[0]
+    E = ops.apply_K(apply(ops, w, R, pscale, bf16_operands)) - R
+    return float(np.mean(np.sum(np.abs(E.reshape(nb, -1)) ** 2, axis=1) /
+                         np.sum(np.abs(R.reshape(nb, -1)) ** 2, axis=1)))
+
+
+def residual_loss_grad(ops, w, R, pscale: float = 1.0, bf16_operands: bool = False):
+    """The residual loss and its gradient with respect to the parameters: g = K (K z - R) /
+    ||R||^2 (the derivative with respect to conj z; zero on the xi + k = 0 voxel, where K
+    vanishes), h = F^H g (the adjoint of the unnormalized forward DFT, N times the
+    normalized inverse), and for the output o_{2c} + i o_{2c+1} that enters z as
+    F[s e^{i phi} (.)], dL/do_{2c} = (2 / nb) s Re(e^{-i phi} h_c), dL/do_{2c+1} = (2 / nb) s
+    Im(e^{-i phi} h_c); then the network's backward pass."""
+    nb = R.shape[0]
+    x, Z0, phi, s = features(ops, R, pscale)
+    out = forward(w, x, ops.n, bf16_operands=bf16_operands)
+    z = Z0 + correction(ops, out, phi, s)
+    z[..., ops.null_mask] = 0.0
+    E = ops.apply_K(z) - R
+    rr = np.sum(np.abs(R.reshape(nb, -1)) ** 2, axis=1)
+    loss = float(np.mean(np.sum(np.abs(E.reshape(nb, -1)) ** 2, axis=1) / rr))
+    G = ops.apply_K(E) / rr[:, None, None, None, None]
+    N = int(np.prod(ops.n))
+    H = (N * ifft3(G)).reshape(nb, 3, -1) * (np.exp(-1j * phi) * s)[:, None, None]
+    dy = np.zeros_like(out)
+    dy[:, :, 0:6:2] = (2.0 / nb) * H.real.transpose(0, 2, 1)
+    dy[:, :, 1:6:2] = (2.0 / nb) * H.imag.transpose(0, 2, 1)
+    return loss, backward(w, x, dy, ops.n, bf16_operands=bf16_operands)

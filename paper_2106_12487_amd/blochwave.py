@@ -19,10 +19,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libblochwave.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "blochwave.h")
 
-BW_OK, BW_ENOTCONV = 0, 1
+BW_OK, BW_ENOTCONV, BW_ESTALL = 0, 1, 2
 BW_EINVAL, BW_ENOMEM, BW_EHIP, BW_EUNSUPPORTED = -1, -2, -3, -4
 BW_FP64, BW_MIXED = 0, 1
 BW_SUBSPACE, BW_LANCZOS = 0, 1
+BW_PLAIN, BW_LEARNED = 0, 1
 
 
 class BlochwaveError(RuntimeError):
@@ -35,7 +36,8 @@ class bw_eig_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("block", ctypes.c_int32), ("ncv", ctypes.c_int32),
                 ("maxit_outer", ctypes.c_int32), ("maxit_lin", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("tol_eig", ctypes.c_double),
-                ("tol_lin", ctypes.c_double), ("tol_omega", ctypes.c_double), ("kbatch", ctypes.c_int32)]
+                ("tol_lin", ctypes.c_double), ("tol_omega", ctypes.c_double), ("kbatch", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("net", ctypes.c_void_p)]
 
 
 class bw_stats(ctypes.Structure):
@@ -85,6 +87,7 @@ _SIGS = {
     "bw_unet_net_backward": (_I, [_P, _IP, _P, _P, ctypes.POINTER(ctypes.c_float), _I, _P]),
     "bw_unet_apply": (_I, [_P, _P, _DP, _P, _P, _I, _P]),
     "bw_unet_train_step": (_I, [_P, _P, _DP, _P, _P, _I, _D, _DP, _P]),
+    "bw_unet_train_step_residual": (_I, [_P, _P, _DP, _P, _I, _D, _DP, _P]),
     "bw_pcg_solve_learned": (_I, [_P, _P, _DP, _P, _P, _I, _D, _I, _IP, _DP, _IP, _P]),
     "bw_group_velocity": (_I, [_P, _DP, _DP, _I, _P, _DP, _D, _DP, _P]),
     "bw_long_wave_speeds": (_I, [_P, _DP, _D, _D, _DP, _P]),
@@ -269,14 +272,16 @@ def bw_pcg_solve(rve: Rve, k, b, x, rtol: float, maxit: int = 0, stream=None):
 def bw_lowest_modes(rve: Rve, k_list, nmodes: int, method: int = BW_SUBSPACE, block: int = 0, ncv: int = 0,
                     tol_eig: float = 0.0, tol_lin: float = 0.0, maxit_outer: int = 0, maxit_lin: int = 0,
                     warm_start: bool = True, modes=None, want_err: bool = True, tol_omega: float = 0.0,
-                    kbatch: int = 0, stream=None):
-    """omega (nk x nmodes, rad/s), error bounds, status and statistics."""
+                    kbatch: int = 0, net=None, stream=None):
+    """omega (nk x nmodes, rad/s), error bounds, status and statistics.  net: a UNet for
+    the learned preconditioner of the Lanczos inner solves (BW_LEARNED), else plain."""
     k_arr, k_p = _darr(np.asarray(k_list).reshape(-1, 3))
     nk = int(k_arr.shape[0])
     om = np.zeros((nk, nmodes))
     er = np.zeros((nk, nmodes))
     opts = bw_eig_opts(method, block, ncv, maxit_outer, maxit_lin, int(bool(warm_start)), tol_eig, tol_lin,
-                       tol_omega, kbatch)
+                       tol_omega, kbatch, BW_LEARNED if net is not None else BW_PLAIN,
+                       net.handle.value if net is not None else None)
     st = bw_stats()
     code = _check(lib().bw_lowest_modes(rve.handle, k_p, nk, int(nmodes), ctypes.byref(opts),
                                         om.ctypes.data_as(_DP), er.ctypes.data_as(_DP) if want_err else None,
@@ -430,6 +435,16 @@ def bw_unet_train_step(net: UNet, rve: Rve, k, r, x_star, lr: float, stream=None
     loss = ctypes.c_double()
     _check(lib().bw_unet_train_step(net.handle, rve.handle, k_p, _dptr(r), _dptr(x_star), nrhs, float(lr),
                                     ctypes.byref(loss), _stream(stream)))
+    return loss.value
+
+
+def bw_unet_train_step_residual(net: UNet, rve: Rve, k, r, lr: float, stream=None) -> float:
+    """One Adam step on mean ||K z - r||^2 / ||r||^2; returns the loss before the step."""
+    nrhs = int(r.shape[0])
+    k_arr, k_p = _klist(k, nrhs)
+    loss = ctypes.c_double()
+    _check(lib().bw_unet_train_step_residual(net.handle, rve.handle, k_p, _dptr(r), nrhs, float(lr),
+                                             ctypes.byref(loss), _stream(stream)))
     return loss.value
 
 

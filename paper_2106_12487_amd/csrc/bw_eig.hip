@@ -11,6 +11,7 @@
 #include <numeric>
 #include <string>
 #include <thread>
+#include <type_traits>
 
 #include "bw_block.h"
 #include "bw_internal.h"
@@ -29,6 +30,8 @@ struct EigOpts {
   int method, block, ncv, maxit_outer, maxit_lin, warm;
   double tol_eig, tol_lin, tol_omega;
   int kbatch;
+  int precond = BW_PLAIN;
+  bw_unet* net = nullptr;
 };
 
 // Relative omega bound of Ritz pair p from the residual norms res[0 .. nres) of
@@ -54,6 +57,7 @@ static double omega_bound(const double* res, int nres, const std::vector<double>
 
 struct Counters {
   long pcg_iters = 0, block_iters = 0, outer = 0, kap = 0, map = 0;
+  long stalls = 0;   // learned inner solves that finished with the plain preconditioner
 };
 
 // Small device arrays shared by the drivers (one allocation per cell).
@@ -752,11 +756,24 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       // drop the rounding left there, which the preconditioned iteration cannot reduce
       for (int k = 0; k < nk; ++k)
         if (act[k] && qt.null_index[k] >= 0) zero_voxel<T>(B + (size_t)k * n3, 1, g.nvox, qt.null_index[k], s);
-      PcgResult pr = pcg_run<T>(r, dq, qt, B, X, nk, fp32 ? std::max(o.tol_lin, 1e-6) : o.tol_lin, o.maxit_lin,
-                                true, s, false, false);
-      cnt.pcg_iters += pr.total_iters;
-      cnt.block_iters += pr.block_iters;
-      cnt.kap += pr.k_applies;
+      if constexpr (std::is_same<T, float>::value) {
+        if (o.precond == BW_LEARNED) {
+          // flexible PCG with the learned preconditioner (x0 = 0)
+          BW_HIP(hipMemsetAsync(X, 0, (size_t)nk * n3 * sizeof(cplx<T>), s));
+          const FpcgResult fr = fpcg_run(r, o.net, dq, qt, (const float2*)B, (float2*)X, nk,
+                                         std::max(o.tol_lin, 1e-6), o.maxit_lin, s);
+          cnt.pcg_iters += fr.total;
+          cnt.kap += fr.total;
+          for (int k = 0; k < nk; ++k) cnt.stalls += fr.fb[k] > 0;
+        }
+      }
+      if (!(fp32 && o.precond == BW_LEARNED)) {
+        PcgResult pr = pcg_run<T>(r, dq, qt, B, X, nk, fp32 ? std::max(o.tol_lin, 1e-6) : o.tol_lin, o.maxit_lin,
+                                  true, s, false, false);
+        cnt.pcg_iters += pr.total_iters;
+        cnt.block_iters += pr.block_iters;
+        cnt.kap += pr.k_applies;
+      }
       // full re-orthogonalization (twice) in the M inner product
       launch_mdot<T>(MV, xk, n3, j + 1, X, n3, nk, n3, actd, hd, m + 1, r->ws_red, s);
       launch_mlincomb<T>(X, n3, V, xk, n3, j + 1, hd, m + 1, -1.0, nk, n3, actd, s);
@@ -959,10 +976,20 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
       o.tol_lin = opts->tol_lin;
       o.tol_omega = opts->tol_omega;
       o.kbatch = opts->kbatch;
+      o.precond = opts->precond;
+      o.net = const_cast<bw_unet*>(opts->net);
     } else {
       o.warm = 1;
     }
     BW_REQUIRE(o.method == BW_SUBSPACE || o.method == BW_LANCZOS, BW_EINVAL, "unknown method");
+    BW_REQUIRE(o.precond == BW_PLAIN || o.precond == BW_LEARNED, BW_EINVAL, "unknown preconditioner");
+    if (o.precond == BW_LEARNED) {
+      BW_REQUIRE(o.net, BW_EINVAL, "BW_LEARNED needs a network");
+      BW_REQUIRE(r->precision == BW_MIXED, BW_EINVAL, "the learned preconditioner works on BW_MIXED cells");
+      BW_REQUIRE(o.method == BW_LANCZOS, BW_EUNSUPPORTED, "the learned preconditioner runs in the Lanczos solves");
+      BW_REQUIRE(r->g.n0 % 4 == 0 && r->g.n1 % 4 == 0 && r->g.n2 % 4 == 0, BW_EUNSUPPORTED,
+                 "the learned preconditioner needs grid sizes that are multiples of 4");
+    }
     if (o.block <= 0) o.block = std::min(2 * nmodes, nmodes + 8);
     if (o.maxit_outer <= 0) o.maxit_outer = 200;
     if (o.maxit_lin <= 0) o.maxit_lin = 20000;
@@ -1013,6 +1040,11 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
       stats->seconds = std::chrono::duration<double>(t1 - t0).count();
     }
     if (st == BW_ENOTCONV) set_error("bw_lowest_modes: some k hit maxit_outer; see the error bounds");
+    if (st == BW_OK && cnt.stalls > 0) {
+      set_error("bw_lowest_modes: the learned preconditioner stalled in " + std::to_string(cnt.stalls) +
+                " inner solves, which finished with the plain preconditioner");
+      st = BW_ESTALL;
+    }
     return st;
   } catch (const Error& e) {
     set_error(e.msg);

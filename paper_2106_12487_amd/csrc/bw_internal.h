@@ -253,6 +253,16 @@ void launch_pcg_apply(const bw_rve* r, const double* d_qtab, const cplx<T>* rv, 
 template <typename T> void scale_vectors(cplx<T>* x, size_t n, double sc, hipStream_t s);
 template <typename T> void zero_voxel(cplx<T>* x, int nvec, long nvox, long vox, hipStream_t s);
 
+// flexible PCG with the learned preconditioner on the scaled system K' x = b
+// (bw_unet.hip); u null: the plain preconditioner
+struct FpcgResult {
+  std::vector<int> its, fb;    // iterations and fallbacks to the plain preconditioner, per right-hand side
+  std::vector<double> rel;     // final true relative residuals
+  long total = 0;
+  bool conv = true;
+};
+FpcgResult fpcg_run(bw_rve* r, bw_unet* u, const double* dq, const QTable& qt, const float2* b, float2* x, int nrhs,
+                    double rtol, int maxit, hipStream_t s);
 // solver layer (bw_api.hip)
 template <typename T> Workspace<T>& ws(bw_rve* r);
 template <> inline Workspace<double>& ws<double>(bw_rve* r) { return r->ws64; }

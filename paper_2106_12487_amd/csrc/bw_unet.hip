@@ -422,6 +422,28 @@ __global__ void k_target(const float2* __restrict__ D, const double* __restrict_
   }
 }
 
+// gradient of the residual loss with respect to the head output: with h = F^H g
+// (g the gradient with respect to conj z, already divided by ||r||^2), the output
+// o_{2c} + i o_{2c+1} enters z through F[s e^{i phi} (.)], so
+// dL/do_{2c} = fac s Re(e^{-i phi} h_c), dL/do_{2c+1} = fac s Im(e^{-i phi} h_c).
+__global__ void k_outgrad(const float2* __restrict__ H, const double* __restrict__ ps, float* __restrict__ dout,
+                          long nvox, int nb, float fac) {
+  const long total = (long)nb * nvox;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long v = e % nvox;
+    const int b = (int)(e / nvox);
+    const float cr = (float)ps[4 * b], ci = (float)ps[4 * b + 1], f = fac * (float)ps[4 * b + 3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float2 h = H[((size_t)b * 3 + c) * nvox + v];
+      dout[(size_t)e * 16 + 2 * c] = f * (h.x * cr + h.y * ci);
+      dout[(size_t)e * 16 + 2 * c + 1] = f * (h.y * cr - h.x * ci);
+    }
+#pragma unroll
+    for (int c = 6; c < 16; ++c) dout[(size_t)e * 16 + c] = 0.f;
+  }
+}
+
 // network output -> real-space correction D_c(v) = s e^{i phi} (o_{2c} + i o_{2c+1})
 __global__ void k_output(const float* __restrict__ o, const double* __restrict__ ps, float2* __restrict__ D,
                          long nvox, int nb) {
@@ -1077,48 +1099,84 @@ extern "C" int bw_unet_train_step(bw_unet* u, bw_rve* r, const double* k_host, c
   BWU_GUARD_END
 }
 
-// Flexible preconditioned CG (Polak-Ribiere beta, i.e. one-step K-orthogonal
-// directions) with the learned preconditioner; per right-hand side, a step
-// whose preconditioned residual is not a descent direction (Re <r, z> <= 0 or
-// not finite) takes the plain P^ r instead and restarts the direction; after
-// three such steps, or when the residual has not dropped by 10% over 10
-// iterations, that right-hand side continues with the plain preconditioner.
-extern "C" int bw_pcg_solve_learned(bw_rve* r, bw_unet* u, const double k_host[3], const void* b, void* x,
-                                    int32_t nrhs, double rtol, int32_t maxit, int32_t* iters_host,
-                                    double* relres_host, int32_t* fallbacks_host, void* stream) {
+// One Adam step on the residual loss mean_b ||K z_b - r_b||^2 / ||r_b||^2 with z
+// the learned preconditioner applied to r: its gradient with respect to conj z is
+// K (K z - r) / ||r||^2 (K is Hermitian), carried back to the network output by
+// F^H and the output map (k_outgrad).
+extern "C" int bw_unet_train_step_residual(bw_unet* u, bw_rve* r, const double* k_host, const void* res,
+                                           int32_t nrhs, double lr, double* loss_host, void* stream) {
   BWU_GUARD_BEGIN
-  BW_REQUIRE(r && k_host && b && x, BW_EINVAL, "null argument");
-  BW_REQUIRE(nrhs >= 0, BW_EINVAL, "nrhs < 0");
-  BW_REQUIRE(b != x, BW_EINVAL, "b and x must not alias");
-  BW_REQUIRE(rtol > 0 && std::isfinite(rtol), BW_EINVAL, "rtol must be > 0");
-  if (nrhs == 0) return BW_OK;
-  if (u)
-    check_pair(u, r);
-  else
-    BW_REQUIRE(r->precision == BW_MIXED, BW_EINVAL, "flexible PCG works on BW_MIXED cells");
-  if (maxit <= 0) maxit = 20000;
+  BW_REQUIRE(u && r && k_host && res, BW_EINVAL, "null argument");
+  BW_REQUIRE(nrhs >= 1, BW_EINVAL, "nrhs must be >= 1");
+  BW_REQUIRE(lr >= 0 && std::isfinite(lr), BW_EINVAL, "learning rate must be finite and >= 0");
+  check_pair(u, r);
   hipStream_t s = (hipStream_t)stream;
   const Geom& g = r->g;
+  const Dims d1 = dims_of(g.n0, g.n1, g.n2);
   const long n3 = 3 * g.nvox;
-  std::vector<double> ks((size_t)nrhs * 3);
-  for (int v = 0; v < nrhs; ++v)
-    for (int c = 0; c < 3; ++c) ks[3 * v + c] = k_host[c];
-  QTable qt = make_qtable(r, ks.data(), nrhs);
-  const int nullv = qt.null_index[0];
-  DevBuf& qb = u ? u->qbuf : r->ws_q3;
-  const double* dq = upload_qtable(r, qt, qb, s);
-  const float2* bb = (const float2*)b;
-  float2* xx = (float2*)x;
-  if (nullv >= 0) {
-    std::vector<float2> vals((size_t)nrhs * 3);
-    for (int v = 0; v < nrhs; ++v)
-      for (int c = 0; c < 3; ++c)
-        BW_HIP(hipMemcpyAsync(&vals[v * 3 + c], bb + ((size_t)v * 3 + c) * g.nvox + nullv, sizeof(float2),
-                              hipMemcpyDeviceToHost, s));
-    BW_HIP(hipStreamSynchronize(s));
-    for (const float2& e : vals)
-      BW_REQUIRE(e.x == 0.f && e.y == 0.f, BW_EINVAL, "b has a component on the xi + k = 0 voxel (K is singular)");
+  QTable qt = make_qtable(r, k_host, nrhs);
+  const double* dq = upload_qtable(r, qt, u->qbuf, s);
+  Acts a = acts_for(u, d1, nrhs, true);
+  Feat f = feat_bufs(u, r, nrhs);
+  build_features(r, dq, (const float2*)res, nrhs, 1.0 / K_scale(r), f, a, s);
+  unet_forward(u, a, d1, nrhs, s);
+  float2* Z = (float2*)u->tmp.get((size_t)3 * nrhs * n3 * sizeof(float2));
+  float2* E = Z + (size_t)nrhs * n3;
+  float2* G = E + (size_t)nrhs * n3;
+  float2* W = (float2*)ws<float>(r).work((size_t)nrhs * 6 * g.nvox);
+  apply_output(r, f, a, Z, nrhs, s);
+  for (int v = 0; v < nrhs; ++v)   // the learned z is zero on the xi + k = 0 voxel
+    if (qt.null_index[v] >= 0) zero_voxel<float>((cplx<float>*)Z + (size_t)v * n3, 1, g.nvox, qt.null_index[v], s);
+  // E = K z - r (physical units), G = K E / ||r||^2
+  launch_apply_K<float>(r, dq, (const cplx<float>*)Z, (cplx<float>*)E, nrhs, K_scale(r), (cplx<float>*)W, s);
+  hipLaunchKernelGGL(k_sub, dim3(grid_for(nrhs * n3)), dim3(256), 0, s, (const float2*)E, (const float2*)res, E,
+                     (long)nrhs * n3);
+  double2* dd = (double2*)u->small.get((size_t)2 * nrhs * sizeof(double2));
+  launch_dots<float>((const cplx<float>*)E, (const cplx<float>*)E, nrhs, n3, n3, dd, u->part, nullptr, s);
+  launch_dots<float>((const cplx<float>*)res, (const cplx<float>*)res, nrhs, n3, n3, dd + nrhs, r->ws_red2, nullptr, s);
+  std::vector<double2> h(2 * nrhs);
+  BW_HIP(hipMemcpyAsync(h.data(), dd, (size_t)2 * nrhs * sizeof(double2), hipMemcpyDeviceToHost, s));
+  BW_HIP(hipStreamSynchronize(s));
+  launch_apply_K<float>(r, dq, (const cplx<float>*)E, (cplx<float>*)G, nrhs, K_scale(r), (cplx<float>*)W, s);
+  double loss = 0;
+  for (int v = 0; v < nrhs; ++v) {
+    BW_REQUIRE(h[nrhs + v].x > 0, BW_EINVAL, "a residual of the batch is zero");
+    loss += h[v].x / h[nrhs + v].x;
+    scale_vectors<float>((cplx<float>*)G + (size_t)v * n3, (size_t)n3, 1.0 / h[nrhs + v].x, s);
   }
+  loss /= nrhs;
+  BW_REQUIRE(std::isfinite(loss), BW_EINVAL, "training loss is not finite");
+  fft3_inplace<true>(r, G, nrhs, s);           // F^H: the unnormalized inverse transform
+  hipLaunchKernelGGL(k_outgrad, dim3(grid_for(nrhs * g.nvox)), dim3(256), 0, s, (const float2*)G,
+                     (const double*)f.ps, a.dO, g.nvox, nrhs, (float)(2.0 / nrhs));
+  unet_backward(u, a, d1, nrhs, s);
+  hipLaunchKernelGGL(k_mask_grad, dim3(7), dim3(256), 0, s, u->d_g, u->w_off[0], u->w_off[8], u->b_off[8]);
+  u->adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)u->adam_t), c2 = 1.f - std::pow(b2, (float)u->adam_t);
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(u->nparam)), dim3(256), 0, s, u->d_w, (const float*)u->d_g, u->d_m, u->d_v,
+                     u->nparam, (float)lr, b1, b2, 1e-8f, c1, c2);
+  refresh_bf16(u, s);
+  BW_HIP(hipStreamSynchronize(s));
+  if (loss_host) *loss_host = loss;
+  return BW_OK;
+  BWU_GUARD_END
+}
+
+namespace bw {
+
+// Flexible preconditioned CG (Polak-Ribiere beta, i.e. one-step K-orthogonal
+// directions) on the scaled system K' x = b, with the learned preconditioner
+// (u may be null: the plain P^); one wave vector per right-hand side (qt).  Per
+// right-hand side, a step whose preconditioned residual is not a descent
+// direction (Re <r, z> <= 0 or not finite) takes the plain P^ r instead and
+// restarts the direction; after three such steps, or when the residual has not
+// dropped by 10% over 10 iterations, that right-hand side continues with the
+// plain preconditioner.  x holds the initial guess on entry.
+FpcgResult fpcg_run(bw_rve* r, bw_unet* u, const double* dq, const QTable& qt, const float2* bb, float2* xx,
+                    int nrhs, double rtol, int maxit, hipStream_t s) {
+  const Geom& g = r->g;
+  const long n3 = 3 * g.nvox;
   // vectors: r, z, p, Kp, t
   DevBuf& vb = u ? u->vecs : r->ws_misc;
   float2* R = (float2*)vb.get((size_t)5 * nrhs * n3 * sizeof(float2));
@@ -1144,7 +1202,7 @@ extern "C" int bw_pcg_solve_learned(bw_rve* r, bw_unet* u, const double k_host[3
   auto applyK = [&](const float2* in, float2* out) {
     launch_apply_K<float>(r, dq, (const cplx<float>*)in, (cplx<float>*)out, nrhs, 1.0, (cplx<float>*)W, s);
   };
-  std::vector<int> nullvec(nrhs, nullv);
+  const std::vector<int>& nullvec = qt.null_index;
   std::vector<char> plain(nrhs, u ? 0 : 1), active(nrhs, 1);
   std::vector<int> its(nrhs, 0), fb(nrhs, 0);
   std::vector<double> bn(nrhs), rn(nrhs);
@@ -1163,9 +1221,8 @@ extern "C" int bw_pcg_solve_learned(bw_rve* r, bw_unet* u, const double k_host[3
       launch_apply_P<float>(r, dq, (const cplx<float>*)R, (cplx<float>*)Z, nrhs, 1.0, s);
     }
   };
-  // x' = K_scale x (nondimensional system K' x' = b), r = b - K' x'
-  scale_vectors<float>((cplx<float>*)xx, (size_t)nrhs * n3, K_scale(r), s);
-  if (nullv >= 0) zero_voxel<float>((cplx<float>*)xx, nrhs, g.nvox, nullv, s);
+  for (int v = 0; v < nrhs; ++v)
+    if (qt.null_index[v] >= 0) zero_voxel<float>((cplx<float>*)xx + (size_t)v * n3, 1, g.nvox, qt.null_index[v], s);
   applyK(xx, KP);
   hipLaunchKernelGGL(k_sub, dim3(grid_for(nrhs * n3)), dim3(256), 0, s, bb, (const float2*)KP, R, (long)nrhs * n3);
   dots(bb, bb, d_dots);
@@ -1285,24 +1342,81 @@ extern "C" int bw_pcg_solve_learned(bw_rve* r, bw_unet* u, const double k_host[3
     for (int v = 0; v < nrhs; ++v)
       if (active[v] && its[v] >= maxit) active[v] = 0;
   }
-  // final true residuals, back to physical units
+  // final true residuals
   applyK(xx, Tt);
   hipLaunchKernelGGL(k_sub, dim3(grid_for(nrhs * n3)), dim3(256), 0, s, bb, (const float2*)Tt, Tt, (long)nrhs * n3);
   dots(Tt, Tt, d_dots);
   fetch(1);
+  FpcgResult res;
+  res.its = its;
+  res.fb = fb;
+  res.rel.assign(nrhs, 0.0);
+  for (int v = 0; v < nrhs; ++v) {
+    res.rel[v] = bn[v] > 0 ? std::sqrt(h_dots[v].x) / bn[v] : 0.0;
+    if (!(res.rel[v] <= rtol)) res.conv = false;
+    res.total += its[v];
+  }
+  return res;
+}
+
+}  // namespace bw
+
+extern "C" int bw_pcg_solve_learned(bw_rve* r, bw_unet* u, const double k_host[3], const void* b, void* x,
+                                    int32_t nrhs, double rtol, int32_t maxit, int32_t* iters_host,
+                                    double* relres_host, int32_t* fallbacks_host, void* stream) {
+  BWU_GUARD_BEGIN
+  BW_REQUIRE(r && k_host && b && x, BW_EINVAL, "null argument");
+  BW_REQUIRE(nrhs >= 0, BW_EINVAL, "nrhs < 0");
+  BW_REQUIRE(b != x, BW_EINVAL, "b and x must not alias");
+  BW_REQUIRE(rtol > 0 && std::isfinite(rtol), BW_EINVAL, "rtol must be > 0");
+  if (nrhs == 0) return BW_OK;
+  if (u)
+    check_pair(u, r);
+  else
+    BW_REQUIRE(r->precision == BW_MIXED, BW_EINVAL, "flexible PCG works on BW_MIXED cells");
+  if (maxit <= 0) maxit = 20000;
+  hipStream_t s = (hipStream_t)stream;
+  const Geom& g = r->g;
+  const long n3 = 3 * g.nvox;
+  std::vector<double> ks((size_t)nrhs * 3);
+  for (int v = 0; v < nrhs; ++v)
+    for (int c = 0; c < 3; ++c) ks[3 * v + c] = k_host[c];
+  QTable qt = make_qtable(r, ks.data(), nrhs);
+  const int nullv = qt.null_index[0];
+  DevBuf& qb = u ? u->qbuf : r->ws_q3;
+  const double* dq = upload_qtable(r, qt, qb, s);
+  const float2* bb = (const float2*)b;
+  float2* xx = (float2*)x;
+  if (nullv >= 0) {
+    std::vector<float2> vals((size_t)nrhs * 3);
+    for (int v = 0; v < nrhs; ++v)
+      for (int c = 0; c < 3; ++c)
+        BW_HIP(hipMemcpyAsync(&vals[v * 3 + c], bb + ((size_t)v * 3 + c) * g.nvox + nullv, sizeof(float2),
+                              hipMemcpyDeviceToHost, s));
+    BW_HIP(hipStreamSynchronize(s));
+    for (const float2& e : vals)
+      BW_REQUIRE(e.x == 0.f && e.y == 0.f, BW_EINVAL, "b has a component on the xi + k = 0 voxel (K is singular)");
+  }
+  // x' = K_scale x (nondimensional system K' x' = b)
+  scale_vectors<float>((cplx<float>*)xx, (size_t)nrhs * n3, K_scale(r), s);
+  const FpcgResult res = fpcg_run(r, u, dq, qt, bb, xx, nrhs, rtol, maxit, s);
   scale_vectors<float>((cplx<float>*)xx, (size_t)nrhs * n3, 1.0 / K_scale(r), s);
   BW_HIP(hipStreamSynchronize(s));
-  bool conv = true;
+  int stalled = 0;
   for (int v = 0; v < nrhs; ++v) {
-    const double rel = bn[v] > 0 ? std::sqrt(h_dots[v].x) / bn[v] : 0.0;
-    if (iters_host) iters_host[v] = its[v];
-    if (relres_host) relres_host[v] = rel;
-    if (fallbacks_host) fallbacks_host[v] = fb[v];
-    if (!(rel <= rtol)) conv = false;
+    if (iters_host) iters_host[v] = res.its[v];
+    if (relres_host) relres_host[v] = res.rel[v];
+    if (fallbacks_host) fallbacks_host[v] = res.fb[v];
+    stalled += res.fb[v] > 0;
   }
-  if (!conv) {
+  if (!res.conv) {
     set_error("flexible PCG: some right-hand side did not reach rtol");
     return BW_ENOTCONV;
+  }
+  if (stalled) {
+    set_error("flexible PCG: the learned preconditioner stalled for " + std::to_string(stalled) +
+              " right-hand side(s), which finished with the plain preconditioner");
+    return BW_ESTALL;
   }
   return BW_OK;
   BWU_GUARD_END

@@ -56,7 +56,7 @@ def test_group_velocity_polycrystal_matches_oracle(lib, prec):
     scale = np.abs(so).max()
     err = np.abs(s - so).max() / scale
     print(f"max slope error / max slope {err:.2e}", flush=True)
-    assert err <= (3e-5 if prec == 0 else 1e-2)
+    assert err <= (1e-9 if prec == 0 else 1e-5)
     R.close()
 
 

@@ -143,3 +143,27 @@ def test_bf16_operands_change_little():
     y = unet.forward(w, x, n)
     yb = unet.forward(w, x, n, bf16_operands=True)
     assert 1e-4 < np.linalg.norm(yb - y) / np.linalg.norm(y) < 2e-2
+
+
+@pytest.mark.parametrize("k", [(700.0, -300.0, 1200.0), (0.0, 0.0, 0.0)])
+def test_residual_loss_gradient_matches_finite_differences(k):
+    """The chain K (K z - r) / ||r||^2 -> F^H -> output map -> backward pass against central
+    differences of the residual loss along random directions in the head and in the first
+    layer (a wrong conjugate, factor N or phase fails by O(1)); at Gamma the null voxel."""
+    ops = _ops(k)
+    R = _residuals(ops, 2, 21)
+    w = random_weights(22)
+    loss, g = unet.residual_loss_grad(ops, w, R, pscale=2.0)
+    assert np.isclose(loss, unet.residual_loss(ops, w, R, pscale=2.0), rtol=1e-12)
+    rng = np.random.default_rng(23)
+    offs, _ = unet.layout()
+    for layer in (8, 0):
+        wo, bo = offs[layer]
+        cout = unet.LAYERS[layer][1]
+        d = np.zeros_like(w)
+        d[wo:bo + cout] = rng.standard_normal(bo + cout - wo)
+        d = unet.mask_padding(d)
+        eps = 1e-7
+        fd = (unet.residual_loss(ops, w + eps * d, R, 2.0) - unet.residual_loss(ops, w - eps * d, R, 2.0)) / (2 * eps)
+        an = float(g @ d)
+        assert abs(fd - an) <= 1e-4 * max(abs(an), 1e-12), (layer, fd, an)
