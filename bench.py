@@ -168,6 +168,8 @@ def roofline(rep, nvox, word_bytes, workload):
     avg_s = v["ms"] / max(v["launches"], 1) / 1e3
     achieved = per_launch / avg_s / 1e9
     traffic = measured_traffic(name, workload)
+    if traffic is not None:   # counter bytes per voxel and active vector, at this run's launches
+        traffic = int(traffic * per_launch / (words * word_bytes + extra))
     return dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
                 bytes_per_launch=int(per_launch), avg_launch_us=round(avg_s * 1e6, 2),
@@ -188,16 +190,17 @@ def kernel_sources_hash() -> str:
 
 
 def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` on `workload` from the committed counter runs
-    (profiles/traffic_<kernel>_<workload>.json), or None when there is none or the
-    kernel sources changed since the counters were taken."""
+    """HBM bytes per voxel and active vector of `kernel` on `workload` from the
+    committed counter runs (profiles/traffic_<kernel>_<workload>.json: FETCH_SIZE and
+    WRITE_SIZE scaled by what they read for a 1 GiB copy), or None when there is none
+    or the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
     if t.get("sources_sha256_16") != kernel_sources_hash():
         return None
-    return t.get("traffic_bytes_per_launch")
+    return t.get("traffic_bytes_per_voxel_vector")
 
 
 # Algorithmic bytes of one K apply per voxel and vector (3-pass model: strain + axis-2

@@ -23,9 +23,10 @@
 // LDS: line l owns slots [136 l, 136 l + 136) (a pitch of 8 mod 16 slots puts
 // neighbouring lines in opposite halves of the 32 banks).  The exchange puts
 // (k1, j) at slot 8 k1 + (j ^ (k1 >> 1)); the plane puts column k of row l at
-// slot k ^ (l & 1).  Every access pattern of a wavefront (exchange writes and
-// reads, row writes, column reads) then hits each bank four times for 64
-// eight-byte accesses, and every address is a per-thread base plus a constant.
+// slot k ^ (l & 7).  Every access pattern (exchange writes and reads, row
+// writes, column reads) then spreads each group of 16 lanes of an 8-byte access
+// over all 32 banks (and each group of 32 lanes over 64), and every address is
+// a per-thread base plus a constant.
 // Global accesses are a uniform base plus a 32-bit lane offset and a constant.
 // Keeping addresses that cheap is what leaves the registers for three live
 // 16-point sets per thread (at most 128 registers per lane at 1024 threads).
@@ -126,10 +127,10 @@ __device__ __forceinline__ void slab_fft2d(float2 (&x)[16], float2* S, const flo
   float2* reg = S + a * SLAB_LP;
   slab_fft128<INV>(x, reg, j, tw);            // rows (axis 2)
   {
-    // column k = 2 j + p + 16 k2 of row a at slot k ^ (a & 1)
-    const int lb = a & 1;
-    float2* b0 = reg + 2 * j + lb;           // p = 0
-    float2* b1 = reg + 2 * j + (1 - lb);     // p = 1
+    // column k = 2 j + p + 16 k2 of row a at slot k ^ (a & 7) = ((2 j + p) ^ (a & 7)) + 16 k2
+    const int sw = a & 7;
+    float2* b0 = reg + ((2 * j) ^ sw);       // p = 0
+    float2* b1 = reg + ((2 * j + 1) ^ sw);   // p = 1
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) {
       b0[16 * k2] = x[k2];
@@ -138,8 +139,8 @@ __device__ __forceinline__ void slab_fft2d(float2 (&x)[16], float2* S, const flo
   }
   __syncthreads();
   {
-    // rows j + 8 m, column a at slot a ^ (row & 1) = a ^ (j & 1)
-    const float2* b = S + j * SLAB_LP + (a ^ (j & 1));
+    // rows j + 8 m, column a at slot a ^ (row & 7) = a ^ j
+    const float2* b = S + j * SLAB_LP + (a ^ j);
 #pragma unroll
     for (int m = 0; m < 16; ++m) x[m] = b[m * 8 * SLAB_LP];
   }
