@@ -43,14 +43,17 @@ template <typename T>
 void launch_planewaves(cplx<T>* U, int nv, long nvox, const long* vox, const double* pol, hipStream_t s);
 // Per-k bases (batched Lanczos): basis vector i of wave vector k sits at
 // X + k * xk + i * xi; the batch vector of k at Y + k * yk.
-// out[k * ldo + i] = <X_k[i], Y_k> for i < J (skipped, left untouched, where act[k] == 0)
+// out0[k * ldo + i] = <X_k[i], Y0_k>, out1[k * ldo + i] = <X_k[i], Y1_k> for i < J,
+// each basis vector read once
 template <typename T>
-void launch_mdot(const cplx<T>* X, long xk, long xi, int J, const cplx<T>* Y, long yk, int nk, long n,
-                 const int* act, double2* out, int ldo, DevBuf& scratch, hipStream_t s);
-// Y_k += sign * sum_{i < J} X_k[i] c[k * ldc + i]   (FP64 accumulation)
+void launch_mdot2(const cplx<T>* X, long xk, long xi, int J, const cplx<T>* Y0, long yk0, const cplx<T>* Y1, long yk1,
+                  int nk, long n, const int* act, double2* out0, double2* out1, int ldo, DevBuf& scratch,
+                  hipStream_t s);
+// Y0_k <- f0 Y0_k - sum_i X_k[i] a_i;  Y1_k <- f1 Y1_k - sum_i X_k[i] b_i - g Y0_k(new)
+// (coefficients at c + k * ldc: a[0..J-1], b[0..J-1], (f0, 0), (f1, 0), g; Y1 may be null)
 template <typename T>
-void launch_mlincomb(cplx<T>* Y, long yk, const cplx<T>* X, long xk, long xi, int J, const double2* c, int ldc,
-                     double sign, int nk, long n, const int* act, hipStream_t s);
+void launch_mlincomb2(cplx<T>* Y0, long yk0, cplx<T>* Y1, long yk1, const cplx<T>* X, long xk, long xi, int J,
+                      const double2* c, int ldc, int nk, long n, const int* act, hipStream_t s);
 // Y_k = sc[k] * X_k with independent strides
 template <typename T>
 void launch_scale_copy(const cplx<T>* X, long xk, cplx<T>* Y, long yk, const double* sc, int nk, long n,

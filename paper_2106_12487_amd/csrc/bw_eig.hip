@@ -11,6 +11,7 @@
 #include <numeric>
 #include <string>
 #include <thread>
+#include <complex>
 #include <type_traits>
 
 #include "bw_block.h"
@@ -606,6 +607,61 @@ static unsigned long long wave_vector_seed(const double* k) {
   return h;
 }
 
+// Host side of the delayed re-orthogonalization of Lanczos step j (one wave
+// vector; H is the m x m projected matrix, row-major).  Inputs: d1[i] = <v_i,
+// v~_j>_M for i <= j (v~_j: the pending vector, orthogonalized once) and d2[i] =
+// <v_i, X>_M with X = OP v~_j.  With s = d1[0..j-1] and nu^2 = d1[j] - |s|^2 the
+// finished vector is v_j = (v~_j - V s) / nu.  The relation OP V = V H + v~_j h_j^T
+// (h_j: row j of H) then reads OP V = V (H + s h_j^T) + v_j nu h_j^T, and
+// OP v_j = (X - V t - v_j tau) / nu with t = H[0..j-1, 0..j-1] s, tau = h_j s (both
+// after the update); its products with the finished basis are c_i = (d2_i - t_i) / nu
+// and c_j = ((d2_j - s^H d2) / nu - tau) / nu.  Writes column j of H (real parts:
+// the projected matrix of the Hermitian OP is real symmetric up to rounding) and the
+// coefficients of the update kernel: a = s / nu, b = t / nu + c, f0 = f1 = 1 / nu,
+// g = tau / nu + c_j.
+static void delayed_reorth_coefficients(double* H, int m, int j, const double2* d1, const double2* d2,
+                                        double2* coef) {
+  using C = std::complex<double>;
+  std::vector<C> sv(j), z(j), t(j, 0.0);
+  double ss = 0.0;
+  for (int i = 0; i < j; ++i) {
+    sv[i] = C(d1[i].x, d1[i].y);
+    z[i] = C(d2[i].x, d2[i].y);
+    ss += std::norm(sv[i]);
+  }
+  const double om = d1[j].x;
+  const double nu = std::sqrt(std::max(om - ss, 1e-12 * std::max(om, 1e-300)));
+  for (int l = 0; l < j; ++l) {
+    const double hjl = H[(size_t)j * m + l];
+    if (hjl == 0.0) continue;
+    for (int i = 0; i < j; ++i) H[(size_t)i * m + l] += sv[i].real() * hjl;
+    H[(size_t)j * m + l] = nu * hjl;
+    for (int i = 0; i < j; ++i) H[(size_t)l * m + i] = H[(size_t)i * m + l];
+    H[(size_t)l * m + j] = H[(size_t)j * m + l];
+  }
+  C tau = 0.0, sz = 0.0;
+  for (int l = 0; l < j; ++l) {
+    tau += H[(size_t)j * m + l] * sv[l];
+    sz += std::conj(sv[l]) * z[l];
+  }
+  for (int i = 0; i < j; ++i)
+    for (int l = 0; l < j; ++l) t[i] += H[(size_t)i * m + l] * sv[l];
+  const C cj = ((C(d2[j].x, d2[j].y) - sz) / nu - tau) / nu;
+  for (int i = 0; i < j; ++i) {
+    const C ci = (z[i] - t[i]) / nu;
+    const C a = sv[i] / nu, b = t[i] / nu + ci;
+    coef[i] = make_double2(a.real(), a.imag());
+    coef[j + i] = make_double2(b.real(), b.imag());
+    H[(size_t)i * m + j] = ci.real();
+    H[(size_t)j * m + i] = ci.real();
+  }
+  H[(size_t)j * m + j] = cj.real();
+  const C g = tau / nu + cj;
+  coef[2 * j] = make_double2(1.0 / nu, 0.0);
+  coef[2 * j + 1] = make_double2(1.0 / nu, 0.0);
+  coef[2 * j + 2] = make_double2(g.real(), g.imag());
+}
+
 // ---------------------------------------------------------------------------
 // batched thick-restart shift-invert Lanczos (Sec. 3.3, implicitly restarted
 // Lanczos on the shifted-inverse operator).  Every wave vector of the batch
@@ -653,10 +709,13 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
   cplx<T>* MN = w.vec(6, (size_t)3 * n3);
   cplx<T>* N3 = w.vec(7, (size_t)3 * n3);
   const size_t hcount = (size_t)nk * (m + 1);
-  char* sb = (char*)w.v[8].get(2 * hcount * sizeof(double2) + nk * (sizeof(double) + sizeof(int)) + 1024);
+  const int ldc = 2 * (m + 1) + 3;  // coefficients of the re-orthogonalization update per wave vector
+  char* sb = (char*)w.v[8].get((2 * hcount + (size_t)nk * ldc) * sizeof(double2) +
+                               nk * (sizeof(double) + sizeof(int)) + 1024);
   double2* hd = (double2*)sb;
   double2* hd2 = hd + hcount;
-  double* scd = (double*)(hd2 + hcount);
+  double2* cfd = hd2 + hcount;
+  double* scd = (double*)(cfd + (size_t)nk * ldc);
   int* actd = (int*)(scd + nk);
   long jcache = -1;
   auto ensure_MN = [&](long j) {
@@ -736,7 +795,7 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
   if (!unit) launch_scale_copy<T>(MF, n3, MV, xk, scd, nk, n3, nullptr, s);
 
   std::vector<std::vector<double>> H(nk, std::vector<double>((size_t)m * m, 0.0));
-  std::vector<double2> hh(hcount), hh2(hcount);
+  std::vector<double2> hh(hcount), hh2(hcount), cf((size_t)nk * ldc);
   std::vector<double> thv(m);
   std::vector<double2> Sm((size_t)m * m);
   int j0 = 0;
@@ -774,27 +833,33 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
         cnt.block_iters += pr.block_iters;
         cnt.kap += pr.k_applies;
       }
-      // full re-orthogonalization (twice) in the M inner product
-      launch_mdot<T>(MV, xk, n3, j + 1, X, n3, nk, n3, actd, hd, m + 1, r->ws_red, s);
-      launch_mlincomb<T>(X, n3, V, xk, n3, j + 1, hd, m + 1, -1.0, nk, n3, actd, s);
-      launch_mdot<T>(MV, xk, n3, j + 1, X, n3, nk, n3, actd, hd2, m + 1, r->ws_red, s);
-      launch_mlincomb<T>(X, n3, V, xk, n3, j + 1, hd2, m + 1, -1.0, nk, n3, actd, s);
+      // Full re-orthogonalization in the M inner product, twice, with the second
+      // pass of each vector delayed by one step (classical Gram-Schmidt with delayed
+      // re-orthogonalization): v_j was orthogonalized once when it was formed; one
+      // pass of products over MV[0..j] with both v_j and X = OP v_j gives the
+      // second-pass coefficients of v_j and the first-pass ones of X, and one
+      // update pass over V[0..j-1] finishes v_j and orthogonalizes X against the
+      // finished basis, X corrected for the change of v_j through the Lanczos
+      // relation.  The basis is read twice per step instead of four times.
+      launch_mdot2<T>(MV, xk, n3, j + 1, V + (size_t)j * n3, xk, X, n3, nk, n3, actd, hd, hd2, m + 1, r->ws_red, s);
+      BW_HIP(hipMemcpyAsync(hh.data(), hd, hcount * sizeof(double2), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipMemcpyAsync(hh2.data(), hd2, hcount * sizeof(double2), hipMemcpyDeviceToHost, s));
+      BW_HIP(hipStreamSynchronize(s));
+      for (int k = 0; k < nk; ++k)
+        if (act[k]) delayed_reorth_coefficients(H[k].data(), m, j, hh.data() + (size_t)k * (m + 1),
+                                                hh2.data() + (size_t)k * (m + 1), cf.data() + (size_t)k * ldc);
+      h2d(cfd, cf.data(), (size_t)nk * ldc * sizeof(double2), s);
+      launch_mlincomb2<T>(V + (size_t)j * n3, xk, X, n3, V, xk, n3, j, cfd, ldc, nk, n3, actd, s);
+      if (!unit) launch_mlincomb2<T>(MV + (size_t)j * n3, xk, nullptr, 0, MV, xk, n3, j, cfd, ldc, nk, n3, actd, s);
       apply_M_blk<T>(r, X, MF, nk, false, cnt, s);
       deflate_batch(X, MF, act);
       launch_dots<T>(X, MF, nk, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
-      BW_HIP(hipMemcpyAsync(hh.data(), hd, hcount * sizeof(double2), hipMemcpyDeviceToHost, s));
-      BW_HIP(hipMemcpyAsync(hh2.data(), hd2, hcount * sizeof(double2), hipMemcpyDeviceToHost, s));
       BW_HIP(hipMemcpyAsync(bb.data(), sm.dots, nk * sizeof(double2), hipMemcpyDeviceToHost, s));
       BW_HIP(hipStreamSynchronize(s));
       for (int k = 0; k < nk; ++k) {
         if (!act[k]) {
           sc[k] = 0.0;
           continue;
-        }
-        for (int i = 0; i <= j; ++i) {
-          const double h = hh[(size_t)k * (m + 1) + i].x + hh2[(size_t)k * (m + 1) + i].x;
-          H[k][(size_t)i * m + j] = h;
-          H[k][(size_t)j * m + i] = h;
         }
         beta[k] = std::sqrt(std::max(bb[k].x, 0.0));
         if (j + 1 < m) {
@@ -911,7 +976,15 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
                               hipMemcpyDeviceToDevice, s));
       }
       std::fill(H[k].begin(), H[k].end(), 0.0);
-      for (int c = 0; c < kk; ++c) H[k][(size_t)c * m + c] = thv[m - 1 - c];
+      for (int c = 0; c < kk; ++c) {
+        H[k][(size_t)c * m + c] = thv[m - 1 - c];
+        // coupling of the kept Ritz vectors to the residual direction (the arrow
+        // row of the restarted matrix), which the delayed re-orthogonalization of
+        // that direction needs; its column is recomputed in the next step
+        const double h = beta[k] * Sm[(size_t)(m - 1) * m + (m - 1 - c)].x;
+        H[k][(size_t)kk * m + c] = h;
+        H[k][(size_t)c * m + kk] = h;
+      }
       BW_HIP(hipStreamSynchronize(s));
     }
     j0 = kk;

@@ -592,106 +592,135 @@ static long active_units(const int* act, int nk, int J, hipStream_t s) {
   return u;
 }
 
-__global__ __launch_bounds__(NT) void k_mdot_finalize(const double* __restrict__ partial, int bpv, int J,
-                                                      const int* act, double2* out, int ldo) {
-  __shared__ double sh[NT / 64];
-  const int idx = blockIdx.x;  // k * J + i
-  const int k = idx / J, i = idx - k * J;
-  if (act && !act[k]) return;
-  double tot[2];
-  sum_partials<2>(tot, partial, idx, bpv, bpv, sh);
-  if (threadIdx.x == 0) out[(size_t)k * ldo + i] = make_double2(tot[0], tot[1]);
-}
-
-// The same products eight basis vectors per workgroup: the right-hand vector is
-// read once per group of eight instead of once per basis vector.  Per element
-// and per basis vector the accumulation order is that of k_mdot (same slices,
-// same wavefront and workgroup sums), so the results are identical.
+// Products of each basis vector with two right-hand vectors at once (the
+// delayed re-orthogonalization of the Lanczos process): out0[k, i] = <X_k[i],
+// Y0_k>, out1[k, i] = <X_k[i], Y1_k>, reading every basis vector once.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_mdot8(const cplx<T>* __restrict__ X, long xk, long xi, int J,
-                                              const cplx<T>* __restrict__ Y, long yk, long n, const int* act,
-                                              double* partial, int bpv) {
-  __shared__ double sh[16][NT / 64];
+__global__ __launch_bounds__(NT) void k_mdot8x2(const cplx<T>* __restrict__ X, long xk, long xi, int J,
+                                                const cplx<T>* __restrict__ Y0, long yk0,
+                                                const cplx<T>* __restrict__ Y1, long yk1, long n, const int* act,
+                                                double* partial, int bpv) {
+  __shared__ double sh[32][NT / 64];
   const int b = blockIdx.x, g = blockIdx.y, k = blockIdx.z;
   if (act && !act[k]) return;
   const int i0 = 8 * g;
   const int ni = J - i0 < 8 ? J - i0 : 8;
   const cplx<T>* x = X + (size_t)k * xk + (size_t)i0 * xi;
-  const cplx<T>* y = Y + (size_t)k * yk;
-  double sr[8], si[8];
+  const cplx<T>* y0 = Y0 + (size_t)k * yk0;
+  const cplx<T>* y1 = Y1 + (size_t)k * yk1;
+  double a0r[8], a0i[8], a1r[8], a1i[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) sr[i] = si[i] = 0.0;
+  for (int i = 0; i < 8; ++i) a0r[i] = a0i[i] = a1r[i] = a1i[i] = 0.0;
   for (long e = (long)b * NT + threadIdx.x; e < n; e += (long)bpv * NT) {
-    const double2 c = to_d2(y[e]);
+    const double2 c0 = to_d2(y0[e]), c1 = to_d2(y1[e]);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       if (i < ni) {
         const double2 a = to_d2(x[(size_t)i * xi + e]);
-        sr[i] += a.x * c.x + a.y * c.y;
-        si[i] += a.x * c.y - a.y * c.x;
+        a0r[i] += a.x * c0.x + a.y * c0.y;
+        a0i[i] += a.x * c0.y - a.y * c0.x;
+        a1r[i] += a.x * c1.x + a.y * c1.y;
+        a1i[i] += a.x * c1.y - a.y * c1.x;
       }
     }
   }
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const double r0 = wave_sum(sr[i]), r1 = wave_sum(si[i]);
+    const double r0 = wave_sum(a0r[i]), r1 = wave_sum(a0i[i]), r2 = wave_sum(a1r[i]), r3 = wave_sum(a1i[i]);
     if (l == 0) {
-      sh[2 * i][w] = r0;
-      sh[2 * i + 1][w] = r1;
+      sh[4 * i][w] = r0;
+      sh[4 * i + 1][w] = r1;
+      sh[4 * i + 2][w] = r2;
+      sh[4 * i + 3][w] = r3;
     }
   }
   __syncthreads();
   const int v = threadIdx.x;
-  if (v < 2 * ni) {
+  if (v < 4 * ni) {
     double acc = 0;
     for (int ww = 0; ww < NT / 64; ++ww) acc += sh[v][ww];
-    partial[((size_t)(k * J + i0 + (v >> 1)) * bpv + b) * 2 + (v & 1)] = acc;
+    partial[((size_t)(k * J + i0 + (v >> 2)) * bpv + b) * 4 + (v & 3)] = acc;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_mdot2_finalize(const double* __restrict__ partial, int bpv, int J,
+                                                       const int* act, double2* out0, double2* out1, int ldo) {
+  __shared__ double sh[NT / 64];
+  const int idx = blockIdx.x;  // k * J + i
+  const int k = idx / J, i = idx - k * J;
+  if (act && !act[k]) return;
+  double tot[4];
+  sum_partials<4>(tot, partial, idx, bpv, bpv, sh);
+  if (threadIdx.x == 0) {
+    out0[(size_t)k * ldo + i] = make_double2(tot[0], tot[1]);
+    out1[(size_t)k * ldo + i] = make_double2(tot[2], tot[3]);
   }
 }
 
 template <typename T>
-void launch_mdot(const cplx<T>* X, long xk, long xi, int J, const cplx<T>* Y, long yk, int nk, long n,
-                 const int* act, double2* out, int ldo, DevBuf& scratch, hipStream_t s) {
+void launch_mdot2(const cplx<T>* X, long xk, long xi, int J, const cplx<T>* Y0, long yk0, const cplx<T>* Y1, long yk1,
+                  int nk, long n, const int* act, double2* out0, double2* out1, int ldo, DevBuf& scratch,
+                  hipStream_t s) {
   if (J <= 0 || nk <= 0) return;
   int bpv = pw_blocks(n);
   if (bpv > 256) bpv = 256;
-  double* partial = (double*)scratch.get((size_t)nk * J * bpv * 2 * sizeof(double));
-  BW_LAUNCH("k_mdot", active_units(act, nk, J, s), (k_mdot8<T>), dim3(bpv, (J + 7) / 8, nk), dim3(NT), 0, s, X, xk, xi, J, Y, yk, n, act,
-            partial, bpv);
-  hipLaunchKernelGGL(k_mdot_finalize, dim3(nk * J), dim3(NT), 0, s, (const double*)partial, bpv, J, act, out, ldo);
+  double* partial = (double*)scratch.get((size_t)nk * J * bpv * 4 * sizeof(double));
+  BW_LAUNCH("k_mdot2", active_units(act, nk, J, s), (k_mdot8x2<T>), dim3(bpv, (J + 7) / 8, nk), dim3(NT), 0, s, X,
+            xk, xi, J, Y0, yk0, Y1, yk1, n, act, partial, bpv);
+  hipLaunchKernelGGL(k_mdot2_finalize, dim3(nk * J), dim3(NT), 0, s, (const double*)partial, bpv, J, act, out0, out1,
+                     ldo);
 }
 
+// The delayed re-orthogonalization update of one Lanczos step, one pass over
+// the J finished basis vectors X_k[0..J-1]:
+//   Y0_k <- f0 Y0_k - sum_i X_k[i] a_i                 (the pending vector, finished)
+//   Y1_k <- f1 Y1_k - sum_i X_k[i] b_i - g Y0_k(new)    (the new direction, once orthogonalized)
+// Coefficients of wave vector k at c + k * ldc: a[0..J-1], b[0..J-1], then
+// (f0, 0), (f1, 0), g.  Y1 == nullptr: the first output only.  FP64 accumulation.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mlincomb(cplx<T>* __restrict__ Y, long yk, const cplx<T>* __restrict__ X,
-                                                  long xk, long xi, int J, const double2* __restrict__ c, int ldc,
-                                                  double sign, long n, const int* act) {
+__global__ __launch_bounds__(256) void k_mlincomb2(cplx<T>* __restrict__ Y0, long yk0, cplx<T>* __restrict__ Y1,
+                                                   long yk1, const cplx<T>* __restrict__ X, long xk, long xi, int J,
+                                                   const double2* __restrict__ c, int ldc, long n, const int* act) {
   const int k = blockIdx.z;
   if (act && !act[k]) return;
   const cplx<T>* x = X + (size_t)k * xk;
-  cplx<T>* y = Y + (size_t)k * yk;
+  cplx<T>* y0 = Y0 + (size_t)k * yk0;
+  cplx<T>* y1 = Y1 ? Y1 + (size_t)k * yk1 : nullptr;
   const double2* ck = c + (size_t)k * ldc;
+  const double f0 = ck[2 * J].x, f1 = ck[2 * J + 1].x;
+  const double2 gg = ck[2 * J + 2];
   for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
-    double ar = 0, ai = 0;
+    double ar = 0, ai = 0, br = 0, bi = 0;
     for (int i = 0; i < J; ++i) {
-      const double2 a = to_d2(x[(size_t)i * xi + e]);
-      const double2 cc = ck[i];
-      ar += a.x * cc.x - a.y * cc.y;
-      ai += a.x * cc.y + a.y * cc.x;
+      const double2 v = to_d2(x[(size_t)i * xi + e]);
+      const double2 ca = ck[i];
+      ar += v.x * ca.x - v.y * ca.y;
+      ai += v.x * ca.y + v.y * ca.x;
+      if (y1) {
+        const double2 cb = ck[J + i];
+        br += v.x * cb.x - v.y * cb.y;
+        bi += v.x * cb.y + v.y * cb.x;
+      }
     }
-    const double2 o = to_d2(y[e]);
-    y[e] = from_d2<T>(make_double2(o.x + sign * ar, o.y + sign * ai));
+    const double2 o0 = to_d2(y0[e]);
+    const double vr = f0 * o0.x - ar, vi = f0 * o0.y - ai;
+    y0[e] = from_d2<T>(make_double2(vr, vi));
+    if (y1) {
+      const double2 o1 = to_d2(y1[e]);
+      y1[e] = from_d2<T>(make_double2(f1 * o1.x - br - (gg.x * vr - gg.y * vi), f1 * o1.y - bi - (gg.x * vi + gg.y * vr)));
+    }
   }
 }
 
 template <typename T>
-void launch_mlincomb(cplx<T>* Y, long yk, const cplx<T>* X, long xk, long xi, int J, const double2* c, int ldc,
-                     double sign, int nk, long n, const int* act, hipStream_t s) {
-  if (J <= 0 || nk <= 0) return;
+void launch_mlincomb2(cplx<T>* Y0, long yk0, cplx<T>* Y1, long yk1, const cplx<T>* X, long xk, long xi, int J,
+                      const double2* c, int ldc, int nk, long n, const int* act, hipStream_t s) {
+  if (nk <= 0) return;
   long nb = (n + 255) / 256;
   if (nb > 1024) nb = 1024;
-  BW_LAUNCH("k_mlincomb", active_units(act, nk, J, s), (k_mlincomb<T>), dim3((unsigned)nb, 1, nk), dim3(256), 0, s, Y, yk, X, xk,
-            xi, J, c, ldc, sign, n, act);
+  BW_LAUNCH("k_mlincomb2", active_units(act, nk, J, s), (k_mlincomb2<T>), dim3((unsigned)nb, 1, nk), dim3(256), 0, s,
+            Y0, yk0, Y1, yk1, X, xk, xi, J, c, ldc, n, act);
 }
 
 template <typename T>
@@ -777,10 +806,10 @@ void launch_add_hash(cplx<T>* X, long n, long vstride, int nv, unsigned long lon
   template void launch_scale_cols<T>(const cplx<T>*, const double*, cplx<T>*, int, long, long, hipStream_t);      \
   template void launch_deflate<T>(cplx<T>*, cplx<T>*, const cplx<T>*, int, long, long, double2*, hipStream_t);    \
   template void launch_planewaves<T>(cplx<T>*, int, long, const long*, const double*, hipStream_t);             \
-  template void launch_mdot<T>(const cplx<T>*, long, long, int, const cplx<T>*, long, int, long, const int*,      \
-                               double2*, int, DevBuf&, hipStream_t);                                                   \
-  template void launch_mlincomb<T>(cplx<T>*, long, const cplx<T>*, long, long, int, const double2*, int, double,   \
-                                   int, long, const int*, hipStream_t);                                           \
+  template void launch_mdot2<T>(const cplx<T>*, long, long, int, const cplx<T>*, long, const cplx<T>*, long, int,  \
+                                long, const int*, double2*, double2*, int, DevBuf&, hipStream_t);                   \
+  template void launch_mlincomb2<T>(cplx<T>*, long, cplx<T>*, long, const cplx<T>*, long, long, int,              \
+                                    const double2*, int, int, long, const int*, hipStream_t);                      \
   template void launch_scale_copy<T>(const cplx<T>*, long, cplx<T>*, long, const double*, int, long, const int*,  \
                                      hipStream_t);                                                                \
   template void launch_set_entries<T>(cplx<T>*, long, long, int, const long*, const long*, const double*,        \
