@@ -236,9 +236,12 @@ PcgResult pcg_run(bw_rve* r, const double* d_qtab, const QTable& qt, const cplx<
       if (graphs_enabled()) {
         // one chunk of iterations as a captured graph: identical launches with
         // identical arguments every time (per-vector scalars live on the device)
-        const std::vector<const void*> key = {(const void*)d_qtab, x, rv, p, Ap, W, pd.rz, pd.partial,
-                                              (const void*)(long)nvec, (const void*)(long)chunk,
-                                              (const void*)(long)sizeof(T), (const void*)(long)maxit};
+        std::vector<const void*> key = {(const void*)d_qtab, x, rv, p, Ap, W, pd.rz, pd.partial,
+                                        (const void*)(long)nvec, (const void*)(long)chunk,
+                                        (const void*)(long)sizeof(T), (const void*)(long)maxit,
+                                        (const void*)(long)r->csel.n};
+        // the cell selection is a kernel argument of the captured launches
+        for (int i = 0; i + 1 < r->csel.n; ++i) key.push_back((const void*)(long)r->csel.bound[i]);
         if (!r->pcg_exec || r->pcg_key != key) {
           // no allocation or free on another thread while this thread captures
           std::lock_guard<std::recursive_mutex> lk(capture_alloc_mutex());
@@ -476,6 +479,80 @@ static bool spd6(const double* c21) {
   return true;
 }
 
+// Device copies of a cell's (or a cell group's) tables: grain map(s) (ncell x
+// nvox; the transposed copy for the plane pass at n0 = n1 = 64), scaled stiffness
+// and density tables of all grains, inverse densities, counters, twiddles, and
+// for a group the per-cell reference stiffness rows.
+static void upload_cell_tables(bw_rve* r, const uint16_t* grain_map_host) {
+  const int n[3] = {r->g.n0, r->g.n1, r->g.n2};
+  const long nvox = r->g.nvox;
+  const long nmap = nvox * r->ncell;
+  const int n_grains = r->G;
+  std::vector<float> c32(r->C21s_host.begin(), r->C21s_host.end());
+  std::vector<float> r32(r->rhos_host.begin(), r->rhos_host.end());
+  std::vector<double> ri64(n_grains);
+  std::vector<float> ri32(n_grains);
+  for (int gi = 0; gi < n_grains; ++gi) {
+    ri64[gi] = 1.0 / r->rhos_host[gi];
+    ri32[gi] = (float)ri64[gi];
+  }
+  BW_HIP(hipMalloc(&r->d_rhoinv64, n_grains * sizeof(double)));
+  BW_HIP(hipMalloc(&r->d_rhoinv32, n_grains * sizeof(float)));
+  BW_HIP(hipMemcpy(r->d_rhoinv64, ri64.data(), n_grains * sizeof(double), hipMemcpyHostToDevice));
+  BW_HIP(hipMemcpy(r->d_rhoinv32, ri32.data(), n_grains * sizeof(float), hipMemcpyHostToDevice));
+  BW_HIP(hipMalloc(&r->d_ctr, 1024 * sizeof(unsigned)));
+  BW_HIP(hipMemset(r->d_ctr, 0, 1024 * sizeof(unsigned)));
+  BW_HIP(hipMalloc(&r->d_gmap, nmap * sizeof(uint16_t)));
+  BW_HIP(hipMalloc(&r->d_C64, r->C21s_host.size() * sizeof(double)));
+  BW_HIP(hipMalloc(&r->d_C32, c32.size() * sizeof(float)));
+  BW_HIP(hipMalloc(&r->d_rho64, n_grains * sizeof(double)));
+  BW_HIP(hipMalloc(&r->d_rho32, n_grains * sizeof(float)));
+  BW_HIP(hipMemcpy(r->d_gmap, grain_map_host, nmap * sizeof(uint16_t), hipMemcpyHostToDevice));
+  if (n[0] == 64 && n[1] == 64) {
+    std::vector<uint16_t> gt(nmap);
+    for (long c = 0; c < r->ncell; ++c)
+      for (long i0 = 0; i0 < 64; ++i0)
+        for (long i1 = 0; i1 < 64; ++i1)
+          for (long i2 = 0; i2 < n[2]; ++i2)
+            gt[c * nvox + (i2 * 64 + i0) * 64 + i1] = grain_map_host[c * nvox + (i0 * 64 + i1) * n[2] + i2];
+    BW_HIP(hipMalloc(&r->d_gmapT, nmap * sizeof(uint16_t)));
+    BW_HIP(hipMemcpy(r->d_gmapT, gt.data(), nmap * sizeof(uint16_t), hipMemcpyHostToDevice));
+  }
+  BW_HIP(hipMemcpy(r->d_C64, r->C21s_host.data(), r->C21s_host.size() * sizeof(double), hipMemcpyHostToDevice));
+  BW_HIP(hipMemcpy(r->d_C32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
+  BW_HIP(hipMemcpy(r->d_rho64, r->rhos_host.data(), n_grains * sizeof(double), hipMemcpyHostToDevice));
+  BW_HIP(hipMemcpy(r->d_rho32, r32.data(), n_grains * sizeof(float), hipMemcpyHostToDevice));
+  // twiddle tables exp(-2 pi i t / N), computed in long double
+  for (int a = 0; a < 3; ++a) {
+    const int N = n[a];
+    std::vector<double> t64(2 * N);
+    std::vector<float> t32(2 * N);
+    for (int t = 0; t < N; ++t) {
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)N;
+      t64[2 * t] = (double)cosl(ang);
+      t64[2 * t + 1] = (double)sinl(ang);
+      t32[2 * t] = (float)cosl(ang);
+      t32[2 * t + 1] = (float)sinl(ang);
+    }
+    BW_HIP(hipMalloc(&r->d_tw64[a], 2 * N * sizeof(double)));
+    BW_HIP(hipMalloc(&r->d_tw32[a], 2 * N * sizeof(float)));
+    BW_HIP(hipMemcpy(r->d_tw64[a], t64.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice));
+    BW_HIP(hipMemcpy(r->d_tw32[a], t32.data(), 2 * N * sizeof(float), hipMemcpyHostToDevice));
+  }
+  if (r->ncell > 1) {
+    std::vector<float> t32(r->cell_C0s.begin(), r->cell_C0s.end());
+    BW_HIP(hipMalloc(&r->d_C0tab64, r->cell_C0s.size() * sizeof(double)));
+    BW_HIP(hipMalloc(&r->d_C0tab32, t32.size() * sizeof(float)));
+    BW_HIP(hipMemcpy(r->d_C0tab64, r->cell_C0s.data(), r->cell_C0s.size() * sizeof(double), hipMemcpyHostToDevice));
+    BW_HIP(hipMemcpy(r->d_C0tab32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+}
+
+static uint64_t next_serial() {
+  static std::atomic<uint64_t> ctr{0};
+  return ++ctr;
+}
+
 extern "C" int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3], const uint16_t* grain_map_host,
                              int32_t n_grains, const double* C21_host, const double* rho_host, int32_t precision,
                              void* stream) {
@@ -547,55 +624,8 @@ extern "C" int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3]
       r->rhos_host[gi] = rho_host[gi] / r->rho_bar;
       if (count[gi] > 0) r->rho_min_s = std::min(r->rho_min_s, r->rhos_host[gi]);
     }
-    std::vector<float> c32(r->C21s_host.begin(), r->C21s_host.end());
-    std::vector<float> r32(r->rhos_host.begin(), r->rhos_host.end());
-    std::vector<double> ri64(n_grains);
-    std::vector<float> ri32(n_grains);
-    for (int gi = 0; gi < n_grains; ++gi) {
-      ri64[gi] = 1.0 / r->rhos_host[gi];
-      ri32[gi] = (float)ri64[gi];
-    }
-    BW_HIP(hipMalloc(&r->d_rhoinv64, n_grains * sizeof(double)));
-    BW_HIP(hipMalloc(&r->d_rhoinv32, n_grains * sizeof(float)));
-    BW_HIP(hipMemcpy(r->d_rhoinv64, ri64.data(), n_grains * sizeof(double), hipMemcpyHostToDevice));
-    BW_HIP(hipMemcpy(r->d_rhoinv32, ri32.data(), n_grains * sizeof(float), hipMemcpyHostToDevice));
-    BW_HIP(hipMalloc(&r->d_ctr, 1024 * sizeof(unsigned)));
-    BW_HIP(hipMemset(r->d_ctr, 0, 1024 * sizeof(unsigned)));
-    BW_HIP(hipMalloc(&r->d_gmap, nvox * sizeof(uint16_t)));
-    BW_HIP(hipMalloc(&r->d_C64, r->C21s_host.size() * sizeof(double)));
-    BW_HIP(hipMalloc(&r->d_C32, c32.size() * sizeof(float)));
-    BW_HIP(hipMalloc(&r->d_rho64, n_grains * sizeof(double)));
-    BW_HIP(hipMalloc(&r->d_rho32, n_grains * sizeof(float)));
-    BW_HIP(hipMemcpy(r->d_gmap, grain_map_host, nvox * sizeof(uint16_t), hipMemcpyHostToDevice));
-    if (n[0] == 64 && n[1] == 64) {
-      std::vector<uint16_t> gt(nvox);
-      for (long i0 = 0; i0 < 64; ++i0)
-        for (long i1 = 0; i1 < 64; ++i1)
-          for (long i2 = 0; i2 < n[2]; ++i2) gt[(i2 * 64 + i0) * 64 + i1] = grain_map_host[(i0 * 64 + i1) * n[2] + i2];
-      BW_HIP(hipMalloc(&r->d_gmapT, nvox * sizeof(uint16_t)));
-      BW_HIP(hipMemcpy(r->d_gmapT, gt.data(), nvox * sizeof(uint16_t), hipMemcpyHostToDevice));
-    }
-    BW_HIP(hipMemcpy(r->d_C64, r->C21s_host.data(), r->C21s_host.size() * sizeof(double), hipMemcpyHostToDevice));
-    BW_HIP(hipMemcpy(r->d_C32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
-    BW_HIP(hipMemcpy(r->d_rho64, r->rhos_host.data(), n_grains * sizeof(double), hipMemcpyHostToDevice));
-    BW_HIP(hipMemcpy(r->d_rho32, r32.data(), n_grains * sizeof(float), hipMemcpyHostToDevice));
-    // twiddle tables exp(-2 pi i t / N), computed in long double
-    for (int a = 0; a < 3; ++a) {
-      const int N = n[a];
-      std::vector<double> t64(2 * N);
-      std::vector<float> t32(2 * N);
-      for (int t = 0; t < N; ++t) {
-        const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)N;
-        t64[2 * t] = (double)cosl(ang);
-        t64[2 * t + 1] = (double)sinl(ang);
-        t32[2 * t] = (float)cosl(ang);
-        t32[2 * t + 1] = (float)sinl(ang);
-      }
-      BW_HIP(hipMalloc(&r->d_tw64[a], 2 * N * sizeof(double)));
-      BW_HIP(hipMalloc(&r->d_tw32[a], 2 * N * sizeof(float)));
-      BW_HIP(hipMemcpy(r->d_tw64[a], t64.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice));
-      BW_HIP(hipMemcpy(r->d_tw32[a], t32.data(), 2 * N * sizeof(float), hipMemcpyHostToDevice));
-    }
+    upload_cell_tables(r, grain_map_host);
+    r->serial = next_serial();
     (void)s;
   } catch (...) {
     bw_destroy_rve(r);
@@ -605,6 +635,93 @@ extern "C" int bw_create_rve(bw_rve** out, const int32_t n[3], const double L[3]
   return BW_OK;
   BW_GUARD_END
 }
+
+namespace bw {
+
+// A cell group: nc cells of one grid, cell edge and precision as one handle whose
+// vectors carry their cell (CellSel).  Grain maps are stacked with the grain
+// indices of cell c offset by the grains of the cells before it; all tables
+// share the first cell's scales (C' = C / Cref, rho' = rho / rho_bar), so K, M and
+// their eigenvalues keep one unit; every cell keeps its own reference stiffness C0
+// (the preconditioner) and smallest density (the bounds).  Cached in the first
+// cell's handle while the same cells are grouped again.
+bw_rve* cell_group(bw_rve* const* cells, int nc) {
+  BW_REQUIRE(nc >= 2 && nc <= CELLS_MAX, BW_EINVAL, "cell group size out of range");
+  bw_rve* c0 = cells[0];
+  std::vector<uint64_t> key(nc);
+  for (int c = 0; c < nc; ++c) key[c] = cells[c]->serial;
+  if (c0->group && c0->group_key == key) return c0->group;
+  if (c0->group) {
+    bw_destroy_rve(c0->group);
+    c0->group = nullptr;
+    c0->group_key.clear();
+  }
+  const long nvox = c0->g.nvox;
+  int G = 0;
+  for (int c = 0; c < nc; ++c) {
+    const bw_rve* x = cells[c];
+    BW_REQUIRE(x->ncell == 1, BW_EINVAL, "a cell group cannot contain a group");
+    BW_REQUIRE(x->g.n0 == c0->g.n0 && x->g.n1 == c0->g.n1 && x->g.n2 == c0->g.n2 && x->precision == c0->precision &&
+                   x->device == c0->device && x->L[0] == c0->L[0] && x->L[1] == c0->L[1] && x->L[2] == c0->L[2],
+               BW_EINVAL, "cells of a group need one grid, cell edge, precision and device");
+    G += x->G;
+  }
+  BW_REQUIRE(G <= 65535, BW_EINVAL, "too many grains in a cell group");
+  std::vector<uint16_t> gm((size_t)nc * nvox);
+  auto* r = new bw_rve();
+  try {
+    r->g = c0->g;
+    for (int a = 0; a < 3; ++a) r->L[a] = c0->L[a];
+    r->G = G;
+    r->precision = c0->precision;
+    r->device = c0->device;
+    r->ncu = c0->ncu;
+    r->Cref = c0->Cref;
+    r->ell = c0->ell;
+    r->rho_bar = c0->rho_bar;
+    for (int i = 0; i < 21; ++i) {
+      r->C0_si[i] = c0->C0_si[i];
+      r->C0s[i] = c0->C0s[i];
+    }
+    r->ncell = nc;
+    r->rho_unit = 1;
+    r->rho_min_s = INFINITY;
+    r->C21s_host.reserve((size_t)G * 21);
+    r->rhos_host.reserve(G);
+    int goff = 0;
+    for (int c = 0; c < nc; ++c) {
+      const bw_rve* x = cells[c];
+      BW_HIP(hipMemcpy(gm.data() + (size_t)c * nvox, x->d_gmap, nvox * sizeof(uint16_t), hipMemcpyDeviceToHost));
+      for (long i = 0; i < nvox; ++i) gm[(size_t)c * nvox + i] = (uint16_t)(gm[(size_t)c * nvox + i] + goff);
+      const double cs = x->Cref / r->Cref, rs = x->rho_bar / r->rho_bar;
+      for (int gi = 0; gi < x->G; ++gi) {
+        for (int i = 0; i < 21; ++i) r->C21s_host.push_back(x->C21s_host[(size_t)gi * 21 + i] * cs);
+        r->rhos_host.push_back(x->rhos_host[gi] * rs);
+      }
+      for (int i = 0; i < 21; ++i) r->cell_C0s.push_back(x->C0_si[i] / r->Cref);
+      r->cell_rho_min.push_back(x->rho_min_s * rs);
+      r->rho_min_s = std::min(r->rho_min_s, x->rho_min_s * rs);
+      if (!(x->rho_unit && x->rho_bar == r->rho_bar)) r->rho_unit = 0;
+      goff += x->G;
+    }
+    for (int a = 0; a < 3; ++a) {
+      r->tune_reg[a] = c0->tune_reg[a];
+      r->tune_cap[a] = c0->tune_cap[a];
+    }
+    r->tune_plane = c0->tune_plane;
+    r->tune_slab = c0->tune_slab;
+    upload_cell_tables(r, gm.data());
+    r->serial = next_serial();
+  } catch (...) {
+    bw_destroy_rve(r);
+    throw;
+  }
+  c0->group = r;
+  c0->group_key = key;
+  return r;
+}
+
+}  // namespace bw
 
 extern "C" void bw_destroy_rve(bw_rve* r) {
   if (!r) return;
@@ -620,6 +737,9 @@ extern "C" void bw_destroy_rve(bw_rve* r) {
   (void)hipFree(r->d_rhoinv64);
   (void)hipFree(r->d_rhoinv32);
   (void)hipFree(r->d_ctr);
+  (void)hipFree(r->d_C0tab32);
+  (void)hipFree(r->d_C0tab64);
+  if (r->group) bw_destroy_rve(r->group);
   for (int a = 0; a < 3; ++a) {
     (void)hipFree(r->d_tw64[a]);
     (void)hipFree(r->d_tw32[a]);

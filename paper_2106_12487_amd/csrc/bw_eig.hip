@@ -681,6 +681,49 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
   const bool fp32 = sizeof(T) == 4;
   QTable qt = make_qtable(r, k_list, nk);
   const double* dq = upload_qtable(r, qt, r->ws_q2, s);
+  // a cell group: wave vector k of the batch (and its vector in every batched
+  // launch) belongs to cell kcell[k]; the per-k steps (start vector, rigid modes,
+  // FP64 refinement and bounds) select that cell alone
+  const bool grouped = r->ncell > 1;
+  CellSel bsel;
+  std::vector<int> kcell(nk, 0);
+  const std::vector<double> C0s_first(r->C0s, r->C0s + 21);
+  const double rho_min_all = r->rho_min_s;
+  if (grouped) {
+    BW_REQUIRE((int)r->kcell_bounds.size() == r->ncell + 1, BW_EINVAL, "cell group without wave-vector bounds");
+    bsel.n = r->ncell;
+    bsel.gstride = g.nvox;
+    bsel.c0tab32 = r->d_C0tab32;
+    bsel.c0tab64 = r->d_C0tab64;
+    for (int i = 0; i + 1 < r->ncell; ++i) bsel.bound[i] = (int)std::max(0L, r->kcell_bounds[i + 1] - (long)kofs);
+    for (int k = 0; k < nk; ++k) kcell[k] = bsel.cell(k);
+  }
+  auto select_cell = [&](int c) {
+    if (!grouped) return;
+    CellSel u = bsel;
+    u.n = c + 1;
+    for (int i = 0; i < c; ++i) u.bound[i] = 0;
+    r->csel = u;
+    std::copy(r->cell_C0s.begin() + 21 * c, r->cell_C0s.begin() + 21 * (c + 1), r->C0s);
+    r->rho_min_s = r->cell_rho_min[c];
+  };
+  auto select_batch = [&]() {
+    if (!grouped) return;
+    r->csel = bsel;
+    std::copy(C0s_first.begin(), C0s_first.end(), r->C0s);
+    r->rho_min_s = rho_min_all;
+  };
+  struct Restore {   // the handle leaves in its one-cell state, also on errors
+    bw_rve* r;
+    std::vector<double> c0;
+    double rm;
+    ~Restore() {
+      r->csel = CellSel{};
+      std::copy(c0.begin(), c0.end(), r->C0s);
+      r->rho_min_s = rm;
+    }
+  } restore{r, C0s_first, rho_min_all};
+  select_batch();
   std::vector<int> nwk(nk);
   int nwmax = 0;
   for (int k = 0; k < nk; ++k) {
@@ -718,16 +761,20 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
   double* scd = (double*)(cfd + (size_t)nk * ldc);
   int* actd = (int*)(scd + nk);
   long jcache = -1;
-  auto ensure_MN = [&](long j) {
-    if (j != jcache) {
+  int ccache = -1;
+  auto ensure_MN = [&](long j, int c) {
+    if (j != jcache || c != ccache) {
+      select_cell(c);
       rigid_MN<T>(r, j, N3, MN, sm, cnt, s);
+      select_batch();
       jcache = j;
+      ccache = c;
     }
   };
   auto deflate_batch = [&](cplx<T>* Xb, cplx<T>* MXb, const std::vector<int>& act) {
     for (int k = 0; k < nk; ++k)
       if (act[k] && qt.null_index[k] >= 0) {
-        ensure_MN(qt.null_index[k]);
+        ensure_MN(qt.null_index[k], kcell[k]);
         launch_deflate<T>(Xb + (size_t)k * n3, MXb + (size_t)k * n3, MN, 1, g.nvox, qt.null_index[k], sm.coef, s);
       }
   };
@@ -749,7 +796,9 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       QTable q1 = make_qtable(r, k_list + 3 * k, 1);
       std::vector<long> vx;
       std::vector<double> pl;
+      select_cell(kcell[k]);
       reference_start(r, q1, 4, vx, pl);
+      select_batch();
       // plane waves at one voxel (several polarizations of one wave) are summed
       // here, so that every element of B is written by one thread only
       const size_t first = vox.size();
@@ -927,7 +976,9 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
         QTable qk = make_qtable(r, k1.data(), qsel);
         const double* dqk = upload_qtable(r, qk, r->ws_q3, s);
         std::vector<double> lam64, bnd;
+        select_cell(kcell[k]);
         refine64<T>(r, dqk, qk, qt.null_index[k], qsel, nw, lam64, bnd, bound_target, 3, cnt, s);
+        select_batch();
         const double wb = nw > 0 ? *std::max_element(bnd.begin(), bnd.end()) : 0.0;
         if (verbose()) fprintf(stderr, "[bw] lanczos k#%d FP64 bound %.3e\n", kofs + k, wb);
         const bool stalled = wb > 0.5 * best[k];  // the bound stopped improving (precision floor)
@@ -1128,10 +1179,14 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
   }
 }
 
-// Several cells (uneven grids) at once: every cell runs the driver above on a
-// stream of its own, from a host thread of its own, so that the kernels of
-// small cells overlap on the GPU.  Results are those of separate calls (same
-// kernels, same deterministic reductions).
+// Several cells at once.  Cells of one grid, cell edge and precision form a
+// group (Lanczos, no mode output): one handle whose batched launches carry the
+// wave vectors of all its cells, each vector with its own cell's grain map and
+// reference stiffness.  Every group, and every other cell, runs the driver above
+// on a stream of its own, from a host thread of its own, so that the kernels of
+// small cells overlap on the GPU.  A cell's results are those of a separate call
+// up to the rounding of the group's common scales (the same kernels, the same
+// deterministic reductions; bit for bit for an ungrouped cell).
 extern "C" int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const double* const* k_lists,
                                        const int32_t* nks, int32_t nmodes, const bw_eig_opts* opts,
                                        double* const* omegas, double* const* errs, void* const* modes,
@@ -1152,16 +1207,71 @@ extern "C" int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const 
     hipStream_t cs = (hipStream_t)stream;
     // work already queued on the caller's stream precedes the batch
     BW_HIP(hipStreamSynchronize(cs));
-    std::vector<hipStream_t> st(nrve, nullptr);
-    std::vector<int> code(nrve, BW_OK);
-    std::vector<std::string> msg(nrve);
-    std::vector<bw_stats> one(nrve);
+    // units of work: groups of cells of one grid, cell edge and precision, and single cells
+    const bool may_group = opts && opts->method == BW_LANCZOS && !modes && !opts->separate_cells &&
+                           opts->precond != BW_LEARNED;
+    auto same_kind = [](const bw_rve* a, const bw_rve* b) {
+      return a->ncell == 1 && b->ncell == 1 && a->g.n0 == b->g.n0 && a->g.n1 == b->g.n1 && a->g.n2 == b->g.n2 &&
+             a->precision == b->precision && a->device == b->device && a->L[0] == b->L[0] && a->L[1] == b->L[1] &&
+             a->L[2] == b->L[2];
+    };
+    std::vector<std::vector<int>> units;
+    {
+      std::vector<char> used(nrve, 0);
+      for (int i = 0; i < nrve; ++i) {
+        if (used[i]) continue;
+        std::vector<int> u = {i};
+        used[i] = 1;
+        if (may_group && nks[i] > 0)
+          for (int j = i + 1; j < nrve && (int)u.size() < CELLS_MAX; ++j)
+            if (!used[j] && nks[j] > 0 && same_kind(rves[i], rves[j])) {
+              u.push_back(j);
+              used[j] = 1;
+            }
+        units.push_back(u);
+      }
+    }
+    const int nu = (int)units.size();
     int cur = 0;
     BW_HIP(hipGetDevice(&cur));
+    // group handles (built here, not on the worker threads: allocation is serialized
+    // with graph captures) and their concatenated wave-vector lists
+    std::vector<bw_rve*> uh(nu, nullptr);
+    std::vector<std::vector<double>> ukl(nu), uom(nu), uer(nu);
     try {
-      for (int i = 0; i < nrve; ++i) {
-        BW_HIP(hipSetDevice(rves[i]->device));
-        BW_HIP(hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking));
+      for (int u = 0; u < nu; ++u) {
+        const std::vector<int>& c = units[u];
+        if (c.size() == 1) {
+          uh[u] = rves[c[0]];
+          continue;
+        }
+        BW_HIP(hipSetDevice(rves[c[0]]->device));
+        std::vector<bw_rve*> cells;
+        for (int i : c) cells.push_back(rves[i]);
+        bw_rve* gr = cell_group(cells.data(), (int)cells.size());
+        gr->kcell_bounds.assign(1, 0);
+        for (int i : c) {
+          ukl[u].insert(ukl[u].end(), k_lists[i], k_lists[i] + 3 * (size_t)nks[i]);
+          gr->kcell_bounds.push_back(gr->kcell_bounds.back() + nks[i]);
+        }
+        const size_t nkt = (size_t)gr->kcell_bounds.back();
+        uom[u].assign(nkt * nmodes, 0.0);
+        uer[u].assign(nkt * nmodes, 0.0);
+        uh[u] = gr;
+      }
+      BW_HIP(hipSetDevice(cur));
+    } catch (...) {
+      (void)hipSetDevice(cur);
+      throw;
+    }
+    std::vector<hipStream_t> st(nu, nullptr);
+    std::vector<int> code(nu, BW_OK);
+    std::vector<std::string> msg(nu);
+    std::vector<bw_stats> one(nu);
+    try {
+      for (int u = 0; u < nu; ++u) {
+        BW_HIP(hipSetDevice(uh[u]->device));
+        BW_HIP(hipStreamCreateWithFlags(&st[u], hipStreamNonBlocking));
       }
       BW_HIP(hipSetDevice(cur));
     } catch (...) {
@@ -1171,27 +1281,50 @@ extern "C" int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const 
       throw;
     }
     std::vector<std::thread> th;
-    th.reserve(nrve);
-    for (int i = 0; i < nrve; ++i)
-      th.emplace_back([&, i]() {
-        if (hipSetDevice(rves[i]->device) != hipSuccess) {
-          code[i] = BW_EHIP;
-          msg[i] = "hipSetDevice failed";
+    th.reserve(nu);
+    for (int u = 0; u < nu; ++u)
+      th.emplace_back([&, u]() {
+        if (hipSetDevice(uh[u]->device) != hipSuccess) {
+          code[u] = BW_EHIP;
+          msg[u] = "hipSetDevice failed";
           return;
         }
-        std::memset(&one[i], 0, sizeof(bw_stats));
-        code[i] = bw_lowest_modes(rves[i], k_lists[i], nks[i], nmodes, opts, omegas[i], errs ? errs[i] : nullptr,
-                                  modes ? modes[i] : nullptr, &one[i], st[i]);
-        if (code[i] != BW_OK) msg[i] = bw_last_error();
+        std::memset(&one[u], 0, sizeof(bw_stats));
+        const std::vector<int>& c = units[u];
+        if (c.size() == 1) {
+          const int i = c[0];
+          code[u] = bw_lowest_modes(rves[i], k_lists[i], nks[i], nmodes, opts, omegas[i], errs ? errs[i] : nullptr,
+                                    modes ? modes[i] : nullptr, &one[u], st[u]);
+        } else {
+          code[u] = bw_lowest_modes(uh[u], ukl[u].data(), (int)(ukl[u].size() / 3), nmodes, opts, uom[u].data(),
+                                    uer[u].data(), nullptr, &one[u], st[u]);
+        }
+        if (code[u] != BW_OK) msg[u] = bw_last_error();
       });
     for (auto& t : th) t.join();
     for (auto x : st) (void)hipStreamDestroy(x);
+    // the groups' rows back to their cells
+    for (int u = 0; u < nu; ++u) {
+      const std::vector<int>& c = units[u];
+      if (c.size() == 1) continue;
+      size_t row = 0;
+      for (int i : c) {
+        const size_t n = (size_t)nks[i] * nmodes;
+        std::copy(uom[u].begin() + row, uom[u].begin() + row + n, omegas[i]);
+        if (errs && errs[i]) std::copy(uer[u].begin() + row, uer[u].begin() + row + n, errs[i]);
+        row += n;
+      }
+    }
     int status = BW_OK;
     std::string first;
-    for (int i = 0; i < nrve; ++i) {
-      if (code[i] < 0 && (status >= 0 || code[i] < status)) status = code[i];
-      if (code[i] == BW_ENOTCONV && status == BW_OK) status = BW_ENOTCONV;
-      if (code[i] != BW_OK && first.empty()) first = "cell " + std::to_string(i) + ": " + msg[i];
+    for (int u = 0; u < nu; ++u) {
+      if (code[u] < 0 && (status >= 0 || code[u] < status)) status = code[u];
+      if (code[u] == BW_ENOTCONV && status == BW_OK) status = BW_ENOTCONV;
+      if (code[u] != BW_OK && first.empty()) {
+        std::string who = "cell";
+        for (int i : units[u]) who += " " + std::to_string(i);
+        first = who + ": " + msg[u];
+      }
     }
     if (stats) {
       std::memset(stats, 0, sizeof(bw_stats));

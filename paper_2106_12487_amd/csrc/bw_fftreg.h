@@ -170,7 +170,7 @@ __global__ __launch_bounds__(NT) void k_strain_row_r(const cplx<T>* __restrict__
                                                      cplx<T>* __restrict__ W, const double* __restrict__ qtab,
                                                      int n0, int n1, long nvox, int tpv,
                                                      const cplx<T>* __restrict__ tw, const int* __restrict__ active,
-                                                     const double* __restrict__ beta, C21v<T> C0) {
+                                                     const double* __restrict__ beta, C21v<T> C0, CellSel csel) {
   using V = cplx<T>;
   using F = RegFFT<N>;
   __shared__ V lds[2][F::BUF];
@@ -197,10 +197,11 @@ __global__ __launch_bounds__(NT) void k_strain_row_r(const cplx<T>* __restrict__
     for (int m = 0; m < 8; ++m) u[c][m] = U[((size_t)v * 3 + c) * nvox + rbase + F::posA(j, m)];
   if (MODE == 1) {
     const T bt = (T)beta[v];
+    const C21v<T> C0c = cell_c0<T>(csel, v, C0);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       V in[3] = {u[0][m], u[1][m], u[2][m]}, z[3];
-      precond3<T, V>(C0, qa, qb, qc[m], in, z);
+      precond3<T, V>(C0c, qa, qb, qc[m], in, z);
       const size_t o = rbase + F::posA(j, m);
       if (bt != T(0)) {
 #pragma unroll
@@ -391,7 +392,7 @@ template <typename T, int N, int OP, int PCG = 0>
 __global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, long n12, long nvox, int tpv,
                                                       const uint16_t* __restrict__ gmap, const T* __restrict__ Ctab,
                                                       T scale, const cplx<T>* __restrict__ tw,
-                                                      const int* __restrict__ active) {
+                                                      const int* __restrict__ active, CellSel csel) {
   using V = cplx<T>;
   using F = RegFFT<N>;
   constexpr int NC = OP == 0 ? 6 : 3;
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, l
   for (int c = 0; c < NC; ++c) fft_dit<T, N, true>(x[c], lds[0], lds[1], parity, slot, j, w);
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    const int g = gmap[pos + F::posB(j, m) * s12];
+    const int g = gmap[csel.goff(v) + pos + F::posB(j, m) * s12];
     if (OP == 0) {
       T cg[21];
 #pragma unroll
@@ -524,7 +525,7 @@ template <typename T, int PCG = 0, bool CL = false>
 __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W, int n2, int nplanes, long nvox,
                                                          const uint16_t* __restrict__ gmapT, const T* __restrict__ Ctab,
                                                          int ngrains, T scale, const cplx<T>* __restrict__ tw,
-                                                         const int* __restrict__ active) {
+                                                         const int* __restrict__ active, CellSel csel) {
   using V = cplx<T>;
   constexpr int NB = 64 * (64 + 8);   // 64 lines at the skewed row pitch (FFT exchanges, wavefront-local)
   __shared__ V lds[2][NB];
@@ -595,7 +596,7 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
     V* Wv = plane_ptr(p);
     int gm[8];                    // grain of point (i0 = j + 8m, i1 = line)
 #pragma unroll
-    for (int m = 0; m < 8; ++m) gm[m] = gmapT[(size_t)i2 * 4096 + (j + 8 * m) * 64 + line];
+    for (int m = 0; m < 8; ++m) gm[m] = gmapT[csel.goff(p / n2) + (size_t)i2 * 4096 + (j + 8 * m) * 64 + line];
 #pragma unroll
     for (int c = 0; c < 6; c += 2) {
       fft64_dit_pair<T, true>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i1

@@ -108,6 +108,26 @@ struct QTable {
 };
 
 // Geometry and per-launch tile choices of one cell.
+// Cells of one grid solved as one batch (bw_lowest_modes_batched): vector v of a
+// launch belongs to cell(v) = the number of bounds <= v; that cell's grain map
+// starts at cell * gstride and its reference stiffness C0 (scaled, 21 entries) is
+// row `cell` of c0tab32 / c0tab64.  n = 1 (the default): one cell, the kernels'
+// own C0 and grain map.
+constexpr int CELLS_MAX = 8;
+struct CellSel {
+  int n = 1;
+  int bound[CELLS_MAX - 1] = {};
+  long gstride = 0;
+  const float* c0tab32 = nullptr;
+  const double* c0tab64 = nullptr;
+  __host__ __device__ int cell(int v) const {
+    int c = 0;
+    for (int i = 0; i + 1 < n; ++i) c += v >= bound[i] ? 1 : 0;
+    return c;
+  }
+  __host__ __device__ long goff(int v) const { return n > 1 ? (long)cell(v) * gstride : 0; }
+};
+
 struct Geom {
   int n0, n1, n2;
   long nvox;
@@ -182,6 +202,20 @@ struct bw_rve {
   int tune_cap[3] = {0, 0, 0};
   int tune_plane = 1;   // FP32 cells with n0 = n1 = 64: the fused plane pass
   int tune_slab = 1;    // FP32 cells with n1 = n2 = 128: the three-pass slab path
+  // cell groups (several cells of one grid in one batch; bw_lowest_modes_batched):
+  // ncell cells, grain map [ncell][nvox], grain tables of all cells in one scale,
+  // per-cell scaled C0 and smallest scaled density; csel maps the vectors of the
+  // current launches to cells, kcell_bounds the wave vectors of the batched call
+  int ncell = 1;
+  bw::CellSel csel;
+  std::vector<double> cell_C0s;      // ncell x 21
+  std::vector<double> cell_rho_min;  // ncell
+  std::vector<long> kcell_bounds;    // ncell + 1 (first wave vector of each cell)
+  float* d_C0tab32 = nullptr;
+  double* d_C0tab64 = nullptr;
+  uint64_t serial = 0;               // unique per handle (group cache key)
+  bw_rve* group = nullptr;           // cached group of this cell with others
+  std::vector<uint64_t> group_key;
   // captured PCG chunk (replayed with hipGraphLaunch while its key matches)
   hipStream_t cap_stream = nullptr;
   hipGraph_t pcg_graph = nullptr;
@@ -190,6 +224,10 @@ struct bw_rve {
 };
 
 namespace bw {
+
+// The group handle of nc >= 2 cells of one grid, cell edge and precision
+// (created on first use and cached in cells[0]; freed with it).
+bw_rve* cell_group(bw_rve* const* cells, int nc);
 
 // q tables for a list of k (SI, rad/m); fills null_index.
 QTable make_qtable(const bw_rve* r, const double* k_host, int nk);

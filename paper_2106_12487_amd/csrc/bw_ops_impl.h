@@ -26,6 +26,19 @@ namespace bw {
 
 template <typename T> struct C21v { T c[21]; };
 
+// the reference stiffness C0 of vector v's cell (the kernel's own C0 for one cell)
+template <typename T> __device__ __forceinline__ C21v<T> cell_c0(const CellSel& cs, int v, const C21v<T>& C0) {
+  const T* tab;
+  if constexpr (sizeof(T) == 4) tab = (const T*)cs.c0tab32;
+  else tab = (const T*)cs.c0tab64;
+  if (cs.n <= 1 || !tab) return C0;
+  C21v<T> c;
+  const T* row = tab + (size_t)cs.cell(v) * 21;
+#pragma unroll
+  for (int i = 0; i < 21; ++i) c.c[i] = row[i];
+  return c;
+}
+
 // Voigt upper-triangle index of (a, b)
 __host__ __device__ constexpr int vidx(int a, int b) {
   return a <= b ? a * 6 - (a * (a - 1)) / 2 + (b - a) : b * 6 - (b * (b - 1)) / 2 + (a - b);
@@ -212,7 +225,7 @@ __global__ __launch_bounds__(NT) void k_strain_row(const cplx<T>* __restrict__ U
                                                    cplx<T>* __restrict__ W, const double* __restrict__ qtab,
                                                    int n0, int n1, long nvox, RowTile rt,
                                                    const cplx<T>* __restrict__ tw, const int* __restrict__ active,
-                                                   const double* __restrict__ beta, C21v<T> C0) {
+                                                   const double* __restrict__ beta, C21v<T> C0, CellSel csel) {
   using V = cplx<T>;
   constexpr int TP = TileCfg<T>::TP;
   constexpr int PPT = TP / NT;
@@ -226,6 +239,7 @@ __global__ __launch_bounds__(NT) void k_strain_row(const cplx<T>* __restrict__ U
   const double* q = qtab + (size_t)v * (n0 + n1 + N2);
   T bt = 0;
   if (MODE == 1) bt = (T)beta[v];
+  const C21v<T> C0c = MODE == 1 ? cell_c0<T>(csel, v, C0) : C0;
   V u[3][PPT];
   T qa[PPT], qb[PPT], qc[PPT];
   int off[PPT];
@@ -246,7 +260,7 @@ __global__ __launch_bounds__(NT) void k_strain_row(const cplx<T>* __restrict__ U
       for (int c = 0; c < 3; ++c) w[c] = U[((size_t)v * 3 + c) * nvox + off[s]];
       if (MODE == 1) {
         V z[3];
-        precond3<T, V>(C0, qa[s], qb[s], qc[s], w, z);
+        precond3<T, V>(C0c, qa[s], qb[s], qc[s], w, z);
         if (bt != T(0)) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) z[c] = caxpy(z[c], bt, Pp[((size_t)v * 3 + c) * nvox + off[s]]);
@@ -474,7 +488,7 @@ template <typename T, int N0, int OP, int PCG = 0>
 __global__ __launch_bounds__(NT) void k_axis0_op(cplx<T>* __restrict__ X, long n12, long nvox, ColTile ct,
                                                  const uint16_t* __restrict__ gmap, const T* __restrict__ Ctab,
                                                  T scale, const cplx<T>* __restrict__ tw,
-                                                 const int* __restrict__ active) {
+                                                 const int* __restrict__ active, CellSel csel) {
   using V = cplx<T>;
   constexpr int NC = OP == 0 ? 6 : 3;
   constexpr int TP = TileCfg<T>::TP;
@@ -513,7 +527,7 @@ __global__ __launch_bounds__(NT) void k_axis0_op(cplx<T>* __restrict__ X, long n
     const int idx = tid + s * NT;
     if (idx < npts) {
       const int n = idx >> ct.lsh;
-      const int g = gmap[(size_t)n * n12 + pos];
+      const int g = gmap[csel.goff(v) + (size_t)n * n12 + pos];
       if (OP == 0) {
         T cg[21];
 #pragma unroll
@@ -592,18 +606,19 @@ inline VoxIdx voxidx(const Geom& g) { return VoxIdx{g.n0, g.n1, g.n2, log2_exact
 template <typename T>
 __global__ __launch_bounds__(NT) void k_apply_P(const cplx<T>* __restrict__ U, cplx<T>* __restrict__ Y,
                                                 const double* __restrict__ qtab, VoxIdx vi, long nvox, int bpv,
-                                                C21v<T> C0, T scale) {
+                                                C21v<T> C0, T scale, CellSel csel) {
   using V = cplx<T>;
   const int v = blockIdx.x / bpv;
   const int b = blockIdx.x - v * bpv;
   const double* q = qtab + (size_t)v * (vi.n0 + vi.n1 + vi.n2);
+  const C21v<T> C0c = cell_c0<T>(csel, v, C0);
   for (long vox = (long)b * NT + threadIdx.x; vox < nvox; vox += (long)bpv * NT) {
     int i0, i1, i2;
     vi.split(vox, i0, i1, i2);
     V r[3], z[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[c] = U[((size_t)v * 3 + c) * nvox + vox];
-    precond3<T, V>(C0, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], r, z);
+    precond3<T, V>(C0c, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], r, z);
 #pragma unroll
     for (int c = 0; c < 3; ++c) Y[((size_t)v * 3 + c) * nvox + vox] = cscale(z[c], scale);
   }
@@ -616,7 +631,7 @@ template <typename T, bool WZ = false>
 __global__ __launch_bounds__(NT) void k_pcg_update(cplx<T>* __restrict__ x, cplx<T>* __restrict__ r,
                                                    const cplx<T>* __restrict__ p, cplx<T>* __restrict__ Ap,
                                                    const double* __restrict__ qtab, VoxIdx vi, long nvox, int bpv,
-                                                   C21v<T> C0, PcgDev pd) {
+                                                   C21v<T> C0, PcgDev pd, CellSel csel) {
   using V = cplx<T>;
   __shared__ double sh[NT / 64];
   const int v = blockIdx.x / bpv;
@@ -624,6 +639,7 @@ __global__ __launch_bounds__(NT) void k_pcg_update(cplx<T>* __restrict__ x, cplx
   if (!pd.active[v]) return;
   const T al = (T)pd.alpha[v];
   const double* q = qtab + (size_t)v * (vi.n0 + vi.n1 + vi.n2);
+  const C21v<T> C0c = cell_c0<T>(csel, v, C0);
   double rz = 0, rr = 0;
   for (long vox = (long)b * NT + threadIdx.x; vox < nvox; vox += (long)bpv * NT) {
     int i0, i1, i2;
@@ -637,7 +653,7 @@ __global__ __launch_bounds__(NT) void k_pcg_update(cplx<T>* __restrict__ x, cplx
       rv[c] = caxpy(r[o], -al, Ap[o]);
       r[o] = rv[c];
     }
-    precond3<T, V>(C0, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], rv, z);
+    precond3<T, V>(C0c, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], rv, z);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       rz += (double)rv[c].x * z[c].x + (double)rv[c].y * z[c].y;
@@ -693,13 +709,15 @@ __global__ __launch_bounds__(NT) void k_norms2(const cplx<T>* __restrict__ bv, c
 template <typename T>
 __global__ __launch_bounds__(NT) void k_pcg_restart(const cplx<T>* __restrict__ r, const double* __restrict__ qtab,
                                                     VoxIdx vi, long nvox, int bpv, C21v<T> C0, PcgDev pd,
-                                                    const int* __restrict__ mask, cplx<T>* __restrict__ zout) {
+                                                    const int* __restrict__ mask, cplx<T>* __restrict__ zout,
+                                                    CellSel csel) {
   using V = cplx<T>;
   __shared__ double sh[NT / 64];
   const int v = blockIdx.x / bpv;
   const int b = blockIdx.x - v * bpv;
   if (!mask[v]) return;
   const double* q = qtab + (size_t)v * (vi.n0 + vi.n1 + vi.n2);
+  const C21v<T> C0c = cell_c0<T>(csel, v, C0);
   double rz = 0;
   for (long vox = (long)b * NT + threadIdx.x; vox < nvox; vox += (long)bpv * NT) {
     int i0, i1, i2;
@@ -707,7 +725,7 @@ __global__ __launch_bounds__(NT) void k_pcg_restart(const cplx<T>* __restrict__ 
     V rv[3], z[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) rv[c] = r[((size_t)v * 3 + c) * nvox + vox];
-    precond3<T, V>(C0, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], rv, z);
+    precond3<T, V>(C0c, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], rv, z);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       rz += (double)rv[c].x * z[c].x + (double)rv[c].y * z[c].y;
@@ -881,20 +899,20 @@ void launch_axis0(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* act
       const int tpv = (int)(n12 / reg_lines(n0c));
       if (active)
         BW_LAUNCH(name0, units0, (k_axis0_op_r<T, n0c, OP, 1>), dim3(nvec * tpv), dim3(NT), 0, s, W, n12, g.nvox,
-                  tpv, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+                  tpv, r->d_gmap, tab, scale, twiddles<T>(r, 0), active, r->csel);
       else
         BW_LAUNCH(name0, units0, (k_axis0_op_r<T, n0c, OP, 0>), dim3(nvec * tpv), dim3(NT), 0, s, W, n12, g.nvox,
-                  tpv, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+                  tpv, r->d_gmap, tab, scale, twiddles<T>(r, 0), active, r->csel);
     });
   } else {
     with_n(g.n0, [&](auto N0) {
       ColTile ct = axis0_tile<T>(N0, n12, r->tune_cap[0]);
       if (active)
         BW_LAUNCH(name0, units0, (k_axis0_op<T, decltype(N0)::value, OP, 1>), dim3(nvec * ct.tpv), dim3(NT), 0, s,
-                  W, n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+                  W, n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active, r->csel);
       else
         BW_LAUNCH(name0, units0, (k_axis0_op<T, decltype(N0)::value, OP>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W,
-                  n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active);
+                  n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active, r->csel);
     });
   }
 }
@@ -949,17 +967,17 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
         if (mode == 0)
           BW_LAUNCH("k_strain_row", nvec, (k_strain_row_r<T, n2c, 0, true>), dim3(nvec * tpvr), dim3(NT), 0, s, u,
                     (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active,
-                    (const double*)nullptr, c0v<T>(r));
+                    (const double*)nullptr, c0v<T>(r), r->csel);
         else
           BW_LAUNCH("k_strain_row_pcg", 0, (k_strain_row_r<T, n2c, 1, true>), dim3(nvec * tpvr), dim3(NT), 0, s, u,
-                    pp, W, d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
+                    pp, W, d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r), r->csel);
       } else if (mode == 0)
         BW_LAUNCH("k_strain_row", nvec, (k_strain_row_r<T, n2c, 0>), dim3(nvec * tpvr), dim3(NT), 0, s, u,
                   (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active,
-                  (const double*)nullptr, c0v<T>(r));
+                  (const double*)nullptr, c0v<T>(r), r->csel);
       else
         BW_LAUNCH("k_strain_row_pcg", 0, (k_strain_row_r<T, n2c, 1>), dim3(nvec * tpvr), dim3(NT), 0, s, u, pp, W,
-                  d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
+                  d_qtab, g.n0, g.n1, g.nvox, tpvr, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r), r->csel);
     });
   } else {
     with_n(g.n2, [&](auto N2) {
@@ -968,10 +986,10 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
       if (mode == 0)
         BW_LAUNCH("k_strain_row", nvec, (k_strain_row<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u,
                   (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active,
-                  (const double*)nullptr, c0v<T>(r));
+                  (const double*)nullptr, c0v<T>(r), r->csel);
       else
         BW_LAUNCH("k_strain_row_pcg", 0, (k_strain_row<T, n2c, 1>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, pp, W,
-                  d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r));
+                  d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active, pd->beta, c0v<T>(r), r->csel);
     });
   }
   if (plane) {
@@ -984,17 +1002,21 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
       if (active) {
         if (cl)
           BW_LAUNCH("k_plane_contract_pcg", 0, (k_plane64<T, 1, true>), dim3(grid), dim3(PLANE_NT), 0, s, W, g.n2,
-                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active);
+                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active,
+                    r->csel);
         else
           BW_LAUNCH("k_plane_contract_pcg", 0, (k_plane64<T, 1, false>), dim3(grid), dim3(PLANE_NT), 0, s, W, g.n2,
-                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active);
+                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active,
+                    r->csel);
       } else {
         if (cl)
           BW_LAUNCH("k_plane_contract", nvec, (k_plane64<T, 0, true>), dim3(grid), dim3(PLANE_NT), 0, s, W, g.n2,
-                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active);
+                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active,
+                    r->csel);
         else
           BW_LAUNCH("k_plane_contract", nvec, (k_plane64<T, 0, false>), dim3(grid), dim3(PLANE_NT), 0, s, W, g.n2,
-                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active);
+                    nplanes, g.nvox, r->d_gmapT, ctab<T>(r), r->G, sc, twiddles<T>(r, 0), active,
+                    r->csel);
       }
     }
   } else {
@@ -1090,7 +1112,7 @@ void launch_apply_P(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cpl
   const Geom& g = r->g;
   const int bpv = pw_blocks(g.nvox);
   hipLaunchKernelGGL((k_apply_P<T>), dim3(nvec * bpv), dim3(NT), 0, s, u, y, d_qtab, voxidx(g),
-                     g.nvox, bpv, c0v<T>(r), (T)scale);
+                     g.nvox, bpv, c0v<T>(r), (T)scale, r->csel);
 }
 
 template <typename T>
@@ -1106,10 +1128,10 @@ void launch_pcg_update(const bw_rve* r, const double* d_qtab, cplx<T>* x, cplx<T
   const int bpv = pw_blocks(g.nvox);
   if (slab_path<T>(r))
     BW_LAUNCH("k_pcg_update_z", 0, (k_pcg_update<T, true>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
-              voxidx(g), g.nvox, bpv, c0v<T>(r), pd);
+              voxidx(g), g.nvox, bpv, c0v<T>(r), pd, r->csel);
   else
     BW_LAUNCH("k_pcg_update", 0, (k_pcg_update<T>), dim3(nvec * bpv), dim3(NT), 0, s, x, rv, p, Ap, d_qtab,
-              voxidx(g), g.nvox, bpv, c0v<T>(r), pd);
+              voxidx(g), g.nvox, bpv, c0v<T>(r), pd, r->csel);
   hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_BETA, bpv, pd, (const int*)nullptr,
                      (double*)nullptr, (double*)nullptr);
 }
@@ -1149,7 +1171,8 @@ void launch_pcg_restart(const bw_rve* r, const double* d_qtab, const cplx<T>* rv
   const Geom& g = r->g;
   const int bpv = pw_blocks(g.nvox);
   hipLaunchKernelGGL((k_pcg_restart<T>), dim3(nvec * bpv), dim3(NT), 0, s, rv, d_qtab, voxidx(g),
-                     g.nvox, bpv, c0v<T>(r), pd, d_mask, slab_path<T>(r) ? Ap : (cplx<T>*)nullptr);
+                     g.nvox, bpv, c0v<T>(r), pd, d_mask, slab_path<T>(r) ? Ap : (cplx<T>*)nullptr,
+                     r->csel);
   hipLaunchKernelGGL(k_finalize, dim3(nvec), dim3(NT), 0, s, (int)FIN_RESTART, bpv, pd, d_mask, (double*)nullptr,
                      (double*)nullptr);
 }
