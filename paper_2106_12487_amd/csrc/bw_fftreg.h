@@ -407,6 +407,7 @@ __global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, l
   load_twr<T, N>(w, tw, j);
   // 32-bit offsets within the vector (NC * nvox < 2^31, checked by the host)
   cplx<T>* Xv = X + (size_t)v * NC * nvox;
+  const uint16_t* __restrict__ gmv = gmap + csel.goff(v);   // this vector's cell
   const int s12 = (int)n12, cs = (int)nvox;
   V x[NC][8];
 #pragma unroll
@@ -419,7 +420,7 @@ __global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, l
   for (int c = 0; c < NC; ++c) fft_dit<T, N, true>(x[c], lds[0], lds[1], parity, slot, j, w);
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    const int g = gmap[csel.goff(v) + pos + F::posB(j, m) * s12];
+    const int g = gmv[pos + F::posB(j, m) * s12];
     if (OP == 0) {
       T cg[21];
 #pragma unroll
@@ -595,8 +596,9 @@ __global__ __launch_bounds__(PLANE_NT, 1) void k_plane64(cplx<T>* __restrict__ W
     const int i2 = p % n2;
     V* Wv = plane_ptr(p);
     int gm[8];                    // grain of point (i0 = j + 8m, i1 = line)
+    const uint16_t* __restrict__ gmp = gmapT + csel.goff(p / n2) + (size_t)i2 * 4096;   // this plane's cell
 #pragma unroll
-    for (int m = 0; m < 8; ++m) gm[m] = gmapT[csel.goff(p / n2) + (size_t)i2 * 4096 + (j + 8 * m) * 64 + line];
+    for (int m = 0; m < 8; ++m) gm[m] = gmp[(j + 8 * m) * 64 + line];
 #pragma unroll
     for (int c = 0; c < 6; c += 2) {
       fft64_dit_pair<T, true>(x[c], x[c + 1], lds[0], lds[1], slot, j, w);   // along i1

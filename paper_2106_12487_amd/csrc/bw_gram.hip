@@ -133,16 +133,18 @@ __global__ __launch_bounds__(256) void k_ritz(const cplx<T>* __restrict__ X, int
     double2 acc[QO];
 #pragma unroll
     for (int j = 0; j < QO; ++j) acc[j] = make_double2(0, 0);
+#pragma unroll 2
     for (int p = 0; p < q; ++p) {
       const double2 x = to_d2(X[(size_t)p * vstride + e]);
       const double2* __restrict__ Qp = Q + (size_t)p * ldq;
 #pragma unroll
       for (int j = 0; j < QO; ++j) {
-        if (j < qout) {
-          const double2 c = Qp[j];
-          acc[j].x += x.x * c.x - x.y * c.y;
-          acc[j].y += x.x * c.y + x.y * c.x;
-        }
+        // columns past qout take coefficient 0 (a uniform select, not a branch,
+        // so the coefficients stay scalar loads in batches)
+        double2 c = Qp[j < qout ? j : qout - 1];
+        if (j >= qout) c = make_double2(0.0, 0.0);
+        acc[j].x += x.x * c.x - x.y * c.y;
+        acc[j].y += x.x * c.y + x.y * c.x;
       }
     }
 #pragma unroll
@@ -162,6 +164,9 @@ void launch_ritz(const cplx<T>* X, int q, const double2* Q, int ldq, cplx<T>* Y,
               vstride);
   else if (qout <= 16)
     BW_LAUNCH("k_ritz", (long)q * qout, (k_ritz<T, 16>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y, qout,
+              n, vstride);
+  else if (qout <= 24)
+    BW_LAUNCH("k_ritz", (long)q * qout, (k_ritz<T, 24>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y, qout,
               n, vstride);
   else
     BW_LAUNCH("k_ritz", (long)q * qout, (k_ritz<T, GRAM_QMAX>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y,

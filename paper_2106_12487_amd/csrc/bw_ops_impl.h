@@ -495,6 +495,7 @@ __global__ __launch_bounds__(NT) void k_axis0_op(cplx<T>* __restrict__ X, long n
   constexpr int PPT = TP / NT;
   __shared__ V lds[TP];
   const int v = blockIdx.x / ct.tpv;
+  const uint16_t* __restrict__ gmv = gmap + csel.goff(v);   // this vector's cell
   if (active && !active[v]) return;
   const int tile = blockIdx.x - v * ct.tpv;
   const int tid = threadIdx.x;
@@ -527,7 +528,7 @@ __global__ __launch_bounds__(NT) void k_axis0_op(cplx<T>* __restrict__ X, long n
     const int idx = tid + s * NT;
     if (idx < npts) {
       const int n = idx >> ct.lsh;
-      const int g = gmap[csel.goff(v) + (size_t)n * n12 + pos];
+      const int g = gmv[(size_t)n * n12 + pos];
       if (OP == 0) {
         T cg[21];
 #pragma unroll
