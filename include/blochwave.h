@@ -161,12 +161,16 @@ void bw_destroy_rve(bw_rve* rve);
  * of it, and keeps the fastest for this cell (used by every later operator
  * apply and PCG; results agree to rounding whatever the schedule).
  * speedup_host (optional) receives time(default schedule) / time(chosen).
+ * A BW_MIXED cell also gets a schedule of its own for its FP64 applies (the
+ * Rayleigh-Ritz refinement), timed on min(nvec, 16) FP64 vectors.
  * Allocates and frees two scratch blocks of nvec vectors.  Synchronizes `stream`. */
 int bw_autotune(bw_rve* rve, int32_t nvec, double* speedup_host, void* stream);
 
 /* Get (set = 0) or set (set != 0) the FFT schedule of a cell per axis 0..2:
  * reg[a] != 0 uses the register kernels where the length allows, cap[a] > 0
- * limits the lines per tile of the generic kernels (0 = as many as fit). */
+ * limits the lines per tile of the generic kernels (0 = as many as fit).  Set
+ * applies to the FP32 and FP64 kernels alike; get returns the schedule of the
+ * cell's main precision (FP32 for BW_MIXED). */
 int bw_fft_schedule(bw_rve* rve, int32_t reg[3], int32_t cap[3], int32_t set);
 
 /* Query grid / precision / volume averages of a cell.  Any output may be NULL. */

@@ -704,10 +704,11 @@ bw_rve* cell_group(bw_rve* const* cells, int nc) {
       if (!(x->rho_unit && x->rho_bar == r->rho_bar)) r->rho_unit = 0;
       goff += x->G;
     }
-    for (int a = 0; a < 3; ++a) {
-      r->tune_reg[a] = c0->tune_reg[a];
-      r->tune_cap[a] = c0->tune_cap[a];
-    }
+    for (int t = 0; t < 2; ++t)
+      for (int a = 0; a < 3; ++a) {
+        r->tune_reg[t][a] = c0->tune_reg[t][a];
+        r->tune_cap[t][a] = c0->tune_cap[t][a];
+      }
     r->tune_plane = c0->tune_plane;
     r->tune_slab = c0->tune_slab;
     upload_cell_tables(r, gm.data());
@@ -873,12 +874,15 @@ template <typename T> static double autotune_impl(bw_rve* r, int nvec, hipStream
     BW_HIP(hipEventElapsedTime(&ms, e0, e1));
     return (double)ms / 3.0;
   };
+  constexpr int ts = tsel<T>;
   for (int a = 0; a < 3; ++a) {
-    r->tune_reg[a] = 1;
-    r->tune_cap[a] = 0;
+    r->tune_reg[ts][a] = 1;
+    r->tune_cap[ts][a] = 0;
   }
-  r->tune_plane = 1;
-  r->tune_slab = 1;
+  if (sizeof(T) == 4) {
+    r->tune_plane = 1;
+    r->tune_slab = 1;
+  }
   const double t_default = time_apply();
   if (r->d_gmapT && sizeof(T) == 4) {
     r->tune_plane = 0;
@@ -899,16 +903,16 @@ template <typename T> static double autotune_impl(bw_rve* r, int nvec, hipStream
     double best = 1e300;
     std::pair<int, int> pick = cand[0];
     for (auto& c : cand) {
-      r->tune_reg[a] = c.first;
-      r->tune_cap[a] = c.second;
+      r->tune_reg[ts][a] = c.first;
+      r->tune_cap[ts][a] = c.second;
       const double t = time_apply();
       if (t < best) {
         best = t;
         pick = c;
       }
     }
-    r->tune_reg[a] = pick.first;
-    r->tune_cap[a] = pick.second;
+    r->tune_reg[ts][a] = pick.first;
+    r->tune_cap[ts][a] = pick.second;
   }
   const double t_best = time_apply();
   (void)hipEventDestroy(e0);
@@ -979,6 +983,9 @@ extern "C" int bw_autotune(bw_rve* r, int32_t nvec, double* speedup_host, void* 
   BW_REQUIRE(nvec >= 1 && nvec <= 256, BW_EINVAL, "nvec out of range (1 .. 256)");
   hipStream_t s = (hipStream_t)stream;
   const double sp = r->precision == BW_FP64 ? autotune_impl<double>(r, nvec, s) : autotune_impl<float>(r, nvec, s);
+  // a mixed cell's FP64 applies (Rayleigh-Ritz refinement of a few Ritz vectors)
+  // get their own schedule
+  if (r->precision == BW_MIXED) (void)autotune_impl<double>(r, std::min(nvec, 16), s);
   if (speedup_host) *speedup_host = sp;
   return BW_OK;
   BW_GUARD_END
@@ -991,15 +998,17 @@ extern "C" int bw_fft_schedule(bw_rve* r, int32_t reg[3], int32_t cap[3], int32_
     for (int a = 0; a < 3; ++a) BW_REQUIRE(cap[a] >= 0, BW_EINVAL, "tile cap must be >= 0");
     r->tune_plane = reg[0] && reg[1] ? 1 : 0;
     r->tune_slab = reg[1] && reg[2] ? 1 : 0;
-    for (int a = 0; a < 3; ++a) {
-      r->tune_reg[a] = reg[a] ? 1 : 0;
-      r->tune_cap[a] = cap[a];
-    }
+    for (int t = 0; t < 2; ++t)
+      for (int a = 0; a < 3; ++a) {
+        r->tune_reg[t][a] = reg[a] ? 1 : 0;
+        r->tune_cap[t][a] = cap[a];
+      }
     drop_graph(r);
   } else {
+    const int t = r->precision == BW_FP64 ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
-      reg[a] = r->tune_reg[a];
-      cap[a] = r->tune_cap[a];
+      reg[a] = r->tune_reg[t][a];
+      cap[a] = r->tune_cap[t][a];
     }
   }
   return BW_OK;

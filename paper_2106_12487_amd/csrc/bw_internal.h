@@ -198,8 +198,10 @@ struct bw_rve {
   // FFT schedule per axis (0, 1, 2): register kernels where the length allows
   // (tune_reg) and the cap on lines per tile of the generic LDS kernels (0 =
   // as many as fit); set by bw_autotune
-  int tune_reg[3] = {1, 1, 1};
-  int tune_cap[3] = {0, 0, 0};
+  // [0]: FP32 kernels, [1]: FP64 kernels (a BW_MIXED cell runs both: the PCG in
+  // FP32, the Rayleigh-Ritz refinement in FP64)
+  int tune_reg[2][3] = {{1, 1, 1}, {1, 1, 1}};
+  int tune_cap[2][3] = {{0, 0, 0}, {0, 0, 0}};
   int tune_plane = 1;   // FP32 cells with n0 = n1 = 64: the fused plane pass
   int tune_slab = 1;    // FP32 cells with n1 = n2 = 128: the three-pass slab path
   // cell groups (several cells of one grid in one batch; bw_lowest_modes_batched):

@@ -26,6 +26,9 @@ namespace bw {
 
 template <typename T> struct C21v { T c[21]; };
 
+// index of a precision's FFT schedule in a cell (0: FP32 kernels, 1: FP64)
+template <typename T> constexpr int tsel = sizeof(T) == 8 ? 1 : 0;
+
 // the reference stiffness C0 of vector v's cell (the kernel's own C0 for one cell)
 template <typename T> __device__ __forceinline__ C21v<T> cell_c0(const CellSel& cs, int v, const C21v<T>& C0) {
   const T* tab;
@@ -849,7 +852,7 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
   const Geom& g = r->g;
   constexpr int NC = OP == 0 ? 6 : 3;
   const long n12 = (long)g.n1 * g.n2;
-  const bool reg1 = r->tune_reg[1] && reg_len(g.n1) && g.n2 % reg_lines(g.n1) == 0;
+  const bool reg1 = r->tune_reg[tsel<T>][1] && reg_len(g.n1) && g.n2 % reg_lines(g.n1) == 0;
   auto axis1 = [&](auto INVc) {
     constexpr bool INV = decltype(INVc)::value;
     const char* name = active ? (INV ? "k_axis1_inv_pcg" : "k_axis1_fwd_pcg")
@@ -870,7 +873,7 @@ void launch_middle(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* ac
       return;
     }
     with_n(g.n1, [&](auto N1) {
-      ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2, r->tune_cap[1]);
+      ColTile ct = axis1_tile<T>(N1, g.n2, (long)NC * g.n0 * g.n2, r->tune_cap[tsel<T>][1]);
       if (active)
         BW_LAUNCH(name, units, (k_axis1<T, decltype(N1)::value, INV, 1>), dim3(nvec * ct.tpv), dim3(NT), 0, s, W,
                   g.n2, (long)NC * g.nvox, ct, twiddles<T>(r, 1), active);
@@ -894,7 +897,7 @@ void launch_axis0(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* act
   const T* tab = tab_override ? tab_override : (OP == 0 ? ctab<T>(r) : rhotab<T>(r));
   const char* name0 = active ? "k_axis0_contract_pcg" : (OP == 0 ? "k_axis0_contract" : "k_axis0_mass");
   const long units0 = active ? 0 : nvec;
-  if (r->tune_reg[0] && reg_len(g.n0) && n12 % reg_lines(g.n0) == 0 && (long)NC * g.nvox < (1L << 31)) {
+  if (r->tune_reg[tsel<T>][0] && reg_len(g.n0) && n12 % reg_lines(g.n0) == 0 && (long)NC * g.nvox < (1L << 31)) {
     with_reg(g.n0, [&](auto N0) {
       constexpr int n0c = decltype(N0)::value;
       const int tpv = (int)(n12 / reg_lines(n0c));
@@ -907,7 +910,7 @@ void launch_axis0(const bw_rve* r, cplx<T>* W, int nvec, T scale, const int* act
     });
   } else {
     with_n(g.n0, [&](auto N0) {
-      ColTile ct = axis0_tile<T>(N0, n12, r->tune_cap[0]);
+      ColTile ct = axis0_tile<T>(N0, n12, r->tune_cap[tsel<T>][0]);
       if (active)
         BW_LAUNCH(name0, units0, (k_axis0_op<T, decltype(N0)::value, OP, 1>), dim3(nvec * ct.tpv), dim3(NT), 0, s,
                   W, n12, g.nvox, ct, r->d_gmap, tab, scale, twiddles<T>(r, 0), active, r->csel);
@@ -956,7 +959,7 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
       return;
     }
   }
-  const bool reg2 = r->tune_reg[2] && reg_len(g.n2) && ((long)g.n0 * g.n1) % reg_lines(g.n2) == 0;
+  const bool reg2 = r->tune_reg[tsel<T>][2] && reg_len(g.n2) && ((long)g.n0 * g.n1) % reg_lines(g.n2) == 0;
   const int tpvr = reg2 ? (int)(((long)g.n0 * g.n1) / reg_lines(g.n2)) : 0;
   // fused plane pass (FP32, n0 = n1 = 64): strain and stress in the transposed work layout
   const bool plane = std::is_same<T, float>::value && reg2 && r->tune_plane && r->d_gmapT && g.n0 == 64 &&
@@ -983,7 +986,7 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   } else {
     with_n(g.n2, [&](auto N2) {
       constexpr int n2c = decltype(N2)::value;
-      RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1, r->tune_cap[2]);
+      RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1, r->tune_cap[tsel<T>][2]);
       if (mode == 0)
         BW_LAUNCH("k_strain_row", nvec, (k_strain_row<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u,
                   (cplx<T>*)nullptr, W, d_qtab, g.n0, g.n1, g.nvox, rt, twiddles<T>(r, 2), active,
@@ -1048,7 +1051,7 @@ void apply_K_impl(const bw_rve* r, const double* d_qtab, const cplx<T>* u, cplx<
   } else {
     with_n(g.n2, [&](auto N2) {
       constexpr int n2c = decltype(N2)::value;
-      RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1, r->tune_cap[2]);
+      RowTile rt = row_tile<T>(n2c, (long)g.n0 * g.n1, r->tune_cap[tsel<T>][2]);
       nblk = rt.tpv;
       if (mode == 0)
         BW_LAUNCH("k_row_div", nvec, (k_row_div<T, n2c, 0>), dim3(nvec * rt.tpv), dim3(NT), 0, s, W, y, d_qtab,
@@ -1080,7 +1083,7 @@ void apply_M_impl(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, doubl
   const long rows = 3L * g.n0 * g.n1;
   with_n(g.n2, [&](auto N2) {
     constexpr int n2c = decltype(N2)::value;
-    RowTile rt = row_tile<T>(n2c, rows, r->tune_cap[2]);
+    RowTile rt = row_tile<T>(n2c, rows, r->tune_cap[tsel<T>][2]);
     BW_LAUNCH("k_row_inv_mass", nvec, (k_row_plain<T, n2c, true>), dim3(nvec * rt.tpv), dim3(NT), 0, s, u, W, rt,
               (int)rows,
                        twiddles<T>(r, 2), (const int*)nullptr);
@@ -1088,7 +1091,7 @@ void apply_M_impl(const bw_rve* r, const cplx<T>* u, cplx<T>* y, int nvec, doubl
   launch_middle<T, 1>(r, W, nvec, (T)(scale / (double)g.nvox), nullptr, s, tab);
   with_n(g.n2, [&](auto N2) {
     constexpr int n2c = decltype(N2)::value;
-    RowTile rt = row_tile<T>(n2c, rows, r->tune_cap[2]);
+    RowTile rt = row_tile<T>(n2c, rows, r->tune_cap[tsel<T>][2]);
     BW_LAUNCH("k_row_fwd_mass", nvec, (k_row_plain<T, n2c, false>), dim3(nvec * rt.tpv), dim3(NT), 0, s,
               (const cplx<T>*)W, y, rt,
                        (int)rows, twiddles<T>(r, 2), (const int*)nullptr);
