@@ -255,30 +255,32 @@ static void rr64_bounds(bw_rve* r, const double* dq, cplx<double>*& U, int q, in
   lam.resize(q);
   // residuals of the wanted pairs and of the next one (its gap enters the bound)
   const int nr = n_want > 0 ? std::min(q, n_want + 1) : 0;
+  // M' = I (one density): M U is U and M^-1 R is R, no copies
+  const bool unit = r->rho_unit != 0;
   if (do_rr) {
     cplx<double>* U2 = w.vec(4, (size_t)q * n3);
     cplx<double>* KU0 = w.vec(5, (size_t)q * n3);
-    cplx<double>* MU0 = w.vec(6, (size_t)q * n3);
+    cplx<double>* MU0 = unit ? U : w.vec(6, (size_t)q * n3);
     cplx<double>* KU1 = w.vec(7, (size_t)q * n3);
-    cplx<double>* MU1 = w.vec(8, (size_t)q * n3);
+    cplx<double>* MU1 = unit ? U2 : w.vec(8, (size_t)q * n3);
     apply_K_blk<double>(r, dq, U, KU0, q, cnt, s);
-    apply_M_blk<double>(r, U, MU0, q, false, cnt, s);
+    if (!unit) apply_M_blk<double>(r, U, MU0, q, false, cnt, s);
     launch_gram<double>(U, q, KU0, q, n3, n3, sm.Kq, r->ws_red, r->d_ctr, s);
     launch_gram<double>(U, q, MU0, q, n3, n3, sm.Mq, r->ws_red, r->d_ctr, s);
     launch_small_geig(sm.Kq, sm.Mq, q, sm.lam, sm.Q, sm.info, s);
     launch_ritz<double>(U, q, sm.Q, q, U2, q, n3, n3, s);
     launch_ritz<double>(KU0, q, sm.Q, q, KU1, nr, n3, n3, s);
-    launch_ritz<double>(MU0, q, sm.Q, q, MU1, nr, n3, n3, s);
+    if (!unit) launch_ritz<double>(MU0, q, sm.Q, q, MU1, nr, n3, n3, s);
     std::swap(w.v[3], w.v[4]);
     U = (cplx<double>*)w.v[3].p;
     KU = KU1;
-    MU = MU1;
+    MU = unit ? U : MU1;
   } else {
     h2d(sm.lam, lam.data(), q * sizeof(double), s);
   }
   launch_lincomb<double>(KU, MU, sm.lam, R, nr, n3, n3, s);
-  apply_M_blk<double>(r, R, Z, nr, true, cnt, s);
-  launch_dots<double>(R, Z, nr, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
+  if (!unit) apply_M_blk<double>(r, R, Z, nr, true, cnt, s);
+  launch_dots<double>(R, unit ? R : Z, nr, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
   std::vector<double2> rn(nr);
   int info = 0;
   if (do_rr) {
