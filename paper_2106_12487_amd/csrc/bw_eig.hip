@@ -902,9 +902,17 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       h2d(cfd, cf.data(), (size_t)nk * ldc * sizeof(double2), s);
       launch_mlincomb2<T>(V + (size_t)j * n3, xk, X, n3, V, xk, n3, j, cfd, ldc, nk, n3, actd, s);
       if (!unit) launch_mlincomb2<T>(MV + (size_t)j * n3, xk, nullptr, 0, MV, xk, n3, j, cfd, ldc, nk, n3, actd, s);
-      apply_M_blk<T>(r, X, MF, nk, false, cnt, s);
-      deflate_batch(X, MF, act);
-      launch_dots<T>(X, MF, nk, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
+      if (unit) {
+        // M' = I: M X is X, and the M-orthogonal projection off the rigid
+        // translations (plane waves at xi + k = 0) zeroes that voxel
+        for (int k = 0; k < nk; ++k)
+          if (act[k] && qt.null_index[k] >= 0) zero_voxel<T>(X + (size_t)k * n3, 1, g.nvox, qt.null_index[k], s);
+        launch_dots<T>(X, X, nk, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
+      } else {
+        apply_M_blk<T>(r, X, MF, nk, false, cnt, s);
+        deflate_batch(X, MF, act);
+        launch_dots<T>(X, MF, nk, n3, n3, sm.dots, r->ws_red, r->d_ctr + 64, s);
+      }
       BW_HIP(hipMemcpyAsync(bb.data(), sm.dots, nk * sizeof(double2), hipMemcpyDeviceToHost, s));
       BW_HIP(hipStreamSynchronize(s));
       for (int k = 0; k < nk; ++k) {
