@@ -747,10 +747,14 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
   // with M' = I the basis is its own M-image: no second basis to store or restart
   const bool unit = r->rho_unit != 0;
   cplx<T>* MV = unit ? V : w.vec(1, (size_t)nk * xk);
+  // a restart writes the kept Ritz vectors of every restarting wave vector into a
+  // second basis, and the two bases swap roles (no copy back)
+  cplx<T>* V2 = w.vec(12, (size_t)nk * xk);
+  cplx<T>* MV2 = unit ? V2 : w.vec(13, (size_t)nk * xk);
   cplx<T>* B = w.vec(2, (size_t)nk * n3);
   cplx<T>* X = w.vec(3, (size_t)nk * n3);
   cplx<T>* MF = w.vec(4, (size_t)nk * n3);
-  cplx<T>* TMP = w.vec(5, (size_t)std::max(kk, qsel) * n3);
+  cplx<T>* TMP = w.vec(5, (size_t)qsel * n3);
   cplx<T>* MN = w.vec(6, (size_t)3 * n3);
   cplx<T>* N3 = w.vec(7, (size_t)3 * n3);
   const size_t hcount = (size_t)nk * (m + 1);
@@ -1025,15 +1029,15 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
         for (int c = 0; c < kk; ++c) Qk[(size_t)p * kk + c] = Sm[(size_t)p * m + (m - 1 - c)];
       h2d(sm.Q, Qk.data(), Qk.size() * sizeof(double2), s);
       cplx<T>* Vk = V + (size_t)k * xk;
-      cplx<T>* MVk = MV + (size_t)k * xk;
-      launch_ritz<T>(Vk, m, sm.Q, kk, TMP, kk, n3, n3, s);
-      BW_HIP(hipMemcpyAsync(Vk, TMP, (size_t)kk * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
-      BW_HIP(hipMemcpyAsync(Vk + (size_t)kk * n3, Vk + (size_t)m * n3, n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice,
-                            s));
+      cplx<T>* V2k = V2 + (size_t)k * xk;
+      launch_ritz<T>(Vk, m, sm.Q, kk, V2k, kk, n3, n3, s);
+      BW_HIP(hipMemcpyAsync(V2k + (size_t)kk * n3, Vk + (size_t)m * n3, n3 * sizeof(cplx<T>),
+                            hipMemcpyDeviceToDevice, s));
       if (!unit) {
-        launch_ritz<T>(MVk, m, sm.Q, kk, TMP, kk, n3, n3, s);
-        BW_HIP(hipMemcpyAsync(MVk, TMP, (size_t)kk * n3 * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
-        BW_HIP(hipMemcpyAsync(MVk + (size_t)kk * n3, MVk + (size_t)m * n3, n3 * sizeof(cplx<T>),
+        cplx<T>* MVk = MV + (size_t)k * xk;
+        cplx<T>* MV2k = MV2 + (size_t)k * xk;
+        launch_ritz<T>(MVk, m, sm.Q, kk, MV2k, kk, n3, n3, s);
+        BW_HIP(hipMemcpyAsync(MV2k + (size_t)kk * n3, MVk + (size_t)m * n3, n3 * sizeof(cplx<T>),
                               hipMemcpyDeviceToDevice, s));
       }
       std::fill(H[k].begin(), H[k].end(), 0.0);
@@ -1048,6 +1052,10 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       }
       BW_HIP(hipStreamSynchronize(s));
     }
+    // the restarted wave vectors' bases are now in V2 (a finished one's basis is
+    // no longer read)
+    std::swap(V, V2);
+    std::swap(MV, MV2);
     j0 = kk;
   }
   return status;
@@ -1145,11 +1153,14 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
     auto t0 = std::chrono::steady_clock::now();
     int st = BW_OK;
     if (o.method == BW_LANCZOS) {
-      // wave vectors per batch: the bases (2 (ncv + 1) vectors each) within ~48 GB
+      // wave vectors per batch: the bases within ~48 GB
       const int nwm = nmodes;
       const int m = o.ncv > 0 ? o.ncv : std::max(2 * nwm + 1, 20);
       const double vbytes = (double)r->g.nvox * 3 * (r->precision == BW_FP64 ? 16 : 8);
-      int kb = (int)std::max(1.0, std::floor(48e9 / (vbytes * (2.0 * (m + 1) + 3))));
+      // two bases per wave vector (restarts alternate between them), twice that
+      // with their M-images when the density is not uniform
+      const double nbases = r->rho_unit ? 2.0 : 4.0;
+      int kb = (int)std::max(1.0, std::floor(48e9 / (vbytes * (nbases * (m + 1) + 3))));
       kb = std::min({kb, nk, 64});
       if (o.kbatch > 0) kb = std::min(kb, o.kbatch);
       for (int k0 = 0; k0 < nk; k0 += kb) {
