@@ -645,24 +645,46 @@ __global__ __launch_bounds__(NT) void k_pcg_update(cplx<T>* __restrict__ x, cplx
   const double* q = qtab + (size_t)v * (vi.n0 + vi.n1 + vi.n2);
   const C21v<T> C0c = cell_c0<T>(csel, v, C0);
   double rz = 0, rr = 0;
-  for (long vox = (long)b * NT + threadIdx.x; vox < nvox; vox += (long)bpv * NT) {
-    int i0, i1, i2;
-    vi.split(vox, i0, i1, i2);
-    V rv[3], z[3];
+  // two voxels of the thread's sequence per pass, all 24 loads issued before any
+  // store (the same voxel order as one at a time, so the same sums)
+  const long stride = (long)bpv * NT;
+  for (long vox = (long)b * NT + threadIdx.x; vox < nvox; vox += 2 * stride) {
+    const bool two = vox + stride < nvox;
+    V pv[2][3], xv[2][3], rv[2][3], av[2][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const size_t o = ((size_t)v * 3 + c) * nvox + vox;
-      const V pv = p[o];
-      x[o] = caxpy(x[o], al, pv);
-      rv[c] = caxpy(r[o], -al, Ap[o]);
-      r[o] = rv[c];
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !two) break;
+      const long vx = vox + u * stride;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const size_t o = ((size_t)v * 3 + c) * nvox + vx;
+        pv[u][c] = p[o];
+        xv[u][c] = x[o];
+        rv[u][c] = r[o];
+        av[u][c] = Ap[o];
+      }
     }
-    precond3<T, V>(C0c, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], rv, z);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      rz += (double)rv[c].x * z[c].x + (double)rv[c].y * z[c].y;
-      rr += (double)rv[c].x * rv[c].x + (double)rv[c].y * rv[c].y;
-      if (WZ) Ap[((size_t)v * 3 + c) * nvox + vox] = z[c];
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !two) break;
+      const long vx = vox + u * stride;
+      int i0, i1, i2;
+      vi.split(vx, i0, i1, i2);
+      V z[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const size_t o = ((size_t)v * 3 + c) * nvox + vx;
+        x[o] = caxpy(xv[u][c], al, pv[u][c]);
+        rv[u][c] = caxpy(rv[u][c], -al, av[u][c]);
+        r[o] = rv[u][c];
+      }
+      precond3<T, V>(C0c, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], rv[u], z);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        rz += (double)rv[u][c].x * z[c].x + (double)rv[u][c].y * z[c].y;
+        rr += (double)rv[u][c].x * rv[u][c].x + (double)rv[u][c].y * rv[u][c].y;
+        if (WZ) Ap[((size_t)v * 3 + c) * nvox + vx] = z[c];
+      }
     }
   }
   const double vals[2] = {rz, rr};
