@@ -122,6 +122,14 @@ typedef struct bw_eig_opts {
                           stiffness; at most 8 cells per group; not when modes
                           are requested or with BW_LEARNED); 1 -> every cell
                           runs on a stream of its own                          */
+  int32_t kgroups;     /* BW_LANCZOS with BW_PLAIN on a single cell: the wave
+                          vectors are split into this many contiguous groups
+                          (at most 8) solved concurrently, each on a stream and
+                          host thread of its own with workspaces of its own (the
+                          cell's tables are shared), so that one group's
+                          latency-bound transforms overlap another's memory-
+                          bound steps; a wave vector's results are those of one
+                          batch bit for bit.  0 or 1 -> one group            */
 } bw_eig_opts;
 
 /* Statistics of the last solver call (all optional outputs). */
@@ -278,10 +286,13 @@ int bw_graphs_enable(int32_t enable);
 /* Restricts the timing to the kernel of that name (NULL or "" = all kernels). */
 int bw_timing_filter(const char* kernel_name);
 
-/* Writes a JSON object {"kernel": {"launches": n, "ms": total, "units": u}}
- * into buf (len bytes, NUL-terminated, truncated if needed) after waiting for
- * the recorded events; `units` counts the vectors each kernel processed.
- * Returns the length the full report needs (including the NUL). */
+/* Writes a JSON object {"kernel": {"launches": n, "ms": total, "units": u,
+ * "union_ms": w}} into buf (len bytes, NUL-terminated, truncated if needed)
+ * after waiting for the recorded events; `units` counts the vectors each kernel
+ * processed, `ms` sums the launch durations and `union_ms` is the time during
+ * which at least one launch of the kernel ran (less than `ms` when launches on
+ * concurrent streams overlap).  Returns the length the full report needs
+ * (including the NUL). */
 int64_t bw_timing_report(char* buf, int64_t len);
 
 /* ------------------------------------------------------------------------

@@ -37,7 +37,8 @@ class bw_eig_opts(ctypes.Structure):
                 ("maxit_outer", ctypes.c_int32), ("maxit_lin", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("tol_eig", ctypes.c_double),
                 ("tol_lin", ctypes.c_double), ("tol_omega", ctypes.c_double), ("kbatch", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("net", ctypes.c_void_p), ("separate_cells", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("net", ctypes.c_void_p), ("separate_cells", ctypes.c_int32),
+                ("kgroups", ctypes.c_int32)]
 
 
 class bw_stats(ctypes.Structure):
@@ -272,16 +273,17 @@ def bw_pcg_solve(rve: Rve, k, b, x, rtol: float, maxit: int = 0, stream=None):
 def bw_lowest_modes(rve: Rve, k_list, nmodes: int, method: int = BW_SUBSPACE, block: int = 0, ncv: int = 0,
                     tol_eig: float = 0.0, tol_lin: float = 0.0, maxit_outer: int = 0, maxit_lin: int = 0,
                     warm_start: bool = True, modes=None, want_err: bool = True, tol_omega: float = 0.0,
-                    kbatch: int = 0, net=None, stream=None):
+                    kbatch: int = 0, net=None, kgroups: int = 0, stream=None):
     """omega (nk x nmodes, rad/s), error bounds, status and statistics.  net: a UNet for
-    the learned preconditioner of the Lanczos inner solves (BW_LEARNED), else plain."""
+    the learned preconditioner of the Lanczos inner solves (BW_LEARNED), else plain.
+    kgroups > 1: the wave vectors in that many concurrent groups (Lanczos)."""
     k_arr, k_p = _darr(np.asarray(k_list).reshape(-1, 3))
     nk = int(k_arr.shape[0])
     om = np.zeros((nk, nmodes))
     er = np.zeros((nk, nmodes))
     opts = bw_eig_opts(method, block, ncv, maxit_outer, maxit_lin, int(bool(warm_start)), tol_eig, tol_lin,
                        tol_omega, kbatch, BW_LEARNED if net is not None else BW_PLAIN,
-                       net.handle.value if net is not None else None)
+                       net.handle.value if net is not None else None, 0, int(kgroups))
     st = bw_stats()
     code = _check(lib().bw_lowest_modes(rve.handle, k_p, nk, int(nmodes), ctypes.byref(opts),
                                         om.ctypes.data_as(_DP), er.ctypes.data_as(_DP) if want_err else None,

@@ -27,6 +27,7 @@ struct Pending {
 struct Totals {
   long launches = 0, units = 0;
   double ms = 0;
+  std::vector<std::pair<float, float>> spans;   // launch intervals from g_ref (ms)
 };
 std::mutex g_tmu;
 std::atomic<bool> g_timing{false};
@@ -34,6 +35,26 @@ std::string g_filter;  // time only this kernel name when non-empty
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::map<std::string, Totals> g_tot;
+hipEvent_t g_ref = nullptr;   // recorded when timing is switched on
+
+// total time during which at least one launch of a kernel ran (launches of one
+// kernel on concurrent streams overlap; their summed durations would count the
+// shared time more than once)
+double union_ms(std::vector<std::pair<float, float>> v) {
+  std::sort(v.begin(), v.end());
+  double tot = 0, a = 0, b = -1;
+  for (auto& x : v) {
+    if (x.first > b) {
+      if (b > a) tot += b - a;
+      a = x.first;
+      b = x.second;
+    } else if (x.second > b) {
+      b = x.second;
+    }
+  }
+  if (b > a) tot += b - a;
+  return tot;
+}
 
 hipEvent_t pool_get() {
   if (!g_pool.empty()) {
@@ -53,6 +74,8 @@ void drain_locked() {
       t.launches += 1;
       t.ms += ms;
       t.units += p.units;
+      float a = 0;
+      if (g_ref && hipEventElapsedTime(&a, g_ref, p.e0) == hipSuccess) t.spans.push_back({a, a + ms});
     }
     if (p.e0) g_pool.push_back(p.e0);
     if (p.e1) g_pool.push_back(p.e1);
@@ -396,6 +419,10 @@ extern "C" int bw_timing_enable(int32_t enable) {
   std::lock_guard<std::mutex> lk(g_tmu);
   drain_locked();
   g_tot.clear();
+  if (enable) {
+    if (!g_ref && hipEventCreate(&g_ref) != hipSuccess) g_ref = nullptr;
+    if (g_ref) (void)hipEventRecord(g_ref, nullptr);
+  }
   g_timing.store(enable != 0);
   return BW_OK;
 }
@@ -445,8 +472,9 @@ extern "C" int64_t bw_timing_report(char* buf, int64_t len) {
   bool first = true;
   for (auto& kv : g_tot) {
     char tmp[256];
-    snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"units\": %ld}", first ? "" : ", ",
-             kv.first.c_str(), kv.second.launches, kv.second.ms, kv.second.units);
+    snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"units\": %ld, \"union_ms\": %.6f}",
+             first ? "" : ", ", kv.first.c_str(), kv.second.launches, kv.second.ms, kv.second.units,
+             kv.second.spans.size() == (size_t)kv.second.launches ? union_ms(kv.second.spans) : kv.second.ms);
     js += tmp;
     first = false;
   }
@@ -722,6 +750,63 @@ bw_rve* cell_group(bw_rve* const* cells, int nc) {
   return r;
 }
 
+bw_rve* cell_clone(bw_rve* r, int i) {
+  BW_REQUIRE(i >= 1 && r->ncell == 1 && !r->shared_tables, BW_EINVAL, "no clone of this handle");
+  if ((int)r->clones.size() < i) r->clones.resize(i, nullptr);
+  bw_rve*& c = r->clones[i - 1];
+  if (!c) {
+    auto* x = new bw_rve();
+    try {
+      x->shared_tables = true;
+      x->g = r->g;
+      for (int a = 0; a < 3; ++a) x->L[a] = r->L[a];
+      x->G = r->G;
+      x->precision = r->precision;
+      x->device = r->device;
+      x->ncu = r->ncu;
+      x->Cref = r->Cref;
+      x->ell = r->ell;
+      x->rho_bar = r->rho_bar;
+      x->rho_min_s = r->rho_min_s;
+      x->rho_unit = r->rho_unit;
+      for (int k = 0; k < 21; ++k) {
+        x->C0_si[k] = r->C0_si[k];
+        x->C0s[k] = r->C0s[k];
+      }
+      x->C21s_host = r->C21s_host;
+      x->rhos_host = r->rhos_host;
+      x->d_gmap = r->d_gmap;
+      x->d_gmapT = r->d_gmapT;
+      x->d_C64 = r->d_C64;
+      x->d_C32 = r->d_C32;
+      x->d_rho64 = r->d_rho64;
+      x->d_rho32 = r->d_rho32;
+      x->d_rhoinv64 = r->d_rhoinv64;
+      x->d_rhoinv32 = r->d_rhoinv32;
+      for (int a = 0; a < 3; ++a) {
+        x->d_tw64[a] = r->d_tw64[a];
+        x->d_tw32[a] = r->d_tw32[a];
+      }
+      BW_HIP(hipMalloc(&x->d_ctr, 1024 * sizeof(unsigned)));
+      BW_HIP(hipMemset(x->d_ctr, 0, 1024 * sizeof(unsigned)));
+      x->serial = next_serial();
+    } catch (...) {
+      bw_destroy_rve(x);
+      throw;
+    }
+    c = x;
+  }
+  // the parent's current FFT schedule
+  for (int t = 0; t < 2; ++t)
+    for (int a = 0; a < 3; ++a) {
+      c->tune_reg[t][a] = r->tune_reg[t][a];
+      c->tune_cap[t][a] = r->tune_cap[t][a];
+    }
+  c->tune_plane = r->tune_plane;
+  c->tune_slab = r->tune_slab;
+  return c;
+}
+
 }  // namespace bw
 
 extern "C" void bw_destroy_rve(bw_rve* r) {
@@ -729,22 +814,26 @@ extern "C" void bw_destroy_rve(bw_rve* r) {
   if (r->pcg_exec) (void)hipGraphExecDestroy(r->pcg_exec);
   if (r->pcg_graph) (void)hipGraphDestroy(r->pcg_graph);
   if (r->cap_stream) (void)hipStreamDestroy(r->cap_stream);
-  (void)hipFree(r->d_gmap);
-  (void)hipFree(r->d_gmapT);
-  (void)hipFree(r->d_C64);
-  (void)hipFree(r->d_C32);
-  (void)hipFree(r->d_rho64);
-  (void)hipFree(r->d_rho32);
-  (void)hipFree(r->d_rhoinv64);
-  (void)hipFree(r->d_rhoinv32);
-  (void)hipFree(r->d_ctr);
-  (void)hipFree(r->d_C0tab32);
-  (void)hipFree(r->d_C0tab64);
-  if (r->group) bw_destroy_rve(r->group);
-  for (int a = 0; a < 3; ++a) {
-    (void)hipFree(r->d_tw64[a]);
-    (void)hipFree(r->d_tw32[a]);
+  for (bw_rve* c : r->clones)
+    if (c) bw_destroy_rve(c);
+  if (!r->shared_tables) {   // a clone's tables belong to its parent
+    (void)hipFree(r->d_gmap);
+    (void)hipFree(r->d_gmapT);
+    (void)hipFree(r->d_C64);
+    (void)hipFree(r->d_C32);
+    (void)hipFree(r->d_rho64);
+    (void)hipFree(r->d_rho32);
+    (void)hipFree(r->d_rhoinv64);
+    (void)hipFree(r->d_rhoinv32);
+    (void)hipFree(r->d_C0tab32);
+    (void)hipFree(r->d_C0tab64);
+    for (int a = 0; a < 3; ++a) {
+      (void)hipFree(r->d_tw64[a]);
+      (void)hipFree(r->d_tw32[a]);
+    }
   }
+  (void)hipFree(r->d_ctr);
+  if (r->group) bw_destroy_rve(r->group);
   r->ws_q.release();
   r->ws_q2.release();
   r->ws_red.release();

@@ -33,6 +33,7 @@ struct EigOpts {
   int kbatch;
   int precond = BW_PLAIN;
   bw_unet* net = nullptr;
+  int kgroups = 1;
 };
 
 // Relative omega bound of Ritz pair p from the residual norms res[0 .. nres) of
@@ -1120,6 +1121,7 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
       o.kbatch = opts->kbatch;
       o.precond = opts->precond;
       o.net = const_cast<bw_unet*>(opts->net);
+      o.kgroups = opts->kgroups;
     } else {
       o.warm = 1;
     }
@@ -1163,12 +1165,74 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
       int kb = (int)std::max(1.0, std::floor(48e9 / (vbytes * (nbases * (m + 1) + 3))));
       kb = std::min({kb, nk, 64});
       if (o.kbatch > 0) kb = std::min(kb, o.kbatch);
-      for (int k0 = 0; k0 < nk; k0 += kb) {
-        const int nb = std::min(kb, nk - k0);
-        const int s1 = r->precision == BW_FP64
-                           ? lanczos_batch<double>(r, k_list + 3 * k0, nb, nmodes, o, omega, err, modes, k0, cnt, s)
-                           : lanczos_batch<float>(r, k_list + 3 * k0, nb, nmodes, o, omega, err, modes, k0, cnt, s);
-        if (s1 != BW_OK) st = s1;
+      // the wave vectors [ka, kz) on handle h and stream hs, in batches of kb
+      auto run_range = [&](bw_rve* h, int ka, int kz, Counters& c, hipStream_t hs) {
+        int stt = BW_OK;
+        for (int k0 = ka; k0 < kz; k0 += kb) {
+          const int nb = std::min(kb, kz - k0);
+          const int s1 = h->precision == BW_FP64
+                             ? lanczos_batch<double>(h, k_list + 3 * k0, nb, nmodes, o, omega, err, modes, k0, c, hs)
+                             : lanczos_batch<float>(h, k_list + 3 * k0, nb, nmodes, o, omega, err, modes, k0, c, hs);
+          if (s1 != BW_OK) stt = s1;
+        }
+        return stt;
+      };
+      const int ng = (r->ncell == 1 && !r->shared_tables && o.precond == BW_PLAIN)
+                         ? std::min({std::max(o.kgroups, 1), nk, 8})
+                         : 1;
+      if (ng <= 1) {
+        st = run_range(r, 0, nk, cnt, s);
+      } else {
+        // concurrent groups of contiguous wave vectors: one handle (the cell or a
+        // clone sharing its tables), stream and host thread each
+        std::vector<int> lo(ng + 1);
+        for (int gi = 0; gi <= ng; ++gi) lo[gi] = (int)((long)nk * gi / ng);
+        std::vector<bw_rve*> h(ng, r);
+        for (int gi = 1; gi < ng; ++gi) {
+          h[gi] = cell_clone(r, gi);
+          h[gi]->ws_red.get(16u << 20);
+          h[gi]->ws_red2.get(16u << 20);
+        }
+        BW_HIP(hipStreamSynchronize(s));
+        std::vector<hipStream_t> gs(ng, nullptr);
+        try {
+          for (int gi = 0; gi < ng; ++gi) BW_HIP(hipStreamCreateWithFlags(&gs[gi], hipStreamNonBlocking));
+        } catch (...) {
+          for (auto x : gs)
+            if (x) (void)hipStreamDestroy(x);
+          throw;
+        }
+        std::vector<Counters> gc(ng);
+        std::vector<int> code(ng, BW_OK);
+        std::vector<std::string> msg(ng);
+        std::vector<std::thread> th;
+        th.reserve(ng);
+        for (int gi = 0; gi < ng; ++gi)
+          th.emplace_back([&, gi]() {
+            try {
+              BW_HIP(hipSetDevice(r->device));
+              code[gi] = run_range(h[gi], lo[gi], lo[gi + 1], gc[gi], gs[gi]);
+              BW_HIP(hipStreamSynchronize(gs[gi]));
+            } catch (const Error& e) {
+              code[gi] = e.code;
+              msg[gi] = e.msg;
+            } catch (const std::exception& e) {
+              code[gi] = BW_EINVAL;
+              msg[gi] = std::string("internal: ") + e.what();
+            }
+          });
+        for (auto& t : th) t.join();
+        for (auto x : gs) (void)hipStreamDestroy(x);
+        for (int gi = 0; gi < ng; ++gi) {
+          cnt.pcg_iters += gc[gi].pcg_iters;
+          cnt.block_iters += gc[gi].block_iters;
+          cnt.outer += gc[gi].outer;
+          cnt.kap += gc[gi].kap;
+          cnt.map += gc[gi].map;
+          cnt.stalls += gc[gi].stalls;
+          if (code[gi] < 0) throw Error{code[gi], msg[gi]};
+          if (code[gi] != BW_OK) st = code[gi];
+        }
       }
     } else {
       st = r->precision == BW_FP64 ? lowest_modes_impl<double>(r, k_list, nk, nmodes, o, omega, err, modes, cnt, s)

@@ -218,6 +218,10 @@ struct bw_rve {
   uint64_t serial = 0;               // unique per handle (group cache key)
   bw_rve* group = nullptr;           // cached group of this cell with others
   std::vector<uint64_t> group_key;
+  // handles that share this cell's device tables but own their workspaces (the
+  // concurrent wave-vector groups of one call); shared_tables marks such a clone
+  std::vector<bw_rve*> clones;
+  bool shared_tables = false;
   // captured PCG chunk (replayed with hipGraphLaunch while its key matches)
   hipStream_t cap_stream = nullptr;
   hipGraph_t pcg_graph = nullptr;
@@ -230,6 +234,9 @@ namespace bw {
 // The group handle of nc >= 2 cells of one grid, cell edge and precision
 // (created on first use and cached in cells[0]; freed with it).
 bw_rve* cell_group(bw_rve* const* cells, int nc);
+// Clone i (>= 1) of a cell for a concurrent wave-vector group: the cell's tables,
+// scales and FFT schedule, workspaces of its own (created on first use, cached).
+bw_rve* cell_clone(bw_rve* r, int i);
 
 // q tables for a list of k (SI, rad/m); fills null_index.
 QTable make_qtable(const bw_rve* r, const double* k_host, int nk);
