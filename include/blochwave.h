@@ -115,13 +115,13 @@ typedef struct bw_eig_opts {
                           A right-hand side whose learned steps stall finishes
                           with P^ and the call returns BW_ESTALL (valid results) */
   const bw_unet* net;  /* the network for BW_LEARNED                              */
-  int32_t separate_cells; /* bw_lowest_modes_batched with BW_LANCZOS: 0 (default) ->
-                          cells of one grid, cell edge and precision form a group
-                          whose wave vectors share every batched launch (each
-                          vector with its own cell's grain map and reference
-                          stiffness; at most 8 cells per group; not when modes
-                          are requested or with BW_LEARNED); 1 -> every cell
-                          runs on a stream of its own                          */
+  int32_t group_cells; /* bw_lowest_modes_batched with BW_LANCZOS: 0 (default) ->
+                          every cell runs on a stream of its own; 1 -> cells of
+                          one grid, cell edge and precision form a group whose
+                          wave vectors share every batched launch (each vector
+                          with its own cell's grain map and reference stiffness;
+                          at most 8 cells per group; not when modes are
+                          requested or with BW_LEARNED)                        */
   int32_t kgroups;     /* BW_LANCZOS with BW_PLAIN on a single cell: the wave
                           vectors are split into this many contiguous groups
                           (at most 8) solved concurrently, each on a stream and

@@ -37,7 +37,7 @@ class bw_eig_opts(ctypes.Structure):
                 ("maxit_outer", ctypes.c_int32), ("maxit_lin", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("tol_eig", ctypes.c_double),
                 ("tol_lin", ctypes.c_double), ("tol_omega", ctypes.c_double), ("kbatch", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("net", ctypes.c_void_p), ("separate_cells", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("net", ctypes.c_void_p), ("group_cells", ctypes.c_int32),
                 ("kgroups", ctypes.c_int32)]
 
 
@@ -295,10 +295,10 @@ def bw_lowest_modes(rve: Rve, k_list, nmodes: int, method: int = BW_SUBSPACE, bl
 def bw_lowest_modes_batched(rves, k_lists, nmodes: int, method: int = BW_SUBSPACE, block: int = 0, ncv: int = 0,
                             tol_eig: float = 0.0, tol_lin: float = 0.0, maxit_outer: int = 0, maxit_lin: int = 0,
                             warm_start: bool = True, tol_omega: float = 0.0, kbatch: int = 0, modes=None,
-                            separate_cells: bool = False, stream=None):
+                            group_cells: bool = False, stream=None):
     """Several cells at once: lists of omega and error arrays, status, summed statistics.
-    With the Lanczos method, cells of one grid share every batched launch unless
-    separate_cells."""
+    Every cell on a stream of its own; with group_cells (Lanczos), cells of one grid
+    share every batched launch."""
     n = len(rves)
     ks = [np.ascontiguousarray(np.asarray(k).reshape(-1, 3), dtype=np.float64) for k in k_lists]
     oms = [np.zeros((k.shape[0], nmodes)) for k in ks]
@@ -310,7 +310,7 @@ def bw_lowest_modes_batched(rves, k_lists, nmodes: int, method: int = BW_SUBSPAC
     ep = (_DP * n)(*[e.ctypes.data_as(_DP) for e in ers])
     mp = (_P * n)(*[(_dptr(m) if m is not None else None) for m in modes]) if modes is not None else None
     opts = bw_eig_opts(method, block, ncv, maxit_outer, maxit_lin, int(bool(warm_start)), tol_eig, tol_lin,
-                       tol_omega, kbatch, BW_PLAIN, None, int(bool(separate_cells)))
+                       tol_omega, kbatch, BW_PLAIN, None, int(bool(group_cells)))
     st = bw_stats()
     code = _check(lib().bw_lowest_modes_batched(h, n, kp, nk, int(nmodes), ctypes.byref(opts), op, ep, mp,
                                                 ctypes.byref(st), _stream(stream)))

@@ -1264,12 +1264,12 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
   }
 }
 
-// Several cells at once.  Cells of one grid, cell edge and precision form a
-// group (Lanczos, no mode output): one handle whose batched launches carry the
-// wave vectors of all its cells, each vector with its own cell's grain map and
-// reference stiffness.  Every group, and every other cell, runs the driver above
-// on a stream of its own, from a host thread of its own, so that the kernels of
-// small cells overlap on the GPU.  A cell's results are those of a separate call
+// Several cells at once.  Every cell runs the driver above on a stream of its own,
+// from a host thread of its own, so that the kernels of small cells overlap on the
+// GPU.  With opts->group_cells (Lanczos, no mode output), cells of one grid, cell
+// edge and precision form a group instead: one handle whose batched launches carry
+// the wave vectors of all its cells, each vector with its own cell's grain map and
+// reference stiffness.  A cell's results are those of a separate call
 // up to the rounding of the group's common scales (the same kernels, the same
 // deterministic reductions; bit for bit for an ungrouped cell).
 extern "C" int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const double* const* k_lists,
@@ -1293,7 +1293,7 @@ extern "C" int bw_lowest_modes_batched(bw_rve* const* rves, int32_t nrve, const 
     // work already queued on the caller's stream precedes the batch
     BW_HIP(hipStreamSynchronize(cs));
     // units of work: groups of cells of one grid, cell edge and precision, and single cells
-    const bool may_group = opts && opts->method == BW_LANCZOS && !modes && !opts->separate_cells &&
+    const bool may_group = opts && opts->method == BW_LANCZOS && !modes && opts->group_cells &&
                            opts->precond != BW_LEARNED;
     auto same_kind = [](const bw_rve* a, const bw_rve* b) {
       return a->ncell == 1 && b->ncell == 1 && a->g.n0 == b->g.n0 && a->g.n1 == b->g.n1 && a->g.n2 == b->g.n2 &&

@@ -90,9 +90,9 @@ def test_equal_grid_cells_share_launches_against_stored_oracle(lib, prec):
     cells = [lib.Rve.from_inputs(r, prec) for r in rves]
     kw = dict(method=lib.BW_LANCZOS, tol_omega=5e-6 if prec == 1 else 1e-10, tol_lin=1e-6 if prec == 1 else 1e-10)
     klists = [ks, ks[1:3], ks]
-    oms, ers, code, st = lib.bw_lowest_modes_batched(cells, klists, nm, **kw)
+    oms, ers, code, st = lib.bw_lowest_modes_batched(cells, klists, nm, group_cells=True, **kw)
     assert code == 0, lib.bw_last_error()
-    oms_s, ers_s, code_s, st_s = lib.bw_lowest_modes_batched(cells, klists, nm, separate_cells=True, **kw)
+    oms_s, ers_s, code_s, st_s = lib.bw_lowest_modes_batched(cells, klists, nm, **kw)
     assert code_s == 0, lib.bw_last_error()
     scale = _omega_ref(rves[0])
     e = np.abs(oms[0] - np.array(g["omega"])) / np.maximum(np.array(g["omega"]), scale)
