@@ -4,9 +4,9 @@ Workload: the lowest 12 branches at the 60 wave vectors of the simple-cubic path
 Gamma-X-M-Gamma-R for a 128^3 periodic Voronoi polycrystal (512 grains,
 hexagonal Ti constants, c-axes spread N(0, 15 deg) about z, L = 1 mm), every
 result carrying an FP64 a-posteriori bound on its relative omega error of at
-most 5e-6 (metric: 1e-5).  One "step" solves one of five consecutive 12-point
-segments of the path, the segments in turn (20 steps = the whole path four
-times); the value is wave vectors solved per second over the timed steps.  The
+most 5e-6 (metric: 1e-5).  One "step" solves one of two consecutive 30-point
+halves of the path, the halves in turn (20 steps = the whole path ten times); the
+value is wave vectors solved per second over the timed steps.  The
 cell and the wave vectors are on the GPU / host before the timed region.
 
 Arms: "mixed" (FP32 FFTs / contraction / PCG vectors, FP64 reductions,
@@ -63,7 +63,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--segments", type=int, default=5,
+    ap.add_argument("--segments", type=int, default=SEGMENTS,
                     help="the 60-point path is solved in this many consecutive segments, one per step")
     ap.add_argument("--skip-fp64", action="store_true", help="do not run the plain FP64 arm")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -88,6 +88,7 @@ def _args():
 TOL_OMEGA = 5e-6   # a-posteriori bound target on the relative omega error (metric: 1e-5)
 TOL_LIN = 1e-3     # relative residual of the inner PCG solves (both arms of the dispersion benches)
 KGROUPS = 4        # concurrent wave-vector groups of the mixed batched Lanczos
+SEGMENTS = 2       # consecutive path segments, one solved per step
 
 
 def run_arm(bw, rve_in, segs, precision, steps, warmup, tol_lin, tol_eig, timing=False, method=1, kbatch=0,

@@ -143,9 +143,9 @@ def test_config4_lowest_modes_match_stored_oracle(lib, ti128):
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="stored 128^3 oracle values not written yet")
 def test_config4_bench_settings_match_stored_oracle(lib, ti128):
     """Both arms of the dispersion bench as it runs them (inner PCG solves to its
-    relative residual, block 16, the mixed arm batched, the FP64 arm one wave vector
-    at a time) against the stored oracle frequencies: every omega within 1e-5 and
-    within its own FP64 bound."""
+    relative residual, block 16, the mixed arm batched in its concurrent wave-vector
+    groups, the FP64 arm one wave vector at a time) against the stored oracle
+    frequencies: every omega within 1e-5 and within its own FP64 bound."""
     _torch()
     import bench
     g = json.load(open(GOLDEN))
@@ -156,11 +156,18 @@ def test_config4_bench_settings_match_stored_oracle(lib, ti128):
     for prec, kbatch in ((lib.BW_MIXED, 0), (lib.BW_FP64, 1)):
         print(f"\n[case] 128^3 Ti, bench settings, precision {prec}, tol_lin {bench.TOL_LIN}", flush=True)
         R = lib.Rve.from_inputs(ti128, prec)
-        lib.bw_autotune(R, len(ks) if kbatch == 0 else 1)
-        om, err, code, _ = lib.bw_lowest_modes(R, ks, nm, method=lib.BW_LANCZOS, block=16, tol_eig=1e-6,
-                                               tol_lin=bench.TOL_LIN, tol_omega=bench.TOL_OMEGA, kbatch=kbatch)
+        lib.bw_autotune(R, min(len(ks) // bench.SEGMENTS, 64) if kbatch == 0 else 1)
+        segs = bench.segments(ks, bench.SEGMENTS) if kbatch == 0 else [ks]
+        om, err = [], []
+        for seg in segs:
+            o, e, code, _ = lib.bw_lowest_modes(R, seg, nm, method=lib.BW_LANCZOS, block=16, tol_eig=1e-6,
+                                                tol_lin=bench.TOL_LIN, tol_omega=bench.TOL_OMEGA, kbatch=kbatch,
+                                                kgroups=bench.KGROUPS if kbatch == 0 else 1)
+            assert code == 0, lib.bw_last_error()
+            om.append(o)
+            err.append(e)
         R.close()
-        assert code == 0, lib.bw_last_error()
+        om, err = np.concatenate(om), np.concatenate(err)
         d = np.abs(om - ref) / np.maximum(ref, om_scale)
         print(f"[case] max rel err {d.max():.2e}, max bound {err.max():.2e}", flush=True)
         assert err.max() <= bench.TOL_OMEGA
