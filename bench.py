@@ -80,6 +80,8 @@ def _args():
                     help="concurrent wave-vector groups of the mixed arm's batched Lanczos (1: one batch)")
     ap.add_argument("--tol-lin", type=float, default=TOL_LIN,
                     help="relative residual of the inner PCG solves (both arms)")
+    ap.add_argument("--operator-only", action="store_true",
+                    help="only time bw_apply_K on the 128^3 Ti cell (8 vectors; for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with plain 1 GiB device copies (reference kernel for memory-counter runs)")
     return ap.parse_args()
@@ -571,6 +573,9 @@ def main():
     w4 = inputs.WORKLOADS[4]
     rve_in = inputs.workload_rve(4, 0)
     ks = inputs.workload_kpoints(4)
+    if a.operator_only:
+        print(json.dumps({"apply_K_mixed": operator_arm(bw, rve_in, nvec=8)}), flush=True)
+        return
     segs = segments(ks, a.segments)
     nvox = int(np.prod(rve_in.n))
     print(f"[bench] {w4['name']}: {len(ks)} wave vectors in {len(segs)} segments of {len(segs[0])}",

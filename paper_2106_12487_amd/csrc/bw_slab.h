@@ -23,8 +23,9 @@
 // LDS: line l owns slots [136 l, 136 l + 136) (a pitch of 8 mod 16 slots puts
 // neighbouring lines in opposite halves of the 32 banks).  The exchange puts
 // (k1, j) at slot 8 k1 + (j ^ (k1 >> 1)); the plane puts column k of row l at
-// slot k ^ (l & 7).  Every access pattern (exchange writes and reads, row
-// writes, column reads) then spreads each group of 16 lanes of an 8-byte access
+// slot k ^ (l & 7); lane j's twiddles start at slot 17 j of their own table.
+// Every access pattern (exchange writes and reads, row writes, column reads,
+// twiddle reads) then spreads each group of 16 lanes of an 8-byte access
 // over all 32 banks (and each group of 32 lanes over 64), and every address is
 // a per-thread base plus a constant.
 // Global accesses are a uniform base plus a 32-bit lane offset and a constant.
@@ -46,6 +47,7 @@ constexpr int SLAB_NT = 1024;
 constexpr int SLAB_N = 128;
 constexpr int SLAB_LP = 136;                // LDS slots per line region
 constexpr int SLAB_LDS = SLAB_N * SLAB_LP;
+constexpr int SLAB_TWP = 17;                // twiddle table pitch per lane (slots)
 
 // exp(2 pi i e / 16) for e < 16 (cosine and sine)
 __device__ __forceinline__ float2 w16(int e, bool inv) {
@@ -82,13 +84,14 @@ template <bool INV> __device__ __forceinline__ void dft16(float2 (&x)[16]) {
 
 // The 128-point transform of the line whose LDS region starts at `reg`, held by
 // its 8 lanes (lane j).  On entry x[m] = x_(j + 8 m); on exit x[p * 8 + k2] =
-// X_(2 j + p + 16 k2).  tw: the LDS table tw[j * 16 + k1] = exp(-2 pi i j k1 /
-// 128).  The exchange is wavefront-local (the line's lanes are 8 consecutive
+// X_(2 j + p + 16 k2).  tw: the LDS table tw[j * 17 + k1] = exp(-2 pi i j k1 /
+// 128) (a pitch of 17 slots: with 16, the 8 lanes of a line, reading the same
+// k1, would all hit one bank pair).  The exchange is wavefront-local (the line's lanes are 8 consecutive
 // lanes of one wavefront).
 template <bool INV>
 __device__ __forceinline__ void slab_fft128(float2 (&x)[16], float2* reg, int j, const float2* tw) {
   dft16<INV>(x);
-  const float2* twj = tw + j * 16;
+  const float2* twj = tw + j * SLAB_TWP;
 #pragma unroll
   for (int k1 = 1; k1 < 16; ++k1) x[k1] = INV ? cmulc(x[k1], twj[k1]) : cmul(x[k1], twj[k1]);
   xsync<true>();
@@ -152,7 +155,7 @@ __device__ __forceinline__ void slab_fft2d(float2 (&x)[16], float2* S, const flo
 // shifted wave numbers of axes 1 and 2 of vector v (visible after a barrier).
 __device__ __forceinline__ void slab_tables(float2* tw, float* q1, float* q2, const float2* __restrict__ twg,
                                             const double* __restrict__ q, int n0, int t) {
-  if (t < 128) tw[t] = twg[(t >> 4) * (t & 15)];
+  if (t < 128) tw[(t >> 4) * SLAB_TWP + (t & 15)] = twg[(t >> 4) * (t & 15)];
   else if (t < 256) q1[t - 128] = (float)q[n0 + t - 128];
   else if (t < 384) q2[t - 256] = (float)q[n0 + SLAB_N + t - 256];
 }
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(SLAB_NT, 1) void k_slab_strain(const float2* __rest
                                                            const int* __restrict__ active,
                                                            const double* __restrict__ beta) {
   __shared__ float2 S[SLAB_LDS];
-  __shared__ float2 tw[128];
+  __shared__ float2 tw[8 * SLAB_TWP];
   __shared__ float q1s[SLAB_N], q2s[SLAB_N];
   const int v = blockIdx.x / n0;
   const int i0 = blockIdx.x - v * n0;
@@ -275,7 +278,7 @@ __global__ __launch_bounds__(SLAB_NT, 1) void k_slab_div(const float2* __restric
                                                         const int* __restrict__ active,
                                                         const float2* __restrict__ Pp, PcgDev pd, float oscale) {
   __shared__ float2 S[SLAB_LDS];
-  __shared__ float2 tw[128];
+  __shared__ float2 tw[8 * SLAB_TWP];
   __shared__ float q1s[SLAB_N], q2s[SLAB_N];
   __shared__ double red[SLAB_NT / 64];
   const int v = blockIdx.x / n0;
