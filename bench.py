@@ -10,7 +10,7 @@ value is wave vectors solved per second over the timed steps.  The
 cell and the wave vectors are on the GPU / host before the timed region.
 
 Arms: "mixed" (FP32 FFTs / contraction / PCG vectors, FP64 reductions,
-Rayleigh-Ritz and eigen-residuals, the wave vectors of a segment batched in four
+Rayleigh-Ritz and eigen-residuals, the wave vectors of a segment batched in three
 concurrent groups; the reported value) and "fp64_plain_one_k" (the plain method in FP64, one wave vector
 and one PCG right-hand side at a time, the whole path once), on the same GPU.  Both
 arms solve the shift-invert systems to the same relative residual TOL_lin = 1e-3
@@ -89,7 +89,7 @@ def _args():
 
 TOL_OMEGA = 5e-6   # a-posteriori bound target on the relative omega error (metric: 1e-5)
 TOL_LIN = 1e-3     # relative residual of the inner PCG solves (both arms of the dispersion benches)
-KGROUPS = 4        # concurrent wave-vector groups of the mixed batched Lanczos
+KGROUPS = 3        # concurrent wave-vector groups of the mixed batched Lanczos
 SEGMENTS = 2       # consecutive path segments, one solved per step
 
 

@@ -123,8 +123,9 @@ typedef struct bw_eig_opts {
                           at most 8 cells per group; not when modes are
                           requested or with BW_LEARNED)                        */
   int32_t kgroups;     /* BW_LANCZOS with BW_PLAIN on a single cell: the wave
-                          vectors are split into this many contiguous groups
-                          (at most 8) solved concurrently, each on a stream and
+                          vectors are split into this many groups (at most 8;
+                          wave vector i in group i mod kgroups) solved
+                          concurrently, each on a stream and
                           host thread of its own with workspaces of its own (the
                           cell's tables are shared), so that one group's
                           latency-bound transforms overlap another's memory-

@@ -675,9 +675,12 @@ static void delayed_reorth_coefficients(double* H, int m, int j, const double2* 
 // the same subspace as implicit restarts with the unwanted Ritz values as
 // exact shifts).  Converged wave vectors leave the batch.
 // ---------------------------------------------------------------------------
+// Results of wave vector k of the batch go to output row kmap[k] (kmap null:
+// kofs + k).
 template <typename T>
 static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, const EigOpts& o, double* omega,
-                         double* err, void* modes, int kofs, Counters& cnt, hipStream_t s) {
+                         double* err, void* modes, int kofs, Counters& cnt, hipStream_t s,
+                         const int* kmap = nullptr) {
   const Geom& g = r->g;
   const long n3 = g.nvox * 3;
   Small sm = small_bufs(r);
@@ -970,7 +973,8 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
         if (res > tolk[k] * std::fabs(thv[c])) conv = false;
       }
       if (verbose())
-        fprintf(stderr, "[bw] lanczos k#%d cycle %d worst |beta s|/theta %.3e\n", kofs + k, cycles, worst);
+        fprintf(stderr, "[bw] lanczos k#%d cycle %d worst |beta s|/theta %.3e\n", kmap ? kmap[k] : kofs + k,
+                cycles, worst);
       const bool last = cycles >= o.maxit_outer;
       if (conv || last) {
         // Ritz vectors of the wanted (and two more) values, then FP64 Rayleigh-Ritz and bounds
@@ -995,7 +999,7 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
         refine64<T>(r, dqk, qk, qt.null_index[k], qsel, nw, lam64, bnd, bound_target, 3, cnt, s);
         select_batch();
         const double wb = nw > 0 ? *std::max_element(bnd.begin(), bnd.end()) : 0.0;
-        if (verbose()) fprintf(stderr, "[bw] lanczos k#%d FP64 bound %.3e\n", kofs + k, wb);
+        if (verbose()) fprintf(stderr, "[bw] lanczos k#%d FP64 bound %.3e\n", kmap ? kmap[k] : kofs + k, wb);
         const bool stalled = wb > 0.5 * best[k];  // the bound stopped improving (precision floor)
         best[k] = std::min(best[k], wb);
         if (wb <= bound_target || last || stalled) {
@@ -1005,7 +1009,7 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
           ko.jstar = qt.null_index[k];
           ko.lam.assign(lam64.begin(), lam64.begin() + nw);
           ko.bound = bnd;
-          const int ik = kofs + k;
+          const int ik = kmap ? kmap[k] : kofs + k;
           int off = 0;
           if (ko.jstar >= 0) {
             for (int i = 0; i < 3; ++i) {
@@ -1183,10 +1187,30 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
       if (ng <= 1) {
         st = run_range(r, 0, nk, cnt, s);
       } else {
-        // concurrent groups of contiguous wave vectors: one handle (the cell or a
-        // clone sharing its tables), stream and host thread each
-        std::vector<int> lo(ng + 1);
-        for (int gi = 0; gi <= ng; ++gi) lo[gi] = (int)((long)nk * gi / ng);
+        // concurrent groups: one handle (the cell or a clone sharing its tables),
+        // stream and host thread each.  Wave vector i goes to group i mod ng, so
+        // that every group gets a share of each stretch of the path (neighbouring
+        // wave vectors take similar numbers of restarts) and the groups end together.
+        std::vector<std::vector<int>> ids(ng);
+        std::vector<std::vector<double>> kls(ng);
+        for (int i = 0; i < nk; ++i) {
+          ids[i % ng].push_back(i);
+          kls[i % ng].insert(kls[i % ng].end(), k_list + 3 * i, k_list + 3 * i + 3);
+        }
+        auto run_list = [&](bw_rve* hh, int gi, Counters& c, hipStream_t hs) {
+          int stt = BW_OK;
+          const int n = (int)ids[gi].size();
+          for (int b0 = 0; b0 < n; b0 += kb) {
+            const int nb = std::min(kb, n - b0);
+            const double* kl = kls[gi].data() + 3 * b0;
+            const int* km = ids[gi].data() + b0;
+            const int s1 = hh->precision == BW_FP64
+                               ? lanczos_batch<double>(hh, kl, nb, nmodes, o, omega, err, modes, 0, c, hs, km)
+                               : lanczos_batch<float>(hh, kl, nb, nmodes, o, omega, err, modes, 0, c, hs, km);
+            if (s1 != BW_OK) stt = s1;
+          }
+          return stt;
+        };
         std::vector<bw_rve*> h(ng, r);
         for (int gi = 1; gi < ng; ++gi) {
           h[gi] = cell_clone(r, gi);
@@ -1211,7 +1235,7 @@ extern "C" int bw_lowest_modes(bw_rve* r, const double* k_list, int32_t nk, int3
           th.emplace_back([&, gi]() {
             try {
               BW_HIP(hipSetDevice(r->device));
-              code[gi] = run_range(h[gi], lo[gi], lo[gi + 1], gc[gi], gs[gi]);
+              code[gi] = run_list(h[gi], gi, gc[gi], gs[gi]);
               BW_HIP(hipStreamSynchronize(gs[gi]));
             } catch (const Error& e) {
               code[gi] = e.code;

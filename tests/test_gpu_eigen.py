@@ -254,20 +254,27 @@ def test_lanczos_batch_split_matches_one_batch(lib):
 def test_lanczos_concurrent_groups_match_one_batch(lib, prec):
     """Ten wave vectors of the 64^3 workload, Gamma included, once as one batch and once
     in three concurrent groups (`kgroups`: a stream, host thread and handle clone each,
-    sharing the cell's tables): frequencies, bounds and PCG totals bit for bit; then the
+    sharing the cell's tables; wave vector i in group i mod 3): frequencies, bounds,
+    mode shapes (each in its wave vector's row) and PCG totals bit for bit; then the
     group handles are reused by a second call (cached clones, a changed FFT schedule)."""
+    _torch()
+    import torch
     rve = inputs.workload_rve(2, 0)
     ks = inputs.workload_kpoints(2)[0:10]
     R = lib.Rve.from_inputs(rve, prec)
     kw = dict(method=lib.BW_LANCZOS, tol_omega=5e-6 if prec == 1 else 1e-9,
               tol_lin=1e-6 if prec == 1 else 1e-10)
-    w0, e0, c0, s0 = lib.bw_lowest_modes(R, ks, 12, **kw)
-    w1, e1, c1, s1 = lib.bw_lowest_modes(R, ks, 12, kgroups=3, **kw)
+    m0 = torch.zeros((len(ks), 12, 3) + tuple(rve.n), dtype=R.complex_dtype, device="cuda")
+    m1 = torch.zeros_like(m0)
+    w0, e0, c0, s0 = lib.bw_lowest_modes(R, ks, 12, modes=m0, **kw)
+    w1, e1, c1, s1 = lib.bw_lowest_modes(R, ks, 12, kgroups=3, modes=m1, **kw)
     print(f"\n[case] cu64 prec={prec} Lanczos 10 wave vectors, one batch vs 3 concurrent groups: pcg "
           f"{s0['pcg_iterations']} vs {s1['pcg_iterations']}, {s0['seconds']:.2f} vs {s1['seconds']:.2f} s", flush=True)
     assert c0 == 0 and c1 == 0, lib.bw_last_error()
     assert np.array_equal(w0, w1) and np.array_equal(e0, e1)
     assert s0["pcg_iterations"] == s1["pcg_iterations"]
+    assert bool(torch.equal(m0, m1))
+    del m0, m1
     lib.bw_fft_schedule(R, reg=[1, 1, 0], cap=[0, 0, 0])
     w2, e2, c2, _ = lib.bw_lowest_modes(R, ks[3:7], 12, kgroups=4, **kw)
     assert c2 == 0, lib.bw_last_error()
