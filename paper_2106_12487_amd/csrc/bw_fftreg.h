@@ -388,8 +388,10 @@ __global__ __launch_bounds__(NT) void k_axis1_r(cplx<T>* __restrict__ X, int n2,
 // inverse FFT (layout A -> B), stiffness contraction (OP 0) or density
 // scaling (OP 1) at the layout-B points, forward FFT back to layout A.
 // ---------------------------------------------------------------------------
+// FP32: at most 168 VGPRs, so that 3 wavefronts fit per SIMD (the 6 x 8 points
+// take 96; the loads and stores hold no 64-bit addresses).
 template <typename T, int N, int OP, int PCG = 0>
-__global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, long n12, long nvox, int tpv,
+__global__ __launch_bounds__(NT, sizeof(T) == 4 ? 3 : 2) void k_axis0_op_r(cplx<T>* __restrict__ X, long n12, long nvox, int tpv,
                                                       const uint16_t* __restrict__ gmap, const T* __restrict__ Ctab,
                                                       T scale, const cplx<T>* __restrict__ tw,
                                                       const int* __restrict__ active, CellSel csel) {
@@ -405,15 +407,19 @@ __global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, l
   const int pos = tile * F::LINES + line;
   V w[F::P - 1][8];
   load_twr<T, N>(w, tw, j);
-  // 32-bit offsets within the vector (NC * nvox < 2^31, checked by the host)
+  // 32-bit offsets within the vector (NC * nvox < 2^31, checked by the host):
+  // point (c, m) of this thread sits at lo + c cs + m T s12, a per-thread base
+  // plus a uniform offset, so no 64-bit address is held per load
   cplx<T>* Xv = X + (size_t)v * NC * nvox;
   const uint16_t* __restrict__ gmv = gmap + csel.goff(v);   // this vector's cell
-  const int s12 = (int)n12, cs = (int)nvox;
+  const int s12 = (int)n12;
+  const uint32_t cs = (uint32_t)nvox, ms = (uint32_t)(F::T * n12);
+  uint32_t lo = (uint32_t)pos + (uint32_t)j * (uint32_t)n12;
   V x[NC][8];
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int m = 0; m < 8; ++m) x[c][m] = Xv[c * cs + pos + F::posA(j, m) * s12];
+    for (int m = 0; m < 8; ++m) x[c][m] = Xv[lo + c * cs + m * ms];
   const ColSlotR<N> slot{line};
   int parity = 0;
 #pragma unroll
@@ -439,11 +445,14 @@ __global__ __launch_bounds__(NT, 2) void k_axis0_op_r(cplx<T>* __restrict__ X, l
     // keep the table loads of one point at a time in flight (register pressure)
     asm volatile("" ::: "memory");
   }
+  // the base again, opaque: the store addresses are formed anew, not kept in
+  // registers since the loads
+  asm volatile("" : "+v"(lo));
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     fft_dif<T, N, false>(x[c], lds[0], lds[1], parity, slot, j, w);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) Xv[c * cs + pos + F::posA(j, m) * s12] = x[c][m];
+    for (int m = 0; m < 8; ++m) Xv[lo + c * cs + m * ms] = x[c][m];
   }
 }
 
