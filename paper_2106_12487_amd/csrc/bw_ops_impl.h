@@ -645,45 +645,54 @@ __global__ __launch_bounds__(NT) void k_pcg_update(cplx<T>* __restrict__ x, cplx
   const double* q = qtab + (size_t)v * (vi.n0 + vi.n1 + vi.n2);
   const C21v<T> C0c = cell_c0<T>(csel, v, C0);
   double rz = 0, rr = 0;
+  // this vector's arrays from uniform bases; component c of voxel vx at the 32-bit
+  // offset c nvox + vx (3 nvox <= 3 2^30 < 2^32), so no 64-bit address is held
+  // per access
+  const size_t vb = (size_t)v * 3 * nvox;
+  V* __restrict__ xb = x + vb;
+  V* __restrict__ rb = r + vb;
+  const V* __restrict__ pb = p + vb;
+  V* __restrict__ ab = Ap + vb;
+  const uint32_t n = (uint32_t)nvox;
   // two voxels of the thread's sequence per pass, all 24 loads issued before any
   // store (the same voxel order as one at a time, so the same sums)
-  const long stride = (long)bpv * NT;
-  for (long vox = (long)b * NT + threadIdx.x; vox < nvox; vox += 2 * stride) {
-    const bool two = vox + stride < nvox;
+  const uint32_t stride = (uint32_t)bpv * NT;
+  for (uint32_t vox = (uint32_t)b * NT + threadIdx.x; vox < n; vox += 2 * stride) {
+    const bool two = vox + stride < n;
     V pv[2][3], xv[2][3], rv[2][3], av[2][3];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       if (u == 1 && !two) break;
-      const long vx = vox + u * stride;
+      const uint32_t vx = vox + u * stride;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const size_t o = ((size_t)v * 3 + c) * nvox + vx;
-        pv[u][c] = p[o];
-        xv[u][c] = x[o];
-        rv[u][c] = r[o];
-        av[u][c] = Ap[o];
+        const uint32_t o = c * n + vx;
+        pv[u][c] = pb[o];
+        xv[u][c] = xb[o];
+        rv[u][c] = rb[o];
+        av[u][c] = ab[o];
       }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       if (u == 1 && !two) break;
-      const long vx = vox + u * stride;
+      const uint32_t vx = vox + u * stride;
       int i0, i1, i2;
       vi.split(vx, i0, i1, i2);
       V z[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const size_t o = ((size_t)v * 3 + c) * nvox + vx;
-        x[o] = caxpy(xv[u][c], al, pv[u][c]);
+        const uint32_t o = c * n + vx;
+        xb[o] = caxpy(xv[u][c], al, pv[u][c]);
         rv[u][c] = caxpy(rv[u][c], -al, av[u][c]);
-        r[o] = rv[u][c];
+        rb[o] = rv[u][c];
       }
       precond3<T, V>(C0c, (T)q[i0], (T)q[vi.n0 + i1], (T)q[vi.n0 + vi.n1 + i2], rv[u], z);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         rz += (double)rv[u][c].x * z[c].x + (double)rv[u][c].y * z[c].y;
         rr += (double)rv[u][c].x * rv[u][c].x + (double)rv[u][c].y * rv[u][c].y;
-        if (WZ) Ap[((size_t)v * 3 + c) * nvox + vx] = z[c];
+        if (WZ) ab[c * n + vx] = z[c];
       }
     }
   }
