@@ -81,7 +81,7 @@ def _args():
     ap.add_argument("--tol-lin", type=float, default=TOL_LIN,
                     help="relative residual of the inner PCG solves (both arms)")
     ap.add_argument("--operator-only", action="store_true",
-                    help="only time bw_apply_K on the 128^3 Ti cell (8 vectors; for counter runs)")
+                    help="only time bw_apply_K on the 128^3 Ti cell (8 vectors) and the 64^3 Cu cell (32 vectors); for counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with plain 1 GiB device copies (reference kernel for memory-counter runs)")
     return ap.parse_args()
@@ -574,7 +574,8 @@ def main():
     rve_in = inputs.workload_rve(4, 0)
     ks = inputs.workload_kpoints(4)
     if a.operator_only:
-        print(json.dumps({"apply_K_mixed": operator_arm(bw, rve_in, nvec=8)}), flush=True)
+        print(json.dumps({"apply_K_mixed": [operator_arm(bw, rve_in, nvec=8),
+                                            operator_arm(bw, inputs.workload_rve(2, 0), nvec=32)]}), flush=True)
         return
     segs = segments(ks, a.segments)
     nvox = int(np.prod(rve_in.n))
