@@ -15,10 +15,11 @@ constexpr int GEIG_QMAX = 48;  // small eigenproblem limit
 template <typename T>
 void launch_gram(const cplx<T>* X, int qx, const cplx<T>* Y, int qy, long n, long vstride, double2* G,
                  DevBuf& scratch, unsigned* counter, hipStream_t s);
-// Y_j = sum_p X_p Q[p][j], j < qout (Q is q x q row-major, FP64)
+// Y_j = sum_p X_p Q[p][j], j < qout (Q is q x q row-major, FP64).  real_q: Q
+// is real (its imaginary parts are ignored), half the multiply-adds.
 template <typename T>
 void launch_ritz(const cplx<T>* X, int q, const double2* Q, int ldq, cplx<T>* Y, int qout, long n, long vstride,
-                 hipStream_t s);
+                 hipStream_t s, bool real_q = false);
 // out[p] = <X_p, Y_p> (complex, FP64) for p < nv
 template <typename T>
 void launch_dots(const cplx<T>* X, const cplx<T>* Y, int nv, long n, long vstride, double2* out, DevBuf& scratch,

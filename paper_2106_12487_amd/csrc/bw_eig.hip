@@ -963,6 +963,12 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       const int k = idx[b];
       std::copy(thall.begin() + (size_t)b * m, thall.begin() + (size_t)(b + 1) * m, thv.begin());
       std::copy(Sall.begin() + (size_t)b * m * m, Sall.begin() + (size_t)(b + 1) * m * m, Sm.begin());
+      // the projected matrix is real symmetric, so are its eigenvectors: the Ritz
+      // updates take real coefficients (complex ones if the solver left more than
+      // rounding in the imaginary parts)
+      double sm_im = 0;
+      for (const double2& e : Sm) sm_im = std::max(sm_im, std::fabs(e.y));
+      const bool rq = sm_im <= 1e-13;
       const int nw = nwk[k];
       bool conv = true;
       double worst = 0;
@@ -984,10 +990,10 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
         h2d(sm.Q, Qs.data(), Qs.size() * sizeof(double2), s);
         cplx<double>* U64 = ws<double>(r).vec(3, (size_t)qsel * n3);
         if (fp32) {
-          launch_ritz<T>(V + (size_t)k * xk, m, sm.Q, qsel, TMP, qsel, n3, n3, s);
+          launch_ritz<T>(V + (size_t)k * xk, m, sm.Q, qsel, TMP, qsel, n3, n3, s, rq);
           launch_convert<float, double>((const cplx<float>*)TMP, U64, (size_t)qsel * n3, s);
         } else {
-          launch_ritz<T>(V + (size_t)k * xk, m, sm.Q, qsel, (cplx<T>*)U64, qsel, n3, n3, s);
+          launch_ritz<T>(V + (size_t)k * xk, m, sm.Q, qsel, (cplx<T>*)U64, qsel, n3, n3, s, rq);
         }
         std::vector<double> k1((size_t)qsel * 3);
         for (int v = 0; v < qsel; ++v)
@@ -1035,13 +1041,13 @@ static int lanczos_batch(bw_rve* r, const double* k_list, int nk, int nmodes, co
       h2d(sm.Q, Qk.data(), Qk.size() * sizeof(double2), s);
       cplx<T>* Vk = V + (size_t)k * xk;
       cplx<T>* V2k = V2 + (size_t)k * xk;
-      launch_ritz<T>(Vk, m, sm.Q, kk, V2k, kk, n3, n3, s);
+      launch_ritz<T>(Vk, m, sm.Q, kk, V2k, kk, n3, n3, s, rq);
       BW_HIP(hipMemcpyAsync(V2k + (size_t)kk * n3, Vk + (size_t)m * n3, n3 * sizeof(cplx<T>),
                             hipMemcpyDeviceToDevice, s));
       if (!unit) {
         cplx<T>* MVk = MV + (size_t)k * xk;
         cplx<T>* MV2k = MV2 + (size_t)k * xk;
-        launch_ritz<T>(MVk, m, sm.Q, kk, MV2k, kk, n3, n3, s);
+        launch_ritz<T>(MVk, m, sm.Q, kk, MV2k, kk, n3, n3, s, rq);
         BW_HIP(hipMemcpyAsync(MV2k + (size_t)kk * n3, MVk + (size_t)m * n3, n3 * sizeof(cplx<T>),
                               hipMemcpyDeviceToDevice, s));
       }

@@ -125,8 +125,11 @@ void launch_gram(const cplx<T>* X, int qx, const cplx<T>* Y, int qy, long n, lon
 // ---------------------------------------------------------------------------
 // Y[:, j] = sum_p X[:, p] Q[p][j] (FP64 accumulation).  The coefficients are
 // the same for every lane, so they are read with scalar loads; QO bounds qout
-// at compile time (fewer accumulators, higher occupancy).
-template <typename T, int QO>
+// at compile time (fewer accumulators, higher occupancy).  RQ: real
+// coefficients (the eigenvectors of the real symmetric Lanczos matrices), two
+// multiply-adds per term instead of four: the update is then bound by memory,
+// not by FP64 issue.
+template <typename T, int QO, bool RQ = false>
 __global__ __launch_bounds__(256) void k_ritz(const cplx<T>* __restrict__ X, int q, const double2* __restrict__ Q,
                                               int ldq, cplx<T>* __restrict__ Y, int qout, long n, long vstride) {
   for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
@@ -141,10 +144,17 @@ __global__ __launch_bounds__(256) void k_ritz(const cplx<T>* __restrict__ X, int
       for (int j = 0; j < QO; ++j) {
         // columns past qout take coefficient 0 (a uniform select, not a branch,
         // so the coefficients stay scalar loads in batches)
-        double2 c = Qp[j < qout ? j : qout - 1];
-        if (j >= qout) c = make_double2(0.0, 0.0);
-        acc[j].x += x.x * c.x - x.y * c.y;
-        acc[j].y += x.x * c.y + x.y * c.x;
+        if (RQ) {
+          double c = Qp[j < qout ? j : qout - 1].x;
+          if (j >= qout) c = 0.0;
+          acc[j].x += x.x * c;
+          acc[j].y += x.y * c;
+        } else {
+          double2 c = Qp[j < qout ? j : qout - 1];
+          if (j >= qout) c = make_double2(0.0, 0.0);
+          acc[j].x += x.x * c.x - x.y * c.y;
+          acc[j].y += x.x * c.y + x.y * c.x;
+        }
       }
     }
 #pragma unroll
@@ -155,10 +165,25 @@ __global__ __launch_bounds__(256) void k_ritz(const cplx<T>* __restrict__ X, int
 
 template <typename T>
 void launch_ritz(const cplx<T>* X, int q, const double2* Q, int ldq, cplx<T>* Y, int qout, long n, long vstride,
-                 hipStream_t s) {
+                 hipStream_t s, bool real_q) {
   BW_REQUIRE(q <= GEIG_QMAX && qout <= GRAM_QMAX, BW_EINVAL, "Ritz block too large");
   long nb = (n + 255) / 256;
   if (nb > 2048) nb = 2048;
+  if (real_q) {
+    // the Lanczos sizes (14 refined, 18 kept for 12 wanted modes) get buckets of
+    // their own: no multiply-adds on padding columns
+    auto go = [&](auto qo) {
+      constexpr int QO = decltype(qo)::value;
+      BW_LAUNCH("k_ritz", (long)q * qout, (k_ritz<T, QO, true>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq,
+                Y, qout, n, vstride);
+    };
+    if (qout <= 8) go(std::integral_constant<int, 8>{});
+    else if (qout <= 14) go(std::integral_constant<int, 14>{});
+    else if (qout <= 18) go(std::integral_constant<int, 18>{});
+    else if (qout <= 24) go(std::integral_constant<int, 24>{});
+    else go(std::integral_constant<int, GRAM_QMAX>{});
+    return;
+  }
   if (qout <= 8)
     BW_LAUNCH("k_ritz", (long)q * qout, (k_ritz<T, 8>), dim3((unsigned)nb), dim3(256), 0, s, X, q, Q, ldq, Y, qout, n,
               vstride);
@@ -803,7 +828,8 @@ void launch_add_hash(cplx<T>* X, long n, long vstride, int nv, unsigned long lon
 #define BW_INST_BLOCK(T)                                                                                          \
   template void launch_gram<T>(const cplx<T>*, int, const cplx<T>*, int, long, long, double2*, DevBuf&,            \
                                unsigned*, hipStream_t);                                                                      \
-  template void launch_ritz<T>(const cplx<T>*, int, const double2*, int, cplx<T>*, int, long, long, hipStream_t); \
+  template void launch_ritz<T>(const cplx<T>*, int, const double2*, int, cplx<T>*, int, long, long, hipStream_t,   \
+                               bool);                                                                              \
   template void launch_dots<T>(const cplx<T>*, const cplx<T>*, int, long, long, double2*, DevBuf&, unsigned*,     \
                                hipStream_t);                                                                      \
   template void launch_lincomb<T>(const cplx<T>*, const cplx<T>*, const double*, cplx<T>*, int, long, long,       \
