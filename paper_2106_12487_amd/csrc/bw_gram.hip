@@ -625,7 +625,8 @@ static long active_units(const int* act, int nk, int J, hipStream_t s) {
 // Products of each basis vector with two right-hand vectors at once (the
 // delayed re-orthogonalization of the Lanczos process): out0[k, i] = <X_k[i],
 // Y0_k>, out1[k, i] = <X_k[i], Y1_k>, reading every basis vector once.
-template <typename T>
+// I: the index type of the element offsets (32-bit when 8 xi + n < 2^32).
+template <typename T, typename I>
 __global__ __launch_bounds__(NT) void k_mdot8x2(const cplx<T>* __restrict__ X, long xk, long xi, int J,
                                                 const cplx<T>* __restrict__ Y0, long yk0,
                                                 const cplx<T>* __restrict__ Y1, long yk1, long n, const int* act,
@@ -641,16 +642,35 @@ __global__ __launch_bounds__(NT) void k_mdot8x2(const cplx<T>* __restrict__ X, l
   double a0r[8], a0i[8], a1r[8], a1i[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) a0r[i] = a0i[i] = a1r[i] = a1i[i] = 0.0;
-  for (long e = (long)b * NT + threadIdx.x; e < n; e += (long)bpv * NT) {
-    const double2 c0 = to_d2(y0[e]), c1 = to_d2(y1[e]);
+  // two elements of the thread's sequence per pass, all their loads issued
+  // first; the terms are added in the same element order as one at a time
+  const I st = (I)bpv * NT, xs = (I)xi;
+  for (I e = (I)b * NT + threadIdx.x; e < (I)n; e += 2 * st) {
+    const bool two = e + st < (I)n;
+    cplx<T> r0[2], r1[2], av[2][8];     // held as loaded, widened at use
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if (i < ni) {
-        const double2 a = to_d2(x[(size_t)i * xi + e]);
-        a0r[i] += a.x * c0.x + a.y * c0.y;
-        a0i[i] += a.x * c0.y - a.y * c0.x;
-        a1r[i] += a.x * c1.x + a.y * c1.y;
-        a1i[i] += a.x * c1.y - a.y * c1.x;
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !two) break;
+      const I eu = e + u * st;
+      r0[u] = y0[eu];
+      r1[u] = y1[eu];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i < ni) av[u][i] = x[(I)i * xs + eu];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !two) break;
+      const double2 c0 = to_d2(r0[u]), c1 = to_d2(r1[u]);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        if (i < ni) {
+          const double2 a = to_d2(av[u][i]);
+          a0r[i] += a.x * c0.x + a.y * c0.y;
+          a0i[i] += a.x * c0.y - a.y * c0.x;
+          a1r[i] += a.x * c1.x + a.y * c1.y;
+          a1i[i] += a.x * c1.y - a.y * c1.x;
+        }
       }
     }
   }
@@ -696,8 +716,12 @@ void launch_mdot2(const cplx<T>* X, long xk, long xi, int J, const cplx<T>* Y0, 
   int bpv = pw_blocks(n);
   if (bpv > 256) bpv = 256;
   double* partial = (double*)scratch.get((size_t)nk * J * bpv * 4 * sizeof(double));
-  BW_LAUNCH("k_mdot2", active_units(act, nk, J, s), (k_mdot8x2<T>), dim3(bpv, (J + 7) / 8, nk), dim3(NT), 0, s, X,
-            xk, xi, J, Y0, yk0, Y1, yk1, n, act, partial, bpv);
+  if (8.0 * xi + n < 4294967296.0)
+    BW_LAUNCH("k_mdot2", active_units(act, nk, J, s), (k_mdot8x2<T, uint32_t>), dim3(bpv, (J + 7) / 8, nk), dim3(NT),
+              0, s, X, xk, xi, J, Y0, yk0, Y1, yk1, n, act, partial, bpv);
+  else
+    BW_LAUNCH("k_mdot2", active_units(act, nk, J, s), (k_mdot8x2<T, size_t>), dim3(bpv, (J + 7) / 8, nk), dim3(NT),
+              0, s, X, xk, xi, J, Y0, yk0, Y1, yk1, n, act, partial, bpv);
   hipLaunchKernelGGL(k_mdot2_finalize, dim3(nk * J), dim3(NT), 0, s, (const double*)partial, bpv, J, act, out0, out1,
                      ldo);
 }
@@ -708,7 +732,9 @@ void launch_mdot2(const cplx<T>* X, long xk, long xi, int J, const cplx<T>* Y0, 
 //   Y1_k <- f1 Y1_k - sum_i X_k[i] b_i - g Y0_k(new)    (the new direction, once orthogonalized)
 // Coefficients of wave vector k at c + k * ldc: a[0..J-1], b[0..J-1], then
 // (f0, 0), (f1, 0), g.  Y1 == nullptr: the first output only.  FP64 accumulation.
-template <typename T>
+// I: the index type of the element offsets (32-bit when J xi + n < 2^32: a
+// uniform base plus a 32-bit lane offset per load, no 64-bit address).
+template <typename T, typename I>
 __global__ __launch_bounds__(256) void k_mlincomb2(cplx<T>* __restrict__ Y0, long yk0, cplx<T>* __restrict__ Y1,
                                                    long yk1, const cplx<T>* __restrict__ X, long xk, long xi, int J,
                                                    const double2* __restrict__ c, int ldc, long n, const int* act) {
@@ -720,10 +746,10 @@ __global__ __launch_bounds__(256) void k_mlincomb2(cplx<T>* __restrict__ Y0, lon
   const double2* ck = c + (size_t)k * ldc;
   const double f0 = ck[2 * J].x, f1 = ck[2 * J + 1].x;
   const double2 gg = ck[2 * J + 2];
-  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+  const I xs = (I)xi;
+  for (I e = (I)blockIdx.x * 256 + threadIdx.x; e < (I)n; e += (I)gridDim.x * 256) {
     double ar = 0, ai = 0, br = 0, bi = 0;
-    for (int i = 0; i < J; ++i) {
-      const double2 v = to_d2(x[(size_t)i * xi + e]);
+    auto term = [&](const double2 v, int i) {
       const double2 ca = ck[i];
       ar += v.x * ca.x - v.y * ca.y;
       ai += v.x * ca.y + v.y * ca.x;
@@ -732,7 +758,26 @@ __global__ __launch_bounds__(256) void k_mlincomb2(cplx<T>* __restrict__ Y0, lon
         br += v.x * cb.x - v.y * cb.y;
         bi += v.x * cb.y + v.y * cb.x;
       }
+    };
+    // sixteen basis loads in flight at a time (held as loaded, widened at use);
+    // the terms are still added in the order i = 0, 1, ..., so the sums do not
+    // change
+    int i = 0;
+    for (; i + 16 <= J; i += 16) {
+      cplx<T> v[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) v[t] = x[(I)(i + t) * xs + e];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) term(to_d2(v[t]), i + t);
     }
+    for (; i + 4 <= J; i += 4) {
+      cplx<T> v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[t] = x[(I)(i + t) * xs + e];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) term(to_d2(v[t]), i + t);
+    }
+    for (; i < J; ++i) term(to_d2(x[(I)i * xs + e]), i);
     const double2 o0 = to_d2(y0[e]);
     const double vr = f0 * o0.x - ar, vi = f0 * o0.y - ai;
     y0[e] = from_d2<T>(make_double2(vr, vi));
@@ -749,8 +794,12 @@ void launch_mlincomb2(cplx<T>* Y0, long yk0, cplx<T>* Y1, long yk1, const cplx<T
   if (nk <= 0) return;
   long nb = (n + 255) / 256;
   if (nb > 1024) nb = 1024;
-  BW_LAUNCH("k_mlincomb2", active_units(act, nk, J, s), (k_mlincomb2<T>), dim3((unsigned)nb, 1, nk), dim3(256), 0, s,
-            Y0, yk0, Y1, yk1, X, xk, xi, J, c, ldc, n, act);
+  if ((double)J * xi + n < 4294967296.0)
+    BW_LAUNCH("k_mlincomb2", active_units(act, nk, J, s), (k_mlincomb2<T, uint32_t>), dim3((unsigned)nb, 1, nk),
+              dim3(256), 0, s, Y0, yk0, Y1, yk1, X, xk, xi, J, c, ldc, n, act);
+  else
+    BW_LAUNCH("k_mlincomb2", active_units(act, nk, J, s), (k_mlincomb2<T, size_t>), dim3((unsigned)nb, 1, nk),
+              dim3(256), 0, s, Y0, yk0, Y1, yk1, X, xk, xi, J, c, ldc, n, act);
 }
 
 template <typename T>
