@@ -320,6 +320,9 @@ __global__ __launch_bounds__(SLAB_NT, 1) void k_slab_div(const float2* __restric
       if (MODE == 1) {
         const float2 pv = at(pb, off);
         part += (double)pv.x * (double)ov.x + (double)pv.y * (double)ov.y;
+        // the direction's loads four at a time (registers: three 16-point sets
+        // are live here)
+        if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
     }
   };
