@@ -61,7 +61,8 @@ KERNEL_WORDS = {
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=6,
+                    help="timed steps (even: both path halves equally often)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--segments", type=int, default=SEGMENTS,
                     help="the 60-point path is solved in this many consecutive segments, one per step")
