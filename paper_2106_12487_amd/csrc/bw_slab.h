@@ -199,13 +199,23 @@ __global__ __launch_bounds__(SLAB_NT, 1) void k_slab_strain(const float2* __rest
 #pragma unroll
     for (int m = 0; m < 16; ++m) f[m] = at(b, lo + 8 * m);
   };
+  // MODE 1: the previous direction of component c, loaded into e while e is
+  // free (no fourth set of registers for it)
+  auto load_p = [&](int c) {
+    if (MODE == 1 && bt != 0.0f) {
+      const float2* b = Pv + (size_t)c * cs;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) e[m] = at(b, lo + 8 * m);
+    }
+  };
   // the values of component c at its first use: MODE 1 forms and stores the new
-  // direction from the fetched z
+  // direction from the fetched z and the previous direction in e[m] (read before
+  // the caller overwrites e[m])
   auto source = [&](int c, int m) -> float2 {
     float2 u = f[m];
     if (MODE == 1) {
+      if (bt != 0.0f) u = caxpy(u, bt, e[m]);
       float2* b = Pv + (size_t)c * cs;
-      if (bt != 0.0f) u = caxpy(u, bt, at(b, lo + 8 * m));
       b[lo + 8 * m] = u;
     }
     return u;
@@ -221,6 +231,7 @@ __global__ __launch_bounds__(SLAB_NT, 1) void k_slab_strain(const float2* __rest
   };
   __syncthreads();                            // tables
   fetch(0);
+  load_p(0);
 #pragma unroll
   for (int m = 0; m < 16; ++m) s[m] = source(0, m);
   fetch(2);                                   // u2, in flight during the first transform
@@ -229,11 +240,13 @@ __global__ __launch_bounds__(SLAB_NT, 1) void k_slab_strain(const float2* __rest
   for (int m = 0; m < 16; ++m) e[m] = cscale(s[m], qa);
   finish(0);
   // e4 = qc u0 + qa u2
+  load_p(2);
 #pragma unroll
   for (int m = 0; m < 16; ++m) e[m] = caxpy(cscale(s[m], qc[8 * m]), qa, source(2, m));
   fetch(1);
   finish(4);
   // e5 = qb u0 + qa u1; then hold u1
+  load_p(1);
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const float2 u1 = source(1, m);
