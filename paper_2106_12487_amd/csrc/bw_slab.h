@@ -195,6 +195,9 @@ __global__ __launch_bounds__(SLAB_NT, 1) void k_slab_strain(const float2* __rest
   const uint32_t lo = (uint32_t)(a * SLAB_N + j);   // row a, point j (+ 8 m)
   float2 s[16], e[16], f[16];
   auto fetch = [&](int c) {                   // raw loads of component c (MODE 1: z)
+    // MODE 0 reads only the input, whose loads could otherwise be hoisted above
+    // the work before them (while f is still live there)
+    if (MODE == 0) asm volatile("" ::: "memory");
     const float2* b = Uv + (size_t)c * cs;
 #pragma unroll
     for (int m = 0; m < 16; ++m) f[m] = at(b, lo + 8 * m);
