@@ -40,6 +40,27 @@ def test_pcg_at_gamma_stays_in_range():
     assert rel <= 1e-12 and np.allclose(x[:, 0, 0, 0], 0.0)
 
 
+def test_reference_vectors_are_exact_lowest_modes_of_a_one_grain_cell():
+    """Pin of the oracle's cold start (the lowest plane waves of the reference medium
+    C0, Sec. 3.3): in a one-grain cell C0 is the crystal's own stiffness, so those plane
+    waves are exact eigenvectors of the pencil (K, M).  Every returned vector satisfies
+    K u = lambda M u to rounding, the vectors are orthonormal, and their Rayleigh
+    quotients are the lowest eigenvalues of the dense pencil."""
+    ops = Operators(_poly(4, 1, 0), np.array([0.3, 0.2, 0.1]) * np.pi / L)
+    n = 7
+    lam_d, _ = solvers.dense_modes(ops, n)
+    U = solvers.reference_vectors(ops, n)
+    lam = []
+    for u in U:
+        Ku, Mu = ops.apply_K(u), ops.apply_M(u)
+        lu = np.vdot(u, Ku).real / np.vdot(u, Mu).real
+        assert np.linalg.norm(Ku - lu * Mu) <= 1e-10 * lu * np.linalg.norm(Mu)
+        lam.append(lu)
+    assert np.allclose(np.sort(lam), lam_d[:n], rtol=1e-10)
+    G = U.reshape(n, -1).conj() @ U.reshape(n, -1).T
+    assert np.allclose(G, np.eye(n), atol=1e-12)
+
+
 @pytest.mark.parametrize("k", [[0.35, 0.0, 0.0], [0.5, 0.5, 0.0], [0.0, 0.0, 0.0]])
 def test_subspace_matches_dense(k):
     ops = Operators(_poly(4, 6, 1), np.array(k) * np.pi / L)
